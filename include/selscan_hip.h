@@ -1,0 +1,187 @@
+/*
+ * selscan_hip.h -- C ABI of the MI355X (gfx950) library for EHH-based
+ * selection scans: EHH, iHS and XPEHH as defined by Szpiech & Hernandez,
+ * "selscan: an efficient multi-threaded program to perform EHH-based scans
+ * for positive selection" (arXiv:1403.6854).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Plain C: no HIP or framework types.  `stream` is a hipStream_t passed as
+ *    an opaque pointer (NULL = the default stream).  Calls enqueue work on
+ *    `stream` and return without synchronizing; outputs are valid once the
+ *    stream has been synchronized.
+ *  - Pointers prefixed `d_` and every pointer inside `ss_hapmat` are DEVICE
+ *    pointers on the current HIP device.  Descriptors (`ss_hapmat`,
+ *    `ss_params`) are HOST structs, read during the call only.
+ *  - The caller owns every buffer.  The library never allocates device
+ *    memory: scratch space is the caller's workspace, sized by
+ *    ss_workspace_bytes() and passed as (d_ws, ws_bytes), 256-byte aligned.
+ *    One workspace must not be used by two calls that overlap in time.
+ *  - Allele encoding (Sec. 1.1): bit 1 = derived allele, bit 0 = ancestral.
+ *    Haplotype matrices are bit-packed MARKER-major: site s occupies
+ *    words_per_site uint64 words at bits + s*words_per_site; haplotype h is
+ *    bit (h % 64) of word (h / 64).  Padding bits above n_haps must be 0.
+ *  - "Downstream" is increasing site index, "upstream" decreasing.
+ *  - Return codes: SS_OK, or a negative SS_E* code with a message available
+ *    from ss_last_error() (per calling thread).  Argument errors are detected
+ *    before anything is enqueued.  Content checks that need the data (sorted
+ *    positions, zero padding, identical sites in both XPEHH populations) are
+ *    the caller's responsibility (the Python binding does them on the host).
+ */
+#ifndef SELSCAN_HIP_H
+#define SELSCAN_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define SS_OK 0
+#define SS_EARG (-1)    /* invalid argument (null pointer, size or parameter) */
+#define SS_ESHAPE (-2)  /* XPEHH populations with different site counts       */
+#define SS_EWS (-3)     /* workspace missing or smaller than required          */
+#define SS_EDEV (-4)    /* HIP runtime error or device limit exceeded          */
+
+/* Per-site status codes (int8 outputs). Any status other than SS_ST_OK leaves
+ * NaN in the scores it affects. */
+#define SS_ST_OK 0
+#define SS_ST_MAF 1        /* iHS: core site with MAF below the cutoff (Sec. 1.2)       */
+#define SS_ST_EDGE 2       /* end of the data reached before the cutoff (Sec. 1.2)      */
+#define SS_ST_GAP 3        /* a gap longer than max_gap_bp was crossed (Sec. 1.2)       */
+#define SS_ST_UNDEFINED 4  /* a core has < 2 haplotypes, or an iHH is 0                 */
+#define SS_ST_BIN 5        /* scores valid but the standardization bin has < 2 loci or
+                              zero spread: the standardized score is NaN               */
+#define SS_ST_CAPACITY 6   /* ss_ehh: a walk needed more than `cap` markers             */
+
+/* Operation selector for ss_workspace_bytes(). */
+#define SS_OP_EHH 0
+#define SS_OP_IHS 1
+#define SS_OP_XPEHH 2
+
+/* The flexible parameters of Sec. 1.2 (and Sec. 1.3 for XPEHH).  Defaults in
+ * brackets are the paper's values; bin_width is the iHS frequency-bin width. */
+typedef struct ss_params {
+    double ehh_cutoff;     /* EHH truncation value, in (0, 1]               [0.05]   */
+    double maf_cutoff;     /* iHS core-site MAF cutoff, in [0, 0.5]         [0.05]   */
+    int64_t gap_scale_bp;  /* gaps b > this scale g by gap_scale_bp / b, > 0 [20000] */
+    int64_t max_gap_bp;    /* gaps b > this abort the locus, >= gap_scale  [200000] */
+    double bin_width;      /* derived-allele-frequency bin width, (0, 1]   [0.025]  */
+} ss_params;
+
+/* A bit-packed haplotype matrix with its physical and genetic map
+ * (non-owning descriptor; all pointers are device pointers). */
+typedef struct ss_hapmat {
+    const uint64_t *bits;     /* [n_sites][words_per_site], see above                  */
+    int64_t n_haps;           /* haplotypes, 2 .. 32767                                  */
+    int64_t n_sites;          /* sites, >= 1                                             */
+    int64_t words_per_site;   /* row stride in words, >= ceil(n_haps / 64)               */
+    const int64_t *pos_bp;    /* [n_sites] physical positions, non-decreasing           */
+    const double *gpos_cm;    /* [n_sites] genetic positions (cM), non-decreasing       */
+} ss_hapmat;
+
+/* Fills *p with the paper's default parameters. */
+void ss_default_params(ss_params *p);
+
+/* Version string of the library build. */
+const char *ss_version(void);
+
+/* Message of the last failing call made by this thread ("" if none). */
+const char *ss_last_error(void);
+
+/*
+ * ss_pack -- bit-pack 0/1 alleles into the marker-major layout (Sec. 1.1's
+ * 0 = ancestral, 1 = derived).
+ *   d_alleles  [n_sites][n_haps] uint8, 0 or 1 (any nonzero byte counts as 1)
+ *   d_bits     [n_sites][words_per_site] uint64 output; padding bits written 0
+ * Errors: SS_EARG for null pointers, n_haps < 1, n_sites < 1 or
+ * words_per_site < ceil(n_haps/64).
+ */
+int ss_pack(const uint8_t *d_alleles, int64_t n_haps, int64_t n_sites,
+            int64_t words_per_site, uint64_t *d_bits, void *stream);
+
+/*
+ * ss_workspace_bytes -- device workspace needed by one call of `op` on these
+ * shapes (b is used for SS_OP_XPEHH only; ehh_cap for SS_OP_EHH only).
+ * Returns 0 for invalid arguments.
+ */
+size_t ss_workspace_bytes(int op, const ss_hapmat *a, const ss_hapmat *b,
+                          const ss_params *p, int64_t ehh_cap);
+
+/*
+ * ss_ehh -- EHH at one core site (Sec. 1.1, Eq. 1 and Eq. 3), both
+ * directions, with the truncation and gap rules of Sec. 1.2 (the MAF cutoff
+ * does not apply).  Walks continue while either core's EHH_c is at or above
+ * the cutoff; every class of both cores is tracked to the end of the walk.
+ *   core            site index of x0, 0 <= core < n_sites
+ *   cap             most markers recorded per direction (>= 1)
+ *   d_S             [2 dirs][cap+1][2] uint64: S_c(x_i) = sum over the classes
+ *                   of core c of C(n_h, 2), i = 0..len (i = 0 is x0)
+ *   d_ehh           [2][cap+1][3] double: EHH_0, EHH_1 (Eq. 3) and the whole-
+ *                   sample EHH (Eq. 1) at x_i; NaN past len or where C(n_c,2)=0
+ *   d_len           [2] int64: markers walked downstream (0) and upstream (1)
+ *   d_class_sizes   NULL, or [2][cap+1][n_haps] uint32: the sizes of the
+ *                   classes with >= 2 members at x_i, in no particular order,
+ *                   core allele in bit 31, zero-filled
+ *   d_ihh           [2] double: iHH_0, iHH_1 (Eq. 4), NaN unless status OK
+ *   d_status        [1] int8: OK, EDGE, GAP, UNDEFINED or CAPACITY
+ * Errors: SS_EARG, SS_EWS, SS_EDEV.
+ */
+int ss_ehh(const ss_hapmat *h, int64_t core, const ss_params *p, int64_t cap,
+           uint64_t *d_S, double *d_ehh, int64_t *d_len, uint32_t *d_class_sizes,
+           double *d_ihh, int8_t *d_status, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * ss_ihs -- iHS scan over every site of h (Sec. 1.2, Eqs. 3-6).
+ * For each core site with MAF >= maf_cutoff: iHH_1 and iHH_0 by trapezoidal
+ * quadrature of EHH_c over the genetic map, truncated before the first marker
+ * with EHH_c < ehh_cutoff, with gap scaling and the edge / gap aborts; the
+ * unstandardized score ln(iHH_1/iHH_0); and the score standardized within
+ * derived-allele-frequency bins (bin = min(floor(B n1/n), B-1),
+ * B = round(1/bin_width); mean and N-1 standard deviation of the OK loci).
+ *   d_ihh1, d_ihh0, d_unstd, d_std   [n_sites] double outputs
+ *   d_freq                           [n_sites] double: derived frequency n1/n
+ *   d_status                         [n_sites] int8 (SS_ST_*)
+ *   d_steps     NULL or [n_sites][2 dirs][2 cores] int32: markers each core
+ *               walked (incl. the one where it stopped); 0 for unscored sites
+ * Errors: SS_EARG, SS_EWS, SS_EDEV.
+ */
+int ss_ihs(const ss_hapmat *h, const ss_params *p, double *d_ihh1, double *d_ihh0,
+           double *d_unstd, double *d_std, double *d_freq, int8_t *d_status,
+           int32_t *d_steps, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * ss_xpehh -- XPEHH scan of population a against b over every site
+ * (Sec. 1.3, Eqs. 7-9).  Both populations share the sites (same n_sites and
+ * the same pos_bp / gpos_cm contents).  Per site: iHH_A and iHH_B integrate
+ * each population's whole-sample EHH (Eq. 1, the core site being part of the
+ * haplotype, so each curve starts at [C(n0,2)+C(n1,2)]/C(n,2)), both truncated
+ * before the first marker where the EHH of the pooled sample drops below the
+ * cutoff; the unstandardized score ln(iHH_A/iHH_B); and the score standardized
+ * over all OK sites.  There is no MAF filter.
+ *   d_ihhA, d_ihhB, d_unstd, d_std   [n_sites] double outputs
+ *   d_status                         [n_sites] int8
+ *   d_steps     NULL or [n_sites][2 dirs] int32: pooled markers walked
+ * Errors: SS_EARG, SS_ESHAPE, SS_EWS, SS_EDEV.
+ */
+int ss_xpehh(const ss_hapmat *a, const ss_hapmat *b, const ss_params *p,
+             double *d_ihhA, double *d_ihhB, double *d_unstd, double *d_std,
+             int8_t *d_status, int32_t *d_steps, void *d_ws, size_t ws_bytes,
+             void *stream);
+
+/*
+ * Kernel timing for measurement: while enabled, ss_ihs / ss_xpehh record HIP
+ * events on their stream around the EHH walk kernel; ss_timing_read() waits
+ * for the recorded events and returns the summed walk-kernel time (ms) and
+ * the number of launches since the last reset.
+ */
+int ss_timing_enable(int on);
+int ss_timing_read(double *walk_ms_total, int64_t *walk_launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SELSCAN_HIP_H */

@@ -500,9 +500,10 @@ int or_ehh(const uint8_t *H, int64_t n, int64_t M, const int64_t *pos, const dou
     if (s == OR_OK && (nc[0] < 2 || nc[1] < 2)) s = OR_UNDEF;
     ihh[0] = ihh[1] = NAN;
     if (s == OR_OK) {
-        ihh[0] = hh[0][0] + hh[1][0];
-        ihh[1] = hh[0][1] + hh[1][1];
-        if (!(ihh[0] > 0.0) || !(ihh[1] > 0.0)) s = OR_UNDEF;
+        double i0 = hh[0][0] + hh[1][0];
+        double i1 = hh[0][1] + hh[1][1];
+        if (!(i0 > 0.0) || !(i1 > 0.0)) s = OR_UNDEF;
+        else { ihh[0] = i0; ihh[1] = i1; }
     }
     *status = (int8_t)s;
     return 0;
@@ -533,9 +534,10 @@ int or_xpehh_trace(const uint8_t *HA, int64_t nA, const uint8_t *HB, int64_t nB,
     int s = st[0] != OR_OK ? st[0] : st[1];
     ihh[0] = ihh[1] = NAN;
     if (s == OR_OK) {
-        ihh[0] = hh[0][0] + hh[1][0];
-        ihh[1] = hh[0][1] + hh[1][1];
-        if (!(ihh[0] > 0.0) || !(ihh[1] > 0.0)) s = OR_UNDEF;
+        double i0 = hh[0][0] + hh[1][0];
+        double i1 = hh[0][1] + hh[1][1];
+        if (!(i0 > 0.0) || !(i1 > 0.0)) s = OR_UNDEF;
+        else { ihh[0] = i0; ihh[1] = i1; }
     }
     *status = (int8_t)s;
     return 0;

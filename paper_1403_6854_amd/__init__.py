@@ -1,0 +1,312 @@
+"""MI355X-native EHH / iHS / XPEHH scans (Szpiech & Hernandez, arXiv:1403.6854).
+
+Thin Python binding over the C ABI of ``libselscan_hip.so``
+(``include/selscan_hip.h``): argument marshalling only.  Every step of the
+scans runs in the library's HIP kernels; PyTorch provides device memory and
+streams.  There is no CPU fallback: if the library is not built, importing the
+entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libselscan_hip.so")
+
+SS_OK, SS_EARG, SS_ESHAPE, SS_EWS, SS_EDEV = 0, -1, -2, -3, -4
+OP_EHH, OP_IHS, OP_XPEHH = 0, 1, 2
+STATUS_NAMES = {0: "OK", 1: "MAF", 2: "EDGE", 3: "GAP", 4: "UNDEFINED", 5: "BIN", 6: "CAPACITY"}
+
+
+class SelscanError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("selscan_hip error %d: %s" % (code, msg))
+        self.code = code
+
+
+@dataclasses.dataclass
+class Params:
+    """Flexible parameters of Sec. 1.2 / 1.3, with the paper's defaults."""
+    ehh_cutoff: float = 0.05
+    maf_cutoff: float = 0.05
+    gap_scale_bp: int = 20_000
+    max_gap_bp: int = 200_000
+    bin_width: float = 0.025
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("ehh_cutoff", ctypes.c_double), ("maf_cutoff", ctypes.c_double),
+                ("gap_scale_bp", ctypes.c_int64), ("max_gap_bp", ctypes.c_int64),
+                ("bin_width", ctypes.c_double)]
+
+
+class _HapMat(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_void_p), ("n_haps", ctypes.c_int64),
+                ("n_sites", ctypes.c_int64), ("words_per_site", ctypes.c_int64),
+                ("pos_bp", ctypes.c_void_p), ("gpos_cm", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libselscan_hip.so is not built; run paper_1403_6854_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+        HM = ctypes.POINTER(_HapMat)
+        PR = ctypes.POINTER(_Params)
+        L.ss_version.restype = ctypes.c_char_p
+        L.ss_last_error.restype = ctypes.c_char_p
+        L.ss_default_params.argtypes = [PR]
+        L.ss_pack.argtypes = [P, i64, i64, i64, P, P]
+        L.ss_workspace_bytes.argtypes = [ctypes.c_int, HM, HM, PR, i64]
+        L.ss_workspace_bytes.restype = sz
+        L.ss_ehh.argtypes = [HM, i64, PR, i64, P, P, P, P, P, P, P, sz, P]
+        L.ss_ihs.argtypes = [HM, PR, P, P, P, P, P, P, P, P, sz, P]
+        L.ss_xpehh.argtypes = [HM, HM, PR, P, P, P, P, P, P, P, sz, P]
+        L.ss_timing_enable.argtypes = [ctypes.c_int]
+        L.ss_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.c_int]
+        for f in ("ss_pack", "ss_ehh", "ss_ihs", "ss_xpehh", "ss_timing_enable", "ss_timing_read"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != SS_OK:
+        raise SelscanError(rc, lib().ss_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _cparams(p: Optional[Params]) -> _Params:
+    p = p or Params()
+    return _Params(float(p.ehh_cutoff), float(p.maf_cutoff), int(p.gap_scale_bp),
+                   int(p.max_gap_bp), float(p.bin_width))
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("tensors must live on the GPU")
+
+
+@dataclasses.dataclass
+class HapMat:
+    """A bit-packed marker-major haplotype matrix resident on the device.
+
+    bits: int64 [n_sites, words_per_site] (uint64 words; haplotype h is bit
+    h % 64 of word h // 64; 1 = derived allele); pos_bp: int64 [n_sites];
+    gpos_cm: float64 [n_sites].
+    """
+    bits: torch.Tensor
+    n_haps: int
+    pos_bp: torch.Tensor
+    gpos_cm: torch.Tensor
+
+    @property
+    def n_sites(self) -> int:
+        return int(self.bits.shape[0])
+
+    @property
+    def words_per_site(self) -> int:
+        return int(self.bits.stride(0))
+
+    def desc(self) -> _HapMat:
+        if self.bits.dtype != torch.int64 or self.bits.dim() != 2 or self.bits.stride(1) != 1:
+            raise ValueError("bits must be a row-contiguous int64 [n_sites, words] tensor")
+        if self.pos_bp.dtype != torch.int64 or self.gpos_cm.dtype != torch.float64:
+            raise ValueError("pos_bp must be int64 and gpos_cm float64")
+        if not (self.pos_bp.is_contiguous() and self.gpos_cm.is_contiguous()):
+            raise ValueError("position arrays must be contiguous")
+        if self.pos_bp.numel() != self.n_sites or self.gpos_cm.numel() != self.n_sites:
+            raise ValueError("position arrays must have n_sites entries")
+        _need_cuda(self.bits, self.pos_bp, self.gpos_cm)
+        return _HapMat(self.bits.data_ptr(), int(self.n_haps), self.n_sites, self.words_per_site,
+                       self.pos_bp.data_ptr(), self.gpos_cm.data_ptr())
+
+    def validate(self):
+        """Content checks the C ABI leaves to the caller: sorted positions and
+        zero padding bits (one device round trip)."""
+        bad = torch.zeros((), dtype=torch.bool, device=self.bits.device)
+        if self.n_sites > 1:
+            bad |= (self.pos_bp[1:] < self.pos_bp[:-1]).any()
+            bad |= (self.gpos_cm[1:] < self.gpos_cm[:-1]).any()
+        words = (self.n_haps + 63) // 64
+        rem = self.n_haps - 64 * (words - 1)
+        if rem < 64:
+            mask = ~((1 << rem) - 1)
+            mask = mask if mask >= -(1 << 63) else mask + (1 << 64)
+            bad |= (self.bits[:, words - 1] & mask).ne(0).any()
+        if self.words_per_site > words:
+            bad |= self.bits[:, words:].ne(0).any()
+        if bool(bad):
+            raise ValueError("positions must be non-decreasing and padding bits zero")
+
+
+def words_for(n_haps: int) -> int:
+    return (int(n_haps) + 63) // 64
+
+
+def pack(alleles: torch.Tensor, stream=None) -> torch.Tensor:
+    """Bit-pack a uint8 [n_sites, n_haps] 0/1 matrix on the device."""
+    _need_cuda(alleles)
+    if alleles.dtype != torch.uint8 or alleles.dim() != 2:
+        raise ValueError("alleles must be uint8 [n_sites, n_haps]")
+    alleles = alleles.contiguous()
+    M, n = alleles.shape
+    W = words_for(n)
+    bits = torch.empty((M, W), dtype=torch.int64, device=alleles.device)
+    _check(lib().ss_pack(_ptr(alleles), n, M, W, _ptr(bits), _stream(stream)))
+    return bits
+
+
+def hapmat(alleles: torch.Tensor, pos_bp: torch.Tensor, gpos_cm: torch.Tensor,
+           stream=None) -> HapMat:
+    """Pack device-resident alleles into a HapMat."""
+    return HapMat(pack(alleles, stream), int(alleles.shape[1]), pos_bp.contiguous(),
+                  gpos_cm.contiguous())
+
+
+def workspace_bytes(op: int, a: HapMat, b: Optional[HapMat] = None,
+                    params: Optional[Params] = None, ehh_cap: int = 0) -> int:
+    da = a.desc()
+    db = b.desc() if b is not None else None
+    cp = _cparams(params)
+    n = lib().ss_workspace_bytes(op, ctypes.byref(da), ctypes.byref(db) if db else None,
+                                 ctypes.byref(cp), int(ehh_cap))
+    if n == 0:
+        raise SelscanError(SS_EARG, "invalid arguments for ss_workspace_bytes")
+    return int(n)
+
+
+def _workspace(nbytes: int, device, ws: Optional[torch.Tensor]):
+    if ws is not None and ws.numel() * ws.element_size() >= nbytes:
+        return ws
+    return torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+
+
+def _aligned(ws: torch.Tensor) -> int:
+    p = ws.data_ptr()
+    return (p + 255) & ~255
+
+
+def ihs(h: HapMat, params: Optional[Params] = None, steps: bool = False, stream=None,
+        ws: Optional[torch.Tensor] = None, out: Optional[dict] = None, validate: bool = True):
+    """iHS scan over every site (Sec. 1.2).  Returns a dict of device tensors:
+    ihh1, ihh0, unstd, std, freq (float64), status (int8) and optionally
+    steps (int32 [n_sites, 2, 2])."""
+    if validate:
+        h.validate()
+    d = h.desc()
+    M = h.n_sites
+    dev = h.bits.device
+    nb = workspace_bytes(OP_IHS, h, None, params)
+    ws = _workspace(nb, dev, ws)
+    if out is None:
+        out = {k: torch.empty(M, dtype=torch.float64, device=dev)
+               for k in ("ihh1", "ihh0", "unstd", "std", "freq")}
+        out["status"] = torch.empty(M, dtype=torch.int8, device=dev)
+        if steps:
+            out["steps"] = torch.empty((M, 2, 2), dtype=torch.int32, device=dev)
+    cp = _cparams(params)
+    base = _aligned(ws)
+    avail = ws.numel() - (base - ws.data_ptr())
+    _check(lib().ss_ihs(ctypes.byref(d), ctypes.byref(cp), _ptr(out["ihh1"]), _ptr(out["ihh0"]),
+                        _ptr(out["unstd"]), _ptr(out["std"]), _ptr(out["freq"]),
+                        _ptr(out["status"]), _ptr(out.get("steps")), ctypes.c_void_p(base),
+                        avail, _stream(stream)))
+    return out
+
+
+def xpehh(a: HapMat, b: HapMat, params: Optional[Params] = None, steps: bool = False,
+          stream=None, ws: Optional[torch.Tensor] = None, out: Optional[dict] = None,
+          validate: bool = True):
+    """XPEHH scan of population a against b (Sec. 1.3).  Returns ihhA, ihhB,
+    unstd, std (float64), status (int8) and optionally steps (int32 [M, 2])."""
+    if validate:
+        a.validate()
+        b.validate()
+        if a.n_sites != b.n_sites or not torch.equal(a.pos_bp, b.pos_bp) \
+                or not torch.equal(a.gpos_cm, b.gpos_cm):
+            raise ValueError("XPEHH populations must share their sites")
+    da, db = a.desc(), b.desc()
+    M = a.n_sites
+    dev = a.bits.device
+    nb = workspace_bytes(OP_XPEHH, a, b, params)
+    ws = _workspace(nb, dev, ws)
+    if out is None:
+        out = {k: torch.empty(M, dtype=torch.float64, device=dev)
+               for k in ("ihhA", "ihhB", "unstd", "std")}
+        out["status"] = torch.empty(M, dtype=torch.int8, device=dev)
+        if steps:
+            out["steps"] = torch.empty((M, 2), dtype=torch.int32, device=dev)
+    cp = _cparams(params)
+    base = _aligned(ws)
+    avail = ws.numel() - (base - ws.data_ptr())
+    _check(lib().ss_xpehh(ctypes.byref(da), ctypes.byref(db), ctypes.byref(cp),
+                          _ptr(out["ihhA"]), _ptr(out["ihhB"]), _ptr(out["unstd"]),
+                          _ptr(out["std"]), _ptr(out["status"]), _ptr(out.get("steps")),
+                          ctypes.c_void_p(base), avail, _stream(stream)))
+    return out
+
+
+def ehh(h: HapMat, core: int, params: Optional[Params] = None, cap: int = 4096,
+        sizes: bool = False, stream=None):
+    """EHH curves at one core site (Sec. 1.1), both directions.  Returns S
+    (uint64 as int64 [2, cap+1, 2]), ehh (float64 [2, cap+1, 3]), len
+    (int64 [2]), optionally sizes (int32 view of uint32 [2, cap+1, n]),
+    ihh (float64 [2] = iHH_0, iHH_1) and status (int8 [1])."""
+    d = h.desc()
+    dev = h.bits.device
+    nb = workspace_bytes(OP_EHH, h, None, params, cap)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+    out = {
+        "S": torch.empty((2, cap + 1, 2), dtype=torch.int64, device=dev),
+        "ehh": torch.empty((2, cap + 1, 3), dtype=torch.float64, device=dev),
+        "len": torch.empty(2, dtype=torch.int64, device=dev),
+        "ihh": torch.empty(2, dtype=torch.float64, device=dev),
+        "status": torch.empty(1, dtype=torch.int8, device=dev),
+    }
+    if sizes:
+        out["sizes"] = torch.empty((2, cap + 1, h.n_haps), dtype=torch.int32, device=dev)
+    cp = _cparams(params)
+    base = _aligned(ws)
+    _check(lib().ss_ehh(ctypes.byref(d), int(core), ctypes.byref(cp), int(cap), _ptr(out["S"]),
+                        _ptr(out["ehh"]), _ptr(out["len"]), _ptr(out.get("sizes")),
+                        _ptr(out["ihh"]), _ptr(out["status"]), ctypes.c_void_p(base),
+                        ws.numel() - (base - ws.data_ptr()), _stream(stream)))
+    return out
+
+
+def timing_enable(on: bool = True):
+    _check(lib().ss_timing_enable(1 if on else 0))
+
+
+def timing_read(reset: bool = False):
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().ss_timing_read(ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+    return float(ms.value), int(n.value)
+
+
+def version() -> str:
+    return lib().ss_version().decode()

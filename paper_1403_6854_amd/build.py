@@ -1,0 +1,53 @@
+"""Build the HIP library ``libselscan_hip.so`` for gfx950 with hipcc.
+
+Flags that matter for the results:
+  * ``-ffp-contract=off``: HIP clang contracts a*b+c into FMA by default, which
+    would round the trapezoid sums differently from their definition;
+  * no fast-math: IEEE division and square root are required so that the
+    cutoff decisions (EHH < cutoff) come out exactly as defined;
+  * ``-Xclang -target-feature -Xclang -packed-fp32-ops``: no packed FP32
+    instructions are generated.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(HERE, "libselscan_hip.so")
+SOURCES = ["ss_walk.hip", "ss_sites.hip", "ss_capi.hip"]
+ARCH = os.environ.get("SS_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc() -> str:
+    for cand in (shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def flags():
+    return ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-ffp-contract=off",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-I", INCLUDE, "-I", CSRC]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source into the shared library (always recompiles)."""
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + flags() + ["-shared"] + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + res.stderr[-8000:])
+    if verbose:
+        print(" ".join(cmd))
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

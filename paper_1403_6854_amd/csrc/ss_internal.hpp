@@ -1,0 +1,78 @@
+// Internal declarations shared by the library's translation units.
+// Not part of the public ABI (that is include/selscan_hip.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace ss {
+
+// Per-site status codes (mirror SS_ST_* of the public header).
+enum : int32_t {
+    ST_OK = 0, ST_MAF = 1, ST_EDGE = 2, ST_GAP = 3, ST_UNDEF = 4, ST_BIN = 5, ST_CAP = 6
+};
+
+enum WalkMode : int { MODE_CORE = 0, MODE_POOLED = 1 };
+
+// Everything one launch of the EHH walk needs.  The pooled haplotype index
+// space places population A in words [0, WA) and population B in words
+// [WA, WA + WB), so that every 64-haplotype word belongs to one population.
+struct WalkArgs {
+    const uint64_t *bitsA;
+    int64_t wpsA;
+    int32_t nA, WA;
+    const uint64_t *bitsB;
+    int64_t wpsB;
+    int32_t nB, WB;
+    int64_t M;
+    const int64_t *pos;
+    const double *gpos;
+    double cutoff;
+    int64_t gap_scale;
+    int64_t max_gap;
+    const uint8_t *walk_flag;   // [M], nonzero = score this site; null = all sites
+    const int32_t *sites;       // null: block x walks site site0 + blockIdx.x
+    int64_t site0;
+    int32_t kmax;               // class-table capacity in LDS
+    double *ihh;                // [M][2 dirs][2]
+    int32_t *dstatus;           // [M][2 dirs]
+    int32_t *steps;             // [M][2 dirs][2]
+    // ss_ehh trace outputs (one site only)
+    uint64_t *trS;              // [2][cap+1][2]
+    uint32_t *trSizes;          // [2][cap+1][n] or null
+    int64_t *trLen;             // [2]
+    int64_t cap;
+};
+
+struct WalkShape {
+    int threads;      // workgroup size, multiple of 64
+    int slots;        // 64-haplotype words handled per wave and step
+    size_t lds;       // dynamic LDS bytes
+};
+
+WalkShape walk_shape(int32_t nA, int32_t nB, int mode);
+hipError_t launch_walk(const WalkArgs &a, int mode, bool trace, int64_t n_blocks,
+                       hipStream_t s);
+
+// Site-level kernels.
+hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps,
+                       uint64_t *bits, hipStream_t s);
+hipError_t launch_site_stats(const uint64_t *bits, int64_t wps, int64_t n, int64_t M,
+                             double maf_cutoff, int32_t nbins, double *freq,
+                             int32_t *bin, uint8_t *walk_flag, int8_t *status,
+                             hipStream_t s);
+hipError_t launch_combine(int mode, int64_t M, const uint8_t *walk_flag,
+                          const double *dihh, const int32_t *dstatus,
+                          const int32_t *dsteps, double *out_a, double *out_b,
+                          double *unstd, int8_t *status, int32_t *steps_out,
+                          hipStream_t s);
+hipError_t launch_standardize(int64_t M, const double *unstd, int8_t *status,
+                              const int32_t *bin, int32_t nbins, double *binstat,
+                              double *z, hipStream_t s);
+hipError_t launch_ehh_finish(int64_t n, int64_t cap, const uint64_t *S, const int64_t *len,
+                             const double *dihh, const int32_t *dstatus, double *ehh,
+                             double *ihh, int8_t *status, hipStream_t s);
+
+}  // namespace ss

@@ -1,0 +1,286 @@
+// Site-level kernels around the EHH walk: packing, per-site counts and
+// filters, the per-site combination of the two walk directions, the
+// frequency-bin standardization, and the EHH curves of ss_ehh.
+//
+// All of these are streaming passes over per-site arrays; they are bound by
+// memory traffic and launch latency, not arithmetic, and are laid out for
+// coalesced access (one wave per bit-packed row, one lane per site).
+#include <math.h>
+
+#include "ss_internal.hpp"
+
+namespace ss {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Bit-pack 0/1 bytes: one wave per (site, 64-haplotype word); lane l reads
+// haplotype 64w + l (64 consecutive bytes) and a ballot forms the word
+// (Sec. 1.1 encoding: bit set = derived allele).
+__global__ void __launch_bounds__(kBlock) pack_kernel(const uint8_t *__restrict__ alleles,
+                                                      int64_t n, int64_t M, int64_t wps,
+                                                      uint64_t *__restrict__ bits) {
+    const int lane = threadIdx.x & 63;
+    const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (item >= M * wps) return;
+    const int64_t site = item / wps;
+    const int64_t w = item - site * wps;
+    const int64_t h = w * 64 + lane;
+    const bool one = h < n && alleles[site * n + h] != 0;
+    const uint64_t word = __ballot(one);
+    if (lane == 0) bits[item] = word;
+}
+
+// Per-site derived count n1, derived frequency, frequency bin, MAF filter
+// (Sec. 1.2: sites with MAF < cutoff are not scored) and the cores' sizes
+// (a core with fewer than two haplotypes leaves the score undefined).
+// One wave per site.
+__global__ void __launch_bounds__(kBlock) site_stats_kernel(
+    const uint64_t *__restrict__ bits, int64_t wps, int64_t n, int64_t M, double maf_cutoff,
+    int32_t nbins, double *__restrict__ freq, int32_t *__restrict__ bin,
+    uint8_t *__restrict__ walk_flag, int8_t *__restrict__ status) {
+    const int lane = threadIdx.x & 63;
+    const int64_t site = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (site >= M) return;
+    const int64_t words = (n + 63) / 64;
+    uint32_t c = 0;
+    for (int64_t w = lane; w < words; w += 64) {
+        uint64_t x = bits[site * wps + w];
+        const int64_t valid = n - w * 64;
+        if (valid < 64) x &= (1ull << valid) - 1ull;
+        c += (uint32_t)__popcll(x);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane != 0) return;
+    const int64_t n1 = c, n0 = n - n1;
+    freq[site] = (double)n1 / (double)n;
+    int64_t b = ((int64_t)nbins * n1) / n;
+    if (b > nbins - 1) b = nbins - 1;
+    bin[site] = (int32_t)b;
+    const double maf = (double)(n0 < n1 ? n0 : n1) / (double)n;
+    int8_t st = ST_OK;
+    if (maf < maf_cutoff) st = ST_MAF;
+    else if (n0 < 2 || n1 < 2) st = ST_UNDEF;
+    status[site] = st;
+    walk_flag[site] = st == ST_OK ? 1 : 0;
+}
+
+// iHH = downstream sum + upstream sum (Eq. 4 / Eq. 7); the locus status is the
+// downstream abort if any, else the upstream one; then the log-ratio
+// (Eq. 5 / Eq. 8).
+__global__ void __launch_bounds__(kBlock) combine_kernel(
+    int64_t M, const uint8_t *__restrict__ walk_flag, const double *__restrict__ dihh,
+    const int32_t *__restrict__ dstatus, const int32_t *__restrict__ dsteps,
+    double *__restrict__ out_a, double *__restrict__ out_b, double *__restrict__ unstd,
+    int8_t *__restrict__ status, int32_t *__restrict__ steps_out, int pooled) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= M) return;
+    const double nan = __builtin_nan("");
+    const bool walked = walk_flag == nullptr || walk_flag[j] != 0;
+    if (!walked) {
+        out_a[j] = nan;
+        out_b[j] = nan;
+        unstd[j] = nan;
+        if (steps_out) {
+            if (pooled) { steps_out[2 * j] = 0; steps_out[2 * j + 1] = 0; }
+            else for (int q = 0; q < 4; ++q) steps_out[4 * j + q] = 0;
+        }
+        return;   // status already set by the site pass
+    }
+    const int32_t sd = dstatus[2 * j], su = dstatus[2 * j + 1];
+    int32_t st = sd != ST_OK ? sd : su;
+    // slot 0 of a direction holds core 0 (iHS) or population A (XPEHH),
+    // slot 1 holds core 1 or population B
+    const double x0 = dihh[4 * j + 0] + dihh[4 * j + 2];
+    const double x1 = dihh[4 * j + 1] + dihh[4 * j + 3];
+    double a = nan, b = nan, u = nan;
+    if (st == ST_OK) {
+        if (!(x0 > 0.0) || !(x1 > 0.0)) {
+            st = ST_UNDEF;
+        } else if (pooled) {
+            a = x0;
+            b = x1;
+            u = log(a / b);
+        } else {
+            a = x1;   // iHH_1 (derived)
+            b = x0;   // iHH_0 (ancestral)
+            u = log(a / b);
+        }
+    }
+    out_a[j] = a;
+    out_b[j] = b;
+    unstd[j] = u;
+    status[j] = (int8_t)st;
+    if (steps_out) {
+        if (pooled) {
+            steps_out[2 * j] = dsteps[4 * j + 0];
+            steps_out[2 * j + 1] = dsteps[4 * j + 2];
+        } else {
+            for (int q = 0; q < 4; ++q) steps_out[4 * j + q] = dsteps[4 * j + q];
+        }
+    }
+}
+
+__device__ double block_sum(double v, double *red) {
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] = red[t] + red[t + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Mean and N-1 standard deviation of the OK scores in each bin (Eq. 6; Eq. 9
+// with one bin), two passes, fixed summation order.  One workgroup per bin.
+__global__ void __launch_bounds__(kBlock) bin_stats_kernel(int64_t M,
+                                                           const double *__restrict__ u,
+                                                           const int8_t *__restrict__ status,
+                                                           const int32_t *__restrict__ bin,
+                                                           double *__restrict__ binstat) {
+    __shared__ double red[kBlock];
+    const int b = blockIdx.x;
+    double s = 0.0, c = 0.0;
+    for (int64_t j = threadIdx.x; j < M; j += kBlock) {
+        if (status[j] == ST_OK && (bin == nullptr || bin[j] == b)) {
+            s += u[j];
+            c += 1.0;
+        }
+    }
+    const double N = block_sum(c, red);
+    const double sum = block_sum(s, red);
+    const double mean = N > 0.0 ? sum / N : __builtin_nan("");
+    double q = 0.0;
+    for (int64_t j = threadIdx.x; j < M; j += kBlock) {
+        if (status[j] == ST_OK && (bin == nullptr || bin[j] == b)) {
+            const double dlt = u[j] - mean;
+            q += dlt * dlt;
+        }
+    }
+    const double ss = block_sum(q, red);
+    if (threadIdx.x == 0) {
+        binstat[3 * b + 0] = N;
+        binstat[3 * b + 1] = mean;
+        binstat[3 * b + 2] = N > 1.0 ? sqrt(ss / (N - 1.0)) : __builtin_nan("");
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) standardize_kernel(int64_t M,
+                                                             const double *__restrict__ u,
+                                                             int8_t *__restrict__ status,
+                                                             const int32_t *__restrict__ bin,
+                                                             const double *__restrict__ binstat,
+                                                             double *__restrict__ z) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= M) return;
+    double out = __builtin_nan("");
+    if (status[j] == ST_OK) {
+        const int b = bin ? bin[j] : 0;
+        const double N = binstat[3 * b + 0], mean = binstat[3 * b + 1], sd = binstat[3 * b + 2];
+        if (N >= 2.0 && sd > 0.0) out = (u[j] - mean) / sd;
+        else status[j] = ST_BIN;
+    }
+    z[j] = out;
+}
+
+// ss_ehh epilogue: EHH curves from the traced integer sums (S_c at x0 is
+// C(n_c, 2), the denominator of Eq. 3), iHH = downstream + upstream, status.
+__global__ void ehh_finish_kernel(int64_t n, int64_t cap, const uint64_t *__restrict__ S,
+                                  const int64_t *__restrict__ len,
+                                  const double *__restrict__ dihh,
+                                  const int32_t *__restrict__ dstatus, double *__restrict__ ehh,
+                                  double *__restrict__ ihh, int8_t *__restrict__ status) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double nan = __builtin_nan("");
+    const double Pall = (double)(n * (n - 1) / 2);
+    if (t < 2 * (cap + 1)) {
+        const int64_t d = t / (cap + 1), i = t - d * (cap + 1);
+        const uint64_t *Sd = S + (size_t)d * (cap + 1) * 2;
+        double *e = ehh + (size_t)t * 3;
+        if (i <= len[d]) {
+            const double P0 = (double)Sd[0], P1 = (double)Sd[1];
+            e[0] = (double)Sd[2 * i + 0] / P0;
+            e[1] = (double)Sd[2 * i + 1] / P1;
+            e[2] = (double)(Sd[2 * i + 0] + Sd[2 * i + 1]) / Pall;
+        } else {
+            e[0] = e[1] = e[2] = nan;
+        }
+    }
+    if (t == 0) {
+        int32_t st = dstatus[0] != ST_OK ? dstatus[0] : dstatus[1];
+        const bool small = S[0] == 0 || S[1] == 0;   // C(n_c, 2) = 0: n_c < 2
+        if (st == ST_OK && small) st = ST_UNDEF;
+        double i0 = nan, i1 = nan;
+        if (st == ST_OK) {
+            i0 = dihh[0] + dihh[2];
+            i1 = dihh[1] + dihh[3];
+            if (!(i0 > 0.0) || !(i1 > 0.0)) {
+                st = ST_UNDEF;
+                i0 = i1 = nan;
+            }
+        }
+        ihh[0] = i0;
+        ihh[1] = i1;
+        status[0] = (int8_t)st;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps,
+                       uint64_t *bits, hipStream_t s) {
+    const int64_t items = M * wps;
+    const int64_t blocks = (items + kBlock / 64 - 1) / (kBlock / 64);
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, alleles, n, M,
+                       wps, bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_site_stats(const uint64_t *bits, int64_t wps, int64_t n, int64_t M,
+                             double maf_cutoff, int32_t nbins, double *freq, int32_t *bin,
+                             uint8_t *walk_flag, int8_t *status, hipStream_t s) {
+    const int64_t blocks = (M + kBlock / 64 - 1) / (kBlock / 64);
+    hipLaunchKernelGGL(site_stats_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, bits, wps,
+                       n, M, maf_cutoff, nbins, freq, bin, walk_flag, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(int mode, int64_t M, const uint8_t *walk_flag, const double *dihh,
+                          const int32_t *dstatus, const int32_t *dsteps, double *out_a,
+                          double *out_b, double *unstd, int8_t *status, int32_t *steps_out,
+                          hipStream_t s) {
+    const int64_t blocks = (M + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, M, walk_flag,
+                       dihh, dstatus, dsteps, out_a, out_b, unstd, status, steps_out,
+                       mode == MODE_POOLED ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_standardize(int64_t M, const double *unstd, int8_t *status, const int32_t *bin,
+                              int32_t nbins, double *binstat, double *z, hipStream_t s) {
+    hipLaunchKernelGGL(bin_stats_kernel, dim3((unsigned)nbins), dim3(kBlock), 0, s, M, unstd,
+                       status, bin, binstat);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t blocks = (M + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(standardize_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, M, unstd,
+                       status, bin, binstat, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_ehh_finish(int64_t n, int64_t cap, const uint64_t *S, const int64_t *len,
+                             const double *dihh, const int32_t *dstatus, double *ehh,
+                             double *ihh, int8_t *status, hipStream_t s) {
+    const int64_t items = 2 * (cap + 1);
+    const int64_t blocks = (items + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(ehh_finish_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, n, cap, S,
+                       len, dihh, dstatus, ehh, ihh, status);
+    return hipGetLastError();
+}
+
+}  // namespace ss

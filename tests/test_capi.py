@@ -1,0 +1,121 @@
+"""The C-ABI library: it loads, exports every declared symbol, and rejects bad
+arguments before touching the device (no compute calls, so no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "selscan_hip.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(ss_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1403_6854_amd as ss
+    if not os.path.exists(ss.LIB_PATH):
+        from paper_1403_6854_amd import build
+        build.build()
+    return ss.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for f in ("ss_pack", "ss_workspace_bytes", "ss_ehh", "ss_ihs", "ss_xpehh", "ss_last_error"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_default_params_and_version(lib):
+    import paper_1403_6854_amd as ss
+    p = ss._Params()
+    lib.ss_default_params(ctypes.byref(p))
+    assert (p.ehh_cutoff, p.maf_cutoff, p.gap_scale_bp, p.max_gap_bp, p.bin_width) == \
+        (0.05, 0.05, 20000, 200000, 0.025)
+    assert "gfx950" in ss.version()
+
+
+def _desc(n_haps=204, n_sites=100, wps=4, null=False):
+    import paper_1403_6854_amd as ss
+    fake = 0 if null else 0x1000   # never dereferenced: the calls fail their checks first
+    return ss._HapMat(fake, n_haps, n_sites, wps, fake, fake)
+
+
+def test_workspace_bytes_is_host_only(lib):
+    import paper_1403_6854_amd as ss
+    p = ss._cparams(None)
+    d = _desc()
+    nb = lib.ss_workspace_bytes(ss.OP_IHS, ctypes.byref(d), None, ctypes.byref(p), 0)
+    assert nb >= 100 * (1 + 4 + 32 + 8 + 16)
+    assert lib.ss_workspace_bytes(ss.OP_XPEHH, ctypes.byref(d), None, ctypes.byref(p), 0) == 0
+    bad = ss._cparams(ss.Params(ehh_cutoff=0.0))
+    assert lib.ss_workspace_bytes(ss.OP_IHS, ctypes.byref(d), None, ctypes.byref(bad), 0) == 0
+
+
+@pytest.mark.parametrize("field,value", [
+    ("ehh_cutoff", 0.0), ("ehh_cutoff", 1.5), ("ehh_cutoff", float("nan")),
+    ("maf_cutoff", -0.1), ("maf_cutoff", 0.6), ("gap_scale_bp", 0),
+    ("max_gap_bp", 100), ("bin_width", 0.0), ("bin_width", 2.0)])
+def test_bad_parameters_are_rejected(lib, field, value):
+    import paper_1403_6854_amd as ss
+    kw = {field: value}
+    p = ss._cparams(ss.Params(**kw))
+    d = _desc()
+    x = ctypes.c_void_p(0x1000)
+    rc = lib.ss_ihs(ctypes.byref(d), ctypes.byref(p), x, x, x, x, x, x, None, x, 1 << 30, None)
+    assert rc == ss.SS_EARG
+    assert lib.ss_last_error()
+
+
+@pytest.mark.parametrize("kw", [dict(n_haps=1), dict(n_haps=40000), dict(n_sites=0),
+                                dict(wps=3), dict(null=True)])
+def test_bad_hapmats_are_rejected(lib, kw):
+    import paper_1403_6854_amd as ss
+    p = ss._cparams(None)
+    d = _desc(**kw)
+    x = ctypes.c_void_p(0x1000)
+    rc = lib.ss_ihs(ctypes.byref(d), ctypes.byref(p), x, x, x, x, x, x, None, x, 1 << 30, None)
+    assert rc == ss.SS_EARG
+
+
+def test_small_workspace_and_shape_mismatch(lib):
+    import paper_1403_6854_amd as ss
+    p = ss._cparams(None)
+    a = _desc(n_sites=100)
+    b = _desc(n_sites=99)
+    x = ctypes.c_void_p(0x1000)
+    rc = lib.ss_ihs(ctypes.byref(a), ctypes.byref(p), x, x, x, x, x, x, None, x, 16, None)
+    assert rc == ss.SS_EWS
+    rc = lib.ss_xpehh(ctypes.byref(a), ctypes.byref(b), ctypes.byref(p), x, x, x, x, x, None, x,
+                      1 << 30, None)
+    assert rc == ss.SS_ESHAPE
+    big = _desc(n_haps=20000, wps=313)
+    rc = lib.ss_xpehh(ctypes.byref(big), ctypes.byref(big), ctypes.byref(p), x, x, x, x, x, None,
+                      x, 1 << 30, None)
+    assert rc == ss.SS_EARG
+    rc = lib.ss_ehh(ctypes.byref(a), 100, ctypes.byref(p), 8, x, x, x, None, x, x, x, 1 << 20, None)
+    assert rc == ss.SS_EARG        # core out of range
+    rc = lib.ss_pack(None, 10, 10, 1, x, None)
+    assert rc == ss.SS_EARG
+
+
+def test_product_does_not_reach_the_oracle():
+    # the package and its sources never import or link the test oracle
+    pkg = os.path.join(ROOT, "paper_1403_6854_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liboracle" not in text and "selscan_oracle" not in text, f

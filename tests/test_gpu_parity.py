@@ -1,0 +1,266 @@
+"""GPU parity: the HIP library through its C ABI against the CPU oracle.
+
+Bars: integer results (class sums S, class sizes, walk lengths, per-site
+status and steps) bit-exact; EHH and iHH within 1e-12 relative; log-ratios
+and standardized scores within 1e-12 * max(|a|, |b|, 1), because a log-ratio
+near 0 has no useful pure-relative bound unless both sides use the same libm.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import hapgen
+import oracle
+from tests.conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an MI355X")]
+
+REL = 1e-12
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ss():
+    import paper_1403_6854_amd as ss
+    ss.lib()
+    return ss
+
+
+def _dev(d):
+    import torch
+    return (torch.from_numpy(np.ascontiguousarray(d.alleles)).cuda(),
+            torch.from_numpy(d.pos_bp).cuda(), torch.from_numpy(d.gpos_cm).cuda())
+
+
+def _hm(ss, alleles, pos, gpos):
+    import torch
+    return ss.hapmat(torch.from_numpy(np.ascontiguousarray(alleles)).cuda(),
+                     torch.from_numpy(np.ascontiguousarray(pos, dtype=np.int64)).cuda(),
+                     torch.from_numpy(np.ascontiguousarray(gpos, dtype=np.float64)).cuda())
+
+
+def _np(out):
+    import torch
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def assert_rel(a, b, mask, what):
+    a, b = a[mask], b[mask]
+    assert np.array_equal(np.isnan(a), np.isnan(b)), what + ": NaN pattern differs"
+    f = ~np.isnan(a)
+    err = np.abs(a[f] - b[f])
+    lim = REL * np.maximum(np.abs(a[f]), np.abs(b[f]))
+    assert np.all(err <= lim), "%s: max rel err %.3g" % (
+        what, float(np.max(err / np.maximum(lim / REL, 1e-300))) if err.size else 0.0)
+
+
+def assert_log(a, b, mask, what):
+    a, b = a[mask], b[mask]
+    assert np.array_equal(np.isnan(a), np.isnan(b)), what + ": NaN pattern differs"
+    f = ~np.isnan(a)
+    err = np.abs(a[f] - b[f])
+    lim = REL * np.maximum(1.0, np.maximum(np.abs(a[f]), np.abs(b[f])))
+    assert np.all(err <= lim), "%s: max err %.3g" % (what, float(err.max()) if err.size else 0.0)
+
+
+def check_ihs(got, ref, what):
+    assert np.array_equal(got["status"], ref["status"]), what + ": status"
+    assert np.array_equal(got["steps"], ref["steps"].astype(np.int32)), what + ": steps"
+    np.testing.assert_array_equal(got["freq"], ref["freq"])
+    every = np.ones(len(ref["status"]), dtype=bool)
+    assert_rel(got["ihh1"], ref["ihh1"], every, what + ": ihh1")
+    assert_rel(got["ihh0"], ref["ihh0"], every, what + ": ihh0")
+    assert_log(got["unstd"], ref["unstd"], every, what + ": unstd")
+    assert_log(got["std"], ref["std"], every, what + ": std")
+
+
+def check_xpehh(got, ref, what):
+    assert np.array_equal(got["status"], ref["status"]), what + ": status"
+    assert np.array_equal(got["steps"], ref["steps"].astype(np.int32)), what + ": steps"
+    every = np.ones(len(ref["status"]), dtype=bool)
+    assert_rel(got["ihhA"], ref["ihhA"], every, what + ": ihhA")
+    assert_rel(got["ihhB"], ref["ihhB"], every, what + ": ihhB")
+    assert_log(got["unstd"], ref["unstd"], every, what + ": unstd")
+    assert_log(got["std"], ref["std"], every, what + ": std")
+
+
+# ---------------------------------------------------------------------------
+# ss_ehh: per-marker integer sums and class sizes, bit-exact
+# ---------------------------------------------------------------------------
+def _ehh_case(ss, d, core, params=oracle.Params(), cap=2048):
+    say("ss_ehh n=%d M=%d core=%d cutoff=%g" % (d.n_haps, d.n_sites, core, params.ehh_cutoff))
+    h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
+    got = _np(ss.ehh(h, core, ss.Params(**vars(params)), cap=cap, sizes=True))
+    ref = oracle.ehh(d.alleles, d.pos_bp, d.gpos_cm, core, params, cap=cap, sizes=True)
+    assert int(got["status"][0]) == ref["status"], "status"
+    np.testing.assert_array_equal(got["len"], ref["len"])
+    for di in range(2):
+        L = int(ref["len"][di])
+        np.testing.assert_array_equal(got["S"][di, : L + 1].astype(np.uint64), ref["S"][di, : L + 1])
+        e_g, e_r = got["ehh"][di, : L + 1], ref["ehh"][di, : L + 1]
+        assert np.array_equal(np.isnan(e_g), np.isnan(e_r))
+        np.testing.assert_array_equal(e_g[~np.isnan(e_g)], e_r[~np.isnan(e_r)])
+        for i in range(L + 1):
+            a = np.sort(got["sizes"][di, i].view(np.uint32))
+            b = np.sort(ref["sizes"][di, i])
+            np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(np.isnan(got["ihh"]), np.isnan(ref["ihh"]))
+    f = ~np.isnan(ref["ihh"])
+    assert np.all(np.abs(got["ihh"][f] - ref["ihh"][f]) <= REL * np.abs(ref["ihh"][f]))
+
+
+def test_ehh_worked_example_shapes(ss):
+    d = hapgen.config_input(0)
+    for core in (0, 1, 57, 999, 1500, 1998, 1999):
+        _ehh_case(ss, d, core)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 63, 64, 65, 127, 128, 129, 300, 700])
+def test_ehh_ragged_haplotype_counts(ss, n):
+    d = hapgen.random_haplotypes(n, 400, 10 + n, n_founders=max(2, n // 10), switch_p=0.02)
+    for core in (0, 133, 399):
+        _ehh_case(ss, d, core, oracle.Params(ehh_cutoff=0.01), cap=512)
+
+
+def test_ehh_long_sweep_walk(ss):
+    d = hapgen.config_input(1)
+    j = d.sweep_sites[0]
+    for core in (j, j - 40, j + 100):
+        _ehh_case(ss, d, core, cap=4096)
+
+
+def test_ehh_capacity_status(ss):
+    d = hapgen.config_input(1)
+    j = d.sweep_sites[0]
+    say("ss_ehh capacity case")
+    h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
+    got = _np(ss.ehh(h, j, cap=8))
+    ref = oracle.ehh(d.alleles, d.pos_bp, d.gpos_cm, j, cap=8)
+    assert int(got["status"][0]) == ref["status"] == 6
+    np.testing.assert_array_equal(got["len"], ref["len"])
+
+
+# ---------------------------------------------------------------------------
+# ss_ihs
+# ---------------------------------------------------------------------------
+def test_ihs_tiny_config(ss):
+    d = hapgen.config_input(0)
+    say("ss_ihs 200 x 2000")
+    h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
+    got = _np(ss.ihs(h, steps=True))
+    ref = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm)
+    check_ihs(got, ref, "tiny")
+
+
+def test_ihs_chr22_shaped_config(ss):
+    d = hapgen.config_input(1)
+    say("ss_ihs 204 x 22147")
+    h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
+    got = _np(ss.ihs(h, steps=True))
+    ref = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm)
+    check_ihs(got, ref, "chr22")
+    assert (ref["status"] == 0).sum() > 10000
+
+
+@pytest.mark.parametrize("case", ["gaps", "dup_positions", "maf0", "cutoff_high", "cutoff_low",
+                                  "narrow_bins", "one_site", "two_haps"])
+def test_ihs_edge_cases(ss, case):
+    rng = np.random.default_rng(hash(case) % 1000)
+    params = oracle.Params()
+    if case == "one_site":
+        d = hapgen.random_haplotypes(20, 1, 1)
+    elif case == "two_haps":
+        d = hapgen.random_haplotypes(2, 300, 2)
+        params = oracle.Params(maf_cutoff=0.0)
+    else:
+        d = hapgen.random_haplotypes(150, 1500, 3, n_founders=12, switch_p=0.01)
+    pos = d.pos_bp.copy()
+    if case == "gaps":
+        steps = rng.integers(1000, 6000, size=len(pos))
+        steps[rng.choice(len(pos), 12, replace=False)] = 25_000 + rng.integers(0, 10_000, 12)
+        steps[rng.choice(len(pos), 4, replace=False)] = 250_000
+        steps[100] = 200_000
+        steps[700] = 200_001
+        steps[900] = 20_000
+        steps[901] = 20_001
+        pos = np.cumsum(steps).astype(np.int64)
+    if case == "dup_positions":
+        pos = np.repeat(np.arange(len(pos) // 2 + 1) * 2000, 2)[: len(pos)].astype(np.int64) + 1
+    gpos = pos * 1e-6
+    if case == "maf0":
+        params = oracle.Params(maf_cutoff=0.0)
+    if case == "cutoff_high":
+        params = oracle.Params(ehh_cutoff=0.5)
+    if case == "cutoff_low":
+        params = oracle.Params(ehh_cutoff=0.001)
+    if case == "narrow_bins":
+        params = oracle.Params(bin_width=0.01)
+    say("ss_ihs edge case %s" % case)
+    h = _hm(ss, d.alleles, pos, gpos)
+    got = _np(ss.ihs(h, ss.Params(**vars(params)), steps=True))
+    ref = oracle.ihs(d.alleles, pos, gpos, params)
+    check_ihs(got, ref, case)
+
+
+def test_ihs_is_deterministic(ss):
+    d = hapgen.config_input(1)
+    say("ss_ihs twice")
+    h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
+    a = _np(ss.ihs(h, steps=True))
+    b = _np(ss.ihs(h, steps=True))
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_ihs_large_haplotype_count(ss):
+    # 5000 haplotypes: 79 words per site, several waves per walk
+    d = hapgen.random_haplotypes(5000, 300, 21, n_founders=100, switch_p=0.002)
+    say("ss_ihs 5000 x 300")
+    h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
+    got = _np(ss.ihs(h, steps=True))
+    ref = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm)
+    check_ihs(got, ref, "n5000")
+
+
+# ---------------------------------------------------------------------------
+# ss_xpehh
+# ---------------------------------------------------------------------------
+def test_xpehh_chr22_shaped_config(ss):
+    a, b = hapgen.config_input(2)
+    say("ss_xpehh 204+210 x 22147")
+    ha = _hm(ss, a.alleles, a.pos_bp, a.gpos_cm)
+    hb = _hm(ss, b.alleles, b.pos_bp, b.gpos_cm)
+    got = _np(ss.xpehh(ha, hb, steps=True))
+    ref = oracle.xpehh(a.alleles, b.alleles, a.pos_bp, a.gpos_cm)
+    check_xpehh(got, ref, "chr22 xpehh")
+
+
+@pytest.mark.parametrize("na,nb", [(2, 2), (3, 64), (64, 65), (100, 7), (400, 300), (2500, 2500)])
+def test_xpehh_ragged_populations(ss, na, nb):
+    M = 600 if na + nb < 2000 else 200
+    a = hapgen.random_haplotypes(na, M, na, n_founders=max(2, na // 20), switch_p=0.01)
+    b = hapgen.random_haplotypes(nb, M, 1000 + nb, n_founders=max(2, nb // 20), switch_p=0.02)
+    say("ss_xpehh %d+%d x %d" % (na, nb, M))
+    ha = _hm(ss, a.alleles, a.pos_bp, a.gpos_cm)
+    hb = _hm(ss, b.alleles, a.pos_bp, a.gpos_cm)
+    got = _np(ss.xpehh(ha, hb, steps=True))
+    ref = oracle.xpehh(a.alleles, b.alleles, a.pos_bp, a.gpos_cm)
+    check_xpehh(got, ref, "xpehh %d+%d" % (na, nb))
+
+
+def test_xpehh_self_is_zero(ss):
+    a, _ = hapgen.config_input(2)
+    say("ss_xpehh A vs A")
+    ha = _hm(ss, a.alleles, a.pos_bp, a.gpos_cm)
+    got = _np(ss.xpehh(ha, ha))
+    m = np.isin(got["status"], (0, 5))
+    assert m.sum() > 10000
+    assert np.all(got["unstd"][m] == 0.0)
+    np.testing.assert_array_equal(got["ihhA"][m], got["ihhB"][m])
