@@ -1,0 +1,216 @@
+"""Benchmark: iHS core loci per second on one MI355X.
+
+Workload (synthetic, seeded): 204 haplotypes x 22,147 biallelic SNPs over
+35 Mb, copying model with 40 founders and switch probability 0.003, one
+planted sweep carried by 70% of the haplotypes (the chromosome-22-shaped
+configuration; the paper's CEU chr22 data are not available).
+
+A step is one pass of the whole hot path on device-resident inputs: bit
+packing of the uint8 allele matrix, site counts and MAF filter, the EHH walks
+with trapezoid iHH, the log-ratios and the frequency-bin standardization
+(ss_pack + ss_ihs).  The XPEHH scan of the same sites against 210 haplotypes
+is timed the same way and reported beside it.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 int32 lanes/clk x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_traffic.json")
+WALK_SRC = os.path.join(ROOT, "paper_1403_6854_amd", "csrc", "ss_walk.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def walk_src_sha() -> str:
+    return hashlib.sha256(open(WALK_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per walk launch from committed rocprofv3 counter runs, if they
+    were taken on the current walk kernel source."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload)
+    if not e or e.get("walk_src_sha") != walk_src_sha():
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def cells(steps: np.ndarray, n_c: np.ndarray) -> int:
+    """Algorithmic work: markers walked by each core times its haplotypes."""
+    return int((steps.astype(np.int64) * n_c.astype(np.int64)).sum())
+
+
+def time_scan(fn, warmup: int, steps: int, ss, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ss.timing_read(reset=True)
+    ss.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ss.timing_enable(False)
+    walk_ms, launches = ss.timing_read(reset=True)
+    return (t1 - t0), walk_ms / max(1, launches), launches
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.calibrate_copy_mb:
+        import torch
+        x = torch.arange(args.calibrate_copy_mb * (1 << 20) // 8, dtype=torch.int64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1, out=y)       # reads and writes calibrate_copy_mb MiB each
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8}))
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X "
+              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import hapgen
+    import paper_1403_6854_amd as ss
+
+    dev = torch.device("cuda:0")
+    log("generating inputs")
+    a, b = hapgen.config_input(2)          # a = the 204 x 22,147 iHS workload
+    M, n = a.alleles.shape
+    A = torch.from_numpy(a.alleles).to(dev)
+    B = torch.from_numpy(b.alleles).to(dev)
+    pos = torch.from_numpy(a.pos_bp).to(dev)
+    gpos = torch.from_numpy(a.gpos_cm).to(dev)
+    params = ss.Params()
+
+    # --- iHS ---------------------------------------------------------------
+    h = ss.hapmat(A, pos, gpos)
+    h.validate()
+    ws = torch.empty(ss.workspace_bytes(ss.OP_IHS, h, None, params) + 256, dtype=torch.uint8,
+                     device=dev)
+    out = ss.ihs(h, params, steps=True, ws=ws)
+    torch.cuda.synchronize()
+    status = out["status"].cpu().numpy()
+    stp = out["steps"].cpu().numpy()
+    n1 = a.alleles.sum(axis=1).astype(np.int64)
+    n_c = np.stack([n - n1, n1], axis=1)             # [M, 2] cores 0 and 1
+    W = cells(stp, n_c[:, None, :].repeat(2, axis=1))
+    core_loci = int((status != 1).sum())
+
+    def ihs_step():
+        hb = ss.HapMat(ss.pack(A), n, pos, gpos)
+        ss.ihs(hb, params, steps=False, ws=ws, out=out, validate=False)
+
+    log("timing iHS")
+    el, walk_ms, launches = time_scan(ihs_step, args.warmup, args.steps, ss, torch)
+    ms_step = el / args.steps * 1e3
+    value = core_loci / (el / args.steps)
+
+    # --- XPEHH -------------------------------------------------------------
+    hA = ss.hapmat(A, pos, gpos)
+    hB = ss.hapmat(B, pos, gpos)
+    wsx = torch.empty(ss.workspace_bytes(ss.OP_XPEHH, hA, hB, params) + 256, dtype=torch.uint8,
+                      device=dev)
+    outx = ss.xpehh(hA, hB, params, steps=True, ws=wsx)
+    torch.cuda.synchronize()
+    stx = outx["steps"].cpu().numpy()
+    Wx = int(stx.astype(np.int64).sum()) * (n + b.alleles.shape[1])
+
+    def xp_step():
+        ha = ss.HapMat(ss.pack(A), n, pos, gpos)
+        hb2 = ss.HapMat(ss.pack(B), b.alleles.shape[1], pos, gpos)
+        ss.xpehh(ha, hb2, params, steps=False, ws=wsx, out=outx, validate=False)
+
+    log("timing XPEHH")
+    elx, walk_ms_x, _ = time_scan(xp_step, args.warmup, args.steps, ss, torch)
+    value_x = M / (elx / args.steps)
+
+    # --- roofline of the dominant kernel (the iHS walk) ----------------------
+    achieved = W / (walk_ms * 1e-3) / 1e12
+    traffic = measured_traffic("ihs_chr22_204x22147")
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_INT32_TOPS, 3),
+                "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 5),
+                "traffic": traffic,
+                "kernel": "walk_kernel<MODE_CORE,false,4>", "kernel_ms": round(walk_ms, 5),
+                "work_cells": W, "ops_per_cell": 1,
+                "algorithmic_bytes": W // 8,
+                "algorithmic_GBps": round(W / 8 / (walk_ms * 1e-3) / 1e9, 3)}
+
+    # --- CPU baseline: the oracle on this host's cores ------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.default_threads()
+        log("timing the CPU oracle on %d threads" % threads)
+        t0 = time.perf_counter()
+        for _ in range(args.cpu_reps):
+            ref = oracle.ihs(a.alleles, a.pos_bp, a.gpos_cm, threads=threads)
+        t_cpu = (time.perf_counter() - t0) / args.cpu_reps
+        assert np.array_equal(ref["status"], status)
+        cpu = {"value": round(core_loci / t_cpu, 1), "unit": "core loci/s", "cores": threads,
+               "kind": "oracle",
+               "sample": "%d full iHS scans of the 204 x 22,147 workload (%d core loci each), "
+                         "%.2f s per scan" % (args.cpu_reps, core_loci, t_cpu)}
+
+    line = {
+        "metric": "iHS core loci/sec on 1 MI355X (XPEHH beside it)",
+        "value": round(value, 1),
+        "unit": "core loci/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "ihs_chr22_204x22147", "n_haps": n, "n_sites": M,
+                   "core_loci": core_loci, "step": "ss_pack + ss_ihs (device-resident uint8 alleles)"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "xpehh": {"workload": "xpehh_chr22_204+210x22147", "value": round(value_x, 1),
+                  "unit": "core loci/s", "ms_per_step": round(elx / args.steps * 1e3, 5),
+                  "walk_kernel_ms": round(walk_ms_x, 5), "work_cells": Wx,
+                  "achieved_TOPs": round(Wx / (walk_ms_x * 1e-3) / 1e12, 4)},
+        "context": {"paper_cpu_loci_per_s": {"ihs_ceu22_1thread": 62.7, "ihs_ceu22_16threads": 671,
+                                             "xpehh_ceuyri22_1thread": 38.3,
+                                             "xpehh_ceuyri22_16threads": 426},
+                    "note": "paper: real CEU/YRI chr22 on a 2x6-core Xeon; here synthetic inputs"},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
