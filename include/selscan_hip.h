@@ -172,6 +172,17 @@ int ss_xpehh(const ss_hapmat *a, const ss_hapmat *b, const ss_params *p,
              void *stream);
 
 /*
+ * ss_set_walk_kernel -- choose the EHH-walk kernel used by ss_ihs / ss_xpehh
+ * (process-wide; results are identical, only speed differs):
+ *   0 = automatic (bitmask kernel when it applies, else class ids),
+ *   1 = class ids in LDS (any haplotype count),
+ *   2 = class bitmasks in registers (up to 512 haplotypes in the walk,
+ *       pooled for XPEHH; larger inputs use class ids).
+ * Errors: SS_EARG for any other value.
+ */
+int ss_set_walk_kernel(int kind);
+
+/*
  * Kernel timing for measurement: while enabled, ss_ihs / ss_xpehh record HIP
  * events on their stream around the EHH walk kernel; ss_timing_read() waits
  * for the recorded events and returns the summed walk-kernel time (ms) and

@@ -139,6 +139,15 @@ hipEvent_t take_event() {
     return e;
 }
 
+int g_walk_kind = ss::WALK_AUTO;
+
+hipError_t launch_scan_walk(const ss::WalkArgs &a, int mode, int64_t blocks, hipStream_t s) {
+    const bool masks_ok = ss::mask_walk_supported(a.nA, a.nB, mode);
+    const bool use_masks = masks_ok && g_walk_kind != ss::WALK_LDS_IDS;
+    if (use_masks) return ss::launch_mask_walk(a, mode, blocks, s);
+    return ss::launch_walk(a, mode, false, blocks, s);
+}
+
 int launch_timed_walk(const ss::WalkArgs &a, int mode, int64_t blocks, hipStream_t s) {
     std::unique_lock<std::mutex> lk(g_timing.mu);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -148,7 +157,7 @@ int launch_timed_walk(const ss::WalkArgs &a, int mode, int64_t blocks, hipStream
         if (!e0 || !e1) return fail(SS_EDEV, "hipEventCreate failed");
         SS_HIP(hipEventRecord(e0, s));
     }
-    SS_HIP(ss::launch_walk(a, mode, false, blocks, s));
+    SS_HIP(launch_scan_walk(a, mode, blocks, s));
     if (g_timing.on) {
         SS_HIP(hipEventRecord(e1, s));
         g_timing.pending.emplace_back(e0, e1);
@@ -313,6 +322,12 @@ int ss_xpehh(const ss_hapmat *ha, const ss_hapmat *hb, const ss_params *p, doubl
     SS_HIP(ss::launch_combine(ss::MODE_POOLED, M, nullptr, w.dihh, w.dstatus, w.dsteps, d_ihhA,
                               d_ihhB, d_unstd, d_status, d_steps, s));
     SS_HIP(ss::launch_standardize(M, d_unstd, d_status, nullptr, 1, w.binstat, d_std, s));
+    return SS_OK;
+}
+
+int ss_set_walk_kernel(int kind) {
+    if (kind < ss::WALK_AUTO || kind > ss::WALK_REG_MASKS) return fail(SS_EARG, "unknown walk kernel");
+    g_walk_kind = kind;
     return SS_OK;
 }
 

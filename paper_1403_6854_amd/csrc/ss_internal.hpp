@@ -53,6 +53,12 @@ struct WalkShape {
 };
 
 WalkShape walk_shape(int32_t nA, int32_t nB, int mode);
+
+// Walk kernel variants: class ids in LDS (any haplotype count) or class
+// bitmasks in registers (up to 512 haplotypes).
+enum WalkKind : int { WALK_AUTO = 0, WALK_LDS_IDS = 1, WALK_REG_MASKS = 2 };
+bool mask_walk_supported(int32_t nA, int32_t nB, int mode);
+hipError_t launch_mask_walk(const WalkArgs &a, int mode, int64_t n_blocks, hipStream_t s);
 hipError_t launch_walk(const WalkArgs &a, int mode, bool trace, int64_t n_blocks,
                        hipStream_t s);
 

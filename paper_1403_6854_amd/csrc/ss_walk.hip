@@ -49,10 +49,18 @@ __device__ __forceinline__ uint32_t choose2(uint32_t x) {
     return (x * (x - 1u)) >> 1;
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+// Sum over the 64 lanes of a wave (DPP reduction in the device library;
+// every lane must be active).
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return __ockl_wfred_add_u32(v); }
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int i) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, i);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), i);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int i) {
+    return __builtin_bit_cast(double, readlane64(__builtin_bit_cast(uint64_t, v), i));
 }
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
@@ -193,157 +201,195 @@ __global__ void __launch_bounds__(1024) walk_kernel(WalkArgs a) {
 
     int32_t K = 2;
     int32_t status = ST_OK;
-    int64_t k = j;
     int step = 0;
     while (act0 || act1) {
-        k += dir;
-        if (k < 0 || k >= a.M) { status = ST_EDGE; break; }
-        const int64_t lo = dir > 0 ? k - 1 : k;
-        const int64_t b = a.pos[lo + 1] - a.pos[lo];
-        if (b > a.max_gap) { status = ST_GAP; break; }
-        double g = a.gpos[lo + 1] - a.gpos[lo];
-        if (b > a.gap_scale) g = g * ((double)a.gap_scale / (double)b);
-        if (TRACE && step >= a.cap) { status = ST_CAP; break; }
-
-        const int par = step & 1;
-        uint32_t *szc = par ? szv1 : szv0;
-        uint32_t *szn = par ? szv0 : szv1;
-        uint32_t *sa = sacc + 4 * par;
-        int32_t *kn = knext + par;
-
-        // (1) ones per class
-        int32_t bit[R];
+        // Stage the next 64 markers of the walk: lane i of every wave loads
+        // its slots' row words for step (step + 1 + i) and works out that
+        // step's segment: end of data, abort gap, or scaled genetic length.
+        // The per-marker loop below then reads them with readlane, so no
+        // global-memory latency sits on the serial chain of the walk.
+        const int64_t kb = j + (int64_t)dir * (int64_t)(step + 1 + lane);
+        const bool inr = kb >= 0 && kb < a.M;
+        uint64_t rowv[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            bit[r] = 0;
-            if (word[r]) {
-                const uint64_t w = src[r][k * stride[r]];
-                bit[r] = (int32_t)((w >> lane) & 1ull);
-                if (cls[r] != DEAD && bit[r]) atomicAdd(&cnt1[cls[r]], inc[r]);
+        for (int r = 0; r < R; ++r) rowv[r] = (word[r] && inr) ? src[r][kb * stride[r]] : 0ull;
+        int32_t stl = ST_OK;
+        double gl = 0.0;
+        if (!inr) {
+            stl = ST_EDGE;
+        } else {
+            const int64_t lo = dir > 0 ? kb - 1 : kb;
+            const int64_t b = a.pos[lo + 1] - a.pos[lo];
+            if (b > a.max_gap) {
+                stl = ST_GAP;
+            } else {
+                double g = a.gpos[lo + 1] - a.gpos[lo];
+                if (b > a.gap_scale) g = g * ((double)a.gap_scale / (double)b);
+                gl = g;
             }
         }
-        __syncthreads();
+        const uint64_t abort_mask = __ballot(stl != ST_OK);
+        const int nb = abort_mask ? (int)__builtin_ctzll(abort_mask) : 64;
+        const int32_t abort_st = abort_mask ? (int32_t)__builtin_amdgcn_readlane(stl, nb) : ST_OK;
 
-        // (2) split every class, keep children with >= 2 members
-        for (int c0 = 0; c0 < K; c0 += T) {
-            const int c = c0 + tid;
-            const bool in = c < K;
-            uint32_t one = 0u, sz = 0u;
-            if (in) {
-                one = cnt1[c];
-                cnt1[c] = 0u;
-                sz = szc[c];
-            }
-            bool keepz = false, keepo = false;
-            uint32_t wz = 0u, wo = 0u;
-            uint32_t s0 = 0u, s1 = 0u, s2 = 0u;
-            if (in) {
-                if (MODE == MODE_CORE) {
-                    const uint32_t core = sz >> 31;
-                    const uint32_t n = sz & 0xFFFFu;
-                    const uint32_t o = one, z = n - one;
-                    const bool live = TRACE || (core ? act1 : act0);
-                    const uint32_t s = choose2(o) + choose2(z);
-                    if (core) s1 = s; else s0 = s;
-                    keepz = live && z >= 2u;
-                    keepo = live && o >= 2u;
-                    wz = z | (core << 31);
-                    wo = o | (core << 31);
-                } else {
-                    const uint32_t nA = sz & 0xFFFFu, nB = sz >> 16;
-                    const uint32_t oA = one & 0xFFFFu, oB = one >> 16;
-                    const uint32_t zA = nA - oA, zB = nB - oB;
-                    s0 = choose2(oA) + choose2(zA);
-                    s1 = choose2(oB) + choose2(zB);
-                    s2 = choose2(oA + oB) + choose2(zA + zB);
-                    keepz = zA + zB >= 2u;
-                    keepo = oA + oB >= 2u;
-                    wz = zA | (zB << 16);
-                    wo = oA | (oB << 16);
+        for (int i = 0; i < 64 && (act0 || act1); ++i) {
+            if (i == nb) { status = abort_st; goto done; }
+            if (TRACE && step >= a.cap) { status = ST_CAP; goto done; }
+            const double g = readlane_f64(gl, i);
+
+            const int par = step & 1;
+            uint32_t *szc = par ? szv1 : szv0;
+            uint32_t *szn = par ? szv0 : szv1;
+            uint32_t *sa = sacc + 4 * par;
+            int32_t *kn = knext + par;
+
+            // (1) ones per class
+            int32_t bit[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                bit[r] = 0;
+                if (word[r]) {
+                    const uint64_t w = readlane64(rowv[r], i);
+                    bit[r] = (int32_t)((w >> lane) & 1ull);
+                    if (cls[r] != DEAD && bit[r]) atomicAdd(&cnt1[cls[r]], inc[r]);
                 }
             }
-            const uint64_t bz = __ballot(keepz);
-            const uint64_t bo = __ballot(keepo);
-            const int nz = __popcll(bz), no = __popcll(bo);
-            int base = 0;
-            if (lane == 0 && nz + no > 0) base = atomicAdd(kn, nz + no);
-            base = __shfl(base, 0, 64);
-            const int idz = base + (int)lanes_below(bz);
-            const int ido = base + nz + (int)lanes_below(bo);
-            if (in) {
-                map[2 * c] = keepz ? idz : DEAD;
-                map[2 * c + 1] = keepo ? ido : DEAD;
-            }
-            if (keepz) szn[idz] = wz;
-            if (keepo) szn[ido] = wo;
-            if (TRACE && a.trSizes) {
-                uint32_t *z = a.trSizes + ((size_t)d * (a.cap + 1) + (step + 1)) * a.nA;
-                if (keepz) z[idz] = wz;
-                if (keepo) z[ido] = wo;
-            }
-            s0 = wave_sum(s0);
-            s1 = wave_sum(s1);
-            if (MODE == MODE_POOLED) s2 = wave_sum(s2);
-            if (lane == 0) {
-                if (s0) atomicAdd(&sa[0], s0);
-                if (s1) atomicAdd(&sa[1], s1);
-                if (MODE == MODE_POOLED && s2) atomicAdd(&sa[2], s2);
-            }
-        }
-        __syncthreads();
+            __syncthreads();
 
-        // (3) new class ids
+            // (2) split every class, keep children with >= 2 members
+            for (int c0 = 0; c0 < K; c0 += T) {
+                const int c = c0 + tid;
+                const bool in = c < K;
+                uint32_t one = 0u, sz = 0u;
+                if (in) {
+                    one = cnt1[c];
+                    cnt1[c] = 0u;
+                    sz = szc[c];
+                }
+                bool keepz = false, keepo = false;
+                uint32_t wz = 0u, wo = 0u;
+                uint32_t s0 = 0u, s1 = 0u, s2 = 0u;
+                if (in) {
+                    if (MODE == MODE_CORE) {
+                        const uint32_t core = sz >> 31;
+                        const uint32_t n = sz & 0xFFFFu;
+                        const uint32_t o = one, z = n - one;
+                        const bool live = TRACE || (core ? act1 : act0);
+                        const uint32_t sc = choose2(o) + choose2(z);
+                        if (core) s1 = sc; else s0 = sc;
+                        keepz = live && z >= 2u;
+                        keepo = live && o >= 2u;
+                        wz = z | (core << 31);
+                        wo = o | (core << 31);
+                    } else {
+                        const uint32_t nA = sz & 0xFFFFu, nB = sz >> 16;
+                        const uint32_t oA = one & 0xFFFFu, oB = one >> 16;
+                        const uint32_t zA = nA - oA, zB = nB - oB;
+                        s0 = choose2(oA) + choose2(zA);
+                        s1 = choose2(oB) + choose2(zB);
+                        s2 = choose2(oA + oB) + choose2(zA + zB);
+                        keepz = zA + zB >= 2u;
+                        keepo = oA + oB >= 2u;
+                        wz = zA | (zB << 16);
+                        wo = oA | (oB << 16);
+                    }
+                }
+                const uint64_t bz = __ballot(keepz);
+                const uint64_t bo = __ballot(keepo);
+                const int nz = __popcll(bz), no = __popcll(bo);
+                int base = 0;
+                if (T == 64) {
+                    base = kn[0];
+                } else if (lane == 0 && nz + no > 0) {
+                    base = atomicAdd(kn, nz + no);
+                }
+                if (T != 64) base = __shfl(base, 0, 64);
+                const int idz = base + (int)lanes_below(bz);
+                const int ido = base + nz + (int)lanes_below(bo);
+                if (in) {
+                    map[2 * c] = keepz ? idz : DEAD;
+                    map[2 * c + 1] = keepo ? ido : DEAD;
+                }
+                if (keepz) szn[idz] = wz;
+                if (keepo) szn[ido] = wo;
+                if (TRACE && a.trSizes) {
+                    uint32_t *z = a.trSizes + ((size_t)d * (a.cap + 1) + (step + 1)) * a.nA;
+                    if (keepz) z[idz] = wz;
+                    if (keepo) z[ido] = wo;
+                }
+                s0 = wave_sum(s0);
+                s1 = wave_sum(s1);
+                if (MODE == MODE_POOLED) s2 = wave_sum(s2);
+                if (lane == 0) {
+                    if (T == 64) {
+                        kn[0] = base + nz + no;
+                        sa[0] += s0;
+                        sa[1] += s1;
+                        if (MODE == MODE_POOLED) sa[2] += s2;
+                    } else {
+                        if (s0) atomicAdd(&sa[0], s0);
+                        if (s1) atomicAdd(&sa[1], s1);
+                        if (MODE == MODE_POOLED && s2) atomicAdd(&sa[2], s2);
+                    }
+                }
+                if (T == 64) __syncthreads();   // kn[0] is read again next round
+            }
+            __syncthreads();
+
+            // (3) new class ids
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (cls[r] != DEAD) cls[r] = map[2 * cls[r] + bit[r]];
-        K = kn[0];
-        const uint32_t S0 = sa[0], S1 = sa[1], S2 = sa[2];
-        if (tid == 0) {
-            uint32_t *other = sacc + 4 * (par ^ 1);
-            other[0] = other[1] = other[2] = 0u;
-            knext[par ^ 1] = 0;
-        }
-        step += 1;
-
-        if (MODE == MODE_CORE) {
-            if (TRACE && tid == 0) {
-                a.trS[((size_t)d * (a.cap + 1) + step) * 2 + 0] = S0;
-                a.trS[((size_t)d * (a.cap + 1) + step) * 2 + 1] = S1;
+            for (int r = 0; r < R; ++r)
+                if (cls[r] != DEAD) cls[r] = map[2 * cls[r] + bit[r]];
+            K = kn[0];
+            const uint32_t S0 = sa[0], S1 = sa[1], S2 = sa[2];
+            if (tid == 0) {
+                uint32_t *other = sacc + 4 * (par ^ 1);
+                other[0] = other[1] = other[2] = 0u;
+                knext[par ^ 1] = 0;
             }
-            if (act0) {
+            step += 1;
+
+            if (MODE == MODE_CORE) {
+                if (TRACE && tid == 0) {
+                    a.trS[((size_t)d * (a.cap + 1) + step) * 2 + 0] = S0;
+                    a.trS[((size_t)d * (a.cap + 1) + step) * 2 + 1] = S1;
+                }
+                if (act0) {
+                    steps0 += 1;
+                    const double e = (double)S0 / P0;
+                    if (e < a.cutoff) {
+                        act0 = false;
+                    } else {
+                        ihh0 += 0.5 * (ep0 + e) * g;
+                        ep0 = e;
+                    }
+                }
+                if (act1) {
+                    steps1 += 1;
+                    const double e = (double)S1 / P1;
+                    if (e < a.cutoff) {
+                        act1 = false;
+                    } else {
+                        ihh1 += 0.5 * (ep1 + e) * g;
+                        ep1 = e;
+                    }
+                }
+            } else {
                 steps0 += 1;
-                const double e = (double)S0 / P0;
-                if (e < a.cutoff) {
+                if ((double)S2 / PP < a.cutoff) {
                     act0 = false;
                 } else {
-                    ihh0 += 0.5 * (ep0 + e) * g;
-                    ep0 = e;
+                    const double eA = (double)S0 / P0;
+                    const double eB = (double)S1 / P1;
+                    ihh0 += 0.5 * (ep0 + eA) * g;
+                    ihh1 += 0.5 * (ep1 + eB) * g;
+                    ep0 = eA;
+                    ep1 = eB;
                 }
-            }
-            if (act1) {
-                steps1 += 1;
-                const double e = (double)S1 / P1;
-                if (e < a.cutoff) {
-                    act1 = false;
-                } else {
-                    ihh1 += 0.5 * (ep1 + e) * g;
-                    ep1 = e;
-                }
-            }
-        } else {
-            steps0 += 1;
-            if ((double)S2 / PP < a.cutoff) {
-                act0 = false;
-            } else {
-                const double eA = (double)S0 / P0;
-                const double eB = (double)S1 / P1;
-                ihh0 += 0.5 * (ep0 + eA) * g;
-                ihh1 += 0.5 * (ep1 + eB) * g;
-                ep0 = eA;
-                ep1 = eB;
             }
         }
     }
+done:
 
     if (tid == 0) {
         const size_t o = (size_t)j * 2 + d;

@@ -6,6 +6,7 @@ and standardized scores within 1e-12 * max(|a|, |b|, 1), because a log-ratio
 near 0 has no useful pure-relative bound unless both sides use the same libm.
 """
 import sys
+import zlib
 
 import numpy as np
 import pytest
@@ -30,6 +31,14 @@ def ss():
     import paper_1403_6854_amd as ss
     ss.lib()
     return ss
+
+
+@pytest.fixture(params=[1, 2], ids=["lds_ids", "reg_masks"])
+def walk(request, ss):
+    """Run a scan test with each EHH-walk kernel (results must not depend on it)."""
+    ss.set_walk_kernel(request.param)
+    yield request.param
+    ss.set_walk_kernel(0)
 
 
 def _dev(d):
@@ -150,18 +159,18 @@ def test_ehh_capacity_status(ss):
 # ---------------------------------------------------------------------------
 # ss_ihs
 # ---------------------------------------------------------------------------
-def test_ihs_tiny_config(ss):
+def test_ihs_tiny_config(ss, walk):
     d = hapgen.config_input(0)
-    say("ss_ihs 200 x 2000")
+    say("ss_ihs 200 x 2000 walk=%d" % walk)
     h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
     got = _np(ss.ihs(h, steps=True))
     ref = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm)
     check_ihs(got, ref, "tiny")
 
 
-def test_ihs_chr22_shaped_config(ss):
+def test_ihs_chr22_shaped_config(ss, walk):
     d = hapgen.config_input(1)
-    say("ss_ihs 204 x 22147")
+    say("ss_ihs 204 x 22147 walk=%d" % walk)
     h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
     got = _np(ss.ihs(h, steps=True))
     ref = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm)
@@ -171,8 +180,8 @@ def test_ihs_chr22_shaped_config(ss):
 
 @pytest.mark.parametrize("case", ["gaps", "dup_positions", "maf0", "cutoff_high", "cutoff_low",
                                   "narrow_bins", "one_site", "two_haps"])
-def test_ihs_edge_cases(ss, case):
-    rng = np.random.default_rng(hash(case) % 1000)
+def test_ihs_edge_cases(ss, walk, case):
+    rng = np.random.default_rng(zlib.crc32(case.encode()))
     params = oracle.Params()
     if case == "one_site":
         d = hapgen.random_haplotypes(20, 1, 1)
@@ -202,14 +211,25 @@ def test_ihs_edge_cases(ss, case):
         params = oracle.Params(ehh_cutoff=0.001)
     if case == "narrow_bins":
         params = oracle.Params(bin_width=0.01)
-    say("ss_ihs edge case %s" % case)
+    say("ss_ihs edge case %s walk=%d" % (case, walk))
     h = _hm(ss, d.alleles, pos, gpos)
     got = _np(ss.ihs(h, ss.Params(**vars(params)), steps=True))
     ref = oracle.ihs(d.alleles, pos, gpos, params)
     check_ihs(got, ref, case)
 
 
-def test_ihs_is_deterministic(ss):
+@pytest.mark.parametrize("n", [3, 63, 64, 65, 128, 129, 256, 257, 400, 511, 512, 513])
+def test_ihs_ragged_haplotype_counts(ss, walk, n):
+    d = hapgen.random_haplotypes(n, 700, 40 + n, n_founders=max(2, n // 12), switch_p=0.01)
+    say("ss_ihs %d x 700 walk=%d" % (n, walk))
+    h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
+    params = oracle.Params(maf_cutoff=0.0)
+    got = _np(ss.ihs(h, ss.Params(**vars(params)), steps=True))
+    ref = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm, params)
+    check_ihs(got, ref, "n=%d" % n)
+
+
+def test_ihs_is_deterministic(ss, walk):
     d = hapgen.config_input(1)
     say("ss_ihs twice")
     h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
@@ -219,7 +239,7 @@ def test_ihs_is_deterministic(ss):
         np.testing.assert_array_equal(a[k], b[k])
 
 
-def test_ihs_large_haplotype_count(ss):
+def test_ihs_large_haplotype_count(ss, walk):
     # 5000 haplotypes: 79 words per site, several waves per walk
     d = hapgen.random_haplotypes(5000, 300, 21, n_founders=100, switch_p=0.002)
     say("ss_ihs 5000 x 300")
@@ -232,9 +252,9 @@ def test_ihs_large_haplotype_count(ss):
 # ---------------------------------------------------------------------------
 # ss_xpehh
 # ---------------------------------------------------------------------------
-def test_xpehh_chr22_shaped_config(ss):
+def test_xpehh_chr22_shaped_config(ss, walk):
     a, b = hapgen.config_input(2)
-    say("ss_xpehh 204+210 x 22147")
+    say("ss_xpehh 204+210 x 22147 walk=%d" % walk)
     ha = _hm(ss, a.alleles, a.pos_bp, a.gpos_cm)
     hb = _hm(ss, b.alleles, b.pos_bp, b.gpos_cm)
     got = _np(ss.xpehh(ha, hb, steps=True))
@@ -243,11 +263,11 @@ def test_xpehh_chr22_shaped_config(ss):
 
 
 @pytest.mark.parametrize("na,nb", [(2, 2), (3, 64), (64, 65), (100, 7), (400, 300), (2500, 2500)])
-def test_xpehh_ragged_populations(ss, na, nb):
+def test_xpehh_ragged_populations(ss, walk, na, nb):
     M = 600 if na + nb < 2000 else 200
     a = hapgen.random_haplotypes(na, M, na, n_founders=max(2, na // 20), switch_p=0.01)
     b = hapgen.random_haplotypes(nb, M, 1000 + nb, n_founders=max(2, nb // 20), switch_p=0.02)
-    say("ss_xpehh %d+%d x %d" % (na, nb, M))
+    say("ss_xpehh %d+%d x %d walk=%d" % (na, nb, M, walk))
     ha = _hm(ss, a.alleles, a.pos_bp, a.gpos_cm)
     hb = _hm(ss, b.alleles, a.pos_bp, a.gpos_cm)
     got = _np(ss.xpehh(ha, hb, steps=True))
@@ -255,7 +275,7 @@ def test_xpehh_ragged_populations(ss, na, nb):
     check_xpehh(got, ref, "xpehh %d+%d" % (na, nb))
 
 
-def test_xpehh_self_is_zero(ss):
+def test_xpehh_self_is_zero(ss, walk):
     a, _ = hapgen.config_input(2)
     say("ss_xpehh A vs A")
     ha = _hm(ss, a.alleles, a.pos_bp, a.gpos_cm)
