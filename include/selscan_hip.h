@@ -183,6 +183,16 @@ int ss_xpehh(const ss_hapmat *a, const ss_hapmat *b, const ss_params *p,
 int ss_set_walk_kernel(int kind);
 
 /*
+ * ss_set_mask_lanes -- tuning of the bitmask walk kernel (process-wide):
+ * how many lanes of a wave hold one class (1, 2, 4 or 8; each lane holds
+ * words_per_class / lanes of its mask), or 0 for the default.  More lanes per
+ * class cut the per-marker work when few classes are alive; fewer lanes fit
+ * more classes in one row.  Results are identical for every setting.
+ * Errors: SS_EARG for any other value.
+ */
+int ss_set_mask_lanes(int lanes_per_class);
+
+/*
  * Kernel timing for measurement: while enabled, ss_ihs / ss_xpehh record HIP
  * events on their stream around the EHH walk kernel; ss_timing_read() waits
  * for the recorded events and returns the summed walk-kernel time (ms) and

@@ -74,11 +74,12 @@ def lib():
         L.ss_ihs.argtypes = [HM, PR, P, P, P, P, P, P, P, P, sz, P]
         L.ss_xpehh.argtypes = [HM, HM, PR, P, P, P, P, P, P, P, sz, P]
         L.ss_set_walk_kernel.argtypes = [ctypes.c_int]
+        L.ss_set_mask_lanes.argtypes = [ctypes.c_int]
         L.ss_timing_enable.argtypes = [ctypes.c_int]
         L.ss_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                      ctypes.c_int]
-        for f in ("ss_pack", "ss_ehh", "ss_ihs", "ss_xpehh", "ss_set_walk_kernel", "ss_timing_enable",
-                  "ss_timing_read"):
+        for f in ("ss_pack", "ss_ehh", "ss_ihs", "ss_xpehh", "ss_set_walk_kernel", "ss_set_mask_lanes",
+                  "ss_timing_enable", "ss_timing_read"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -305,6 +306,11 @@ WALK_AUTO, WALK_LDS_IDS, WALK_REG_MASKS = 0, 1, 2
 def set_walk_kernel(kind: int):
     """Select the EHH-walk kernel (0 auto, 1 class ids in LDS, 2 register bitmasks)."""
     _check(lib().ss_set_walk_kernel(int(kind)))
+
+
+def set_mask_lanes(lanes_per_class: int):
+    """Lanes per class of the bitmask walk (1, 2, 4, 8; 0 = default)."""
+    _check(lib().ss_set_mask_lanes(int(lanes_per_class)))
 
 
 def timing_enable(on: bool = True):

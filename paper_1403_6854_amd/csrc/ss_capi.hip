@@ -79,13 +79,15 @@ struct ScanWs {
     uint8_t *walk_flag;   // [M]
     int32_t *bin;         // [M]
     double *dihh;         // [M][2][2]
-    int32_t *dstatus;     // [M][2]
+    int32_t *dstatus;     // [M][2][2]
     int32_t *dsteps;      // [M][2][2]
     double *binstat;      // [nbins][3]
+    uint64_t *hbits;      // [n][mwp] haplotype-major copy (iHS only)
+    double *seg;          // [M] segment lengths with the gap rules applied
     size_t bytes;
 };
 
-ScanWs carve_scan(void *base, int64_t M, int nbins) {
+ScanWs carve_scan(void *base, int64_t M, int nbins, int64_t n_hapmajor = 0) {
     ScanWs w;
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -96,9 +98,12 @@ ScanWs carve_scan(void *base, int64_t M, int nbins) {
     w.walk_flag = (uint8_t *)take((size_t)M);
     w.bin = (int32_t *)take(4 * (size_t)M);
     w.dihh = (double *)take(32 * (size_t)M);
-    w.dstatus = (int32_t *)take(8 * (size_t)M);
+    w.dstatus = (int32_t *)take(16 * (size_t)M);
     w.dsteps = (int32_t *)take(16 * (size_t)M);
     w.binstat = (double *)take(24 * (size_t)nbins);
+    w.hbits = n_hapmajor ? (uint64_t *)take(8 * (size_t)n_hapmajor * (size_t)ss::hap_major_words(M))
+                         : nullptr;
+    w.seg = (double *)take(8 * (size_t)M);
     w.bytes = off;
     return w;
 }
@@ -140,12 +145,26 @@ hipEvent_t take_event() {
 }
 
 int g_walk_kind = ss::WALK_AUTO;
+int g_mask_lpc = 0;   // lanes per class of the bitmask walk; 0 = default
+
+// Automatic choice: the bitmask walk (with its pairwise phase) for iHS when
+// the haplotypes fit; the class-id walk for XPEHH, whose pooled walks are short
+// and whose bitmask form needs twice the registers.
+bool use_mask_walk(int32_t nA, int32_t nB, int mode) {
+    if (g_walk_kind == ss::WALK_LDS_IDS) return false;
+    if (!ss::mask_walk_shape(nA, nB, mode, g_mask_lpc).ok) return false;
+    return g_walk_kind == ss::WALK_REG_MASKS || mode == ss::MODE_CORE;
+}
 
 hipError_t launch_scan_walk(const ss::WalkArgs &a, int mode, int64_t blocks, hipStream_t s) {
-    const bool masks_ok = ss::mask_walk_supported(a.nA, a.nB, mode);
-    const bool use_masks = masks_ok && g_walk_kind != ss::WALK_LDS_IDS;
-    if (use_masks) return ss::launch_mask_walk(a, mode, blocks, s);
+    if (use_mask_walk(a.nA, a.nB, mode)) return ss::launch_mask_walk(a, mode, g_mask_lpc, blocks, s);
     return ss::launch_walk(a, mode, false, blocks, s);
+}
+
+// LDS needed by the walk chosen for this shape.
+size_t scan_walk_lds(int32_t nA, int32_t nB, int mode) {
+    if (use_mask_walk(nA, nB, mode)) return ss::mask_walk_shape(nA, nB, mode, g_mask_lpc).lds;
+    return ss::walk_shape(nA, nB, mode).lds;
 }
 
 int launch_timed_walk(const ss::WalkArgs &a, int mode, int64_t blocks, hipStream_t s) {
@@ -219,7 +238,7 @@ size_t ss_workspace_bytes(int op, const ss_hapmat *a, const ss_hapmat *b, const 
     if (!a || !p || check_params(p) != SS_OK) return 0;
     switch (op) {
         case SS_OP_EHH: return carve_ehh(nullptr).bytes;
-        case SS_OP_IHS: return carve_scan(nullptr, a->n_sites, nbins_of(p)).bytes;
+        case SS_OP_IHS: return carve_scan(nullptr, a->n_sites, nbins_of(p), a->n_haps).bytes;
         case SS_OP_XPEHH:
             if (!b) return 0;
             return carve_scan(nullptr, a->n_sites, 1).bytes;
@@ -271,10 +290,9 @@ int ss_ihs(const ss_hapmat *h, const ss_params *p, double *d_ihh1, double *d_ihh
     if (!d_ihh1 || !d_ihh0 || !d_unstd || !d_std || !d_freq || !d_status)
         return fail(SS_EARG, "null output pointer");
     const int nbins = nbins_of(p);
-    ScanWs w = carve_scan(d_ws, h->n_sites, nbins);
+    ScanWs w = carve_scan(d_ws, h->n_sites, nbins, h->n_haps);
     if (!d_ws || ws_bytes < w.bytes) return fail(SS_EWS, "workspace smaller than ss_workspace_bytes()");
-    const ss::WalkShape sh = ss::walk_shape((int32_t)h->n_haps, 0, ss::MODE_CORE);
-    if ((rc = check_lds(sh.lds)) != SS_OK) return rc;
+    if ((rc = check_lds(scan_walk_lds((int32_t)h->n_haps, 0, ss::MODE_CORE))) != SS_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int64_t M = h->n_sites;
     SS_HIP(ss::launch_site_stats(h->bits, h->words_per_site, h->n_haps, M, p->maf_cutoff, nbins,
@@ -286,6 +304,11 @@ int ss_ihs(const ss_hapmat *h, const ss_params *p, double *d_ihh1, double *d_ihh
     a.ihh = w.dihh;
     a.dstatus = w.dstatus;
     a.steps = w.dsteps;
+    a.mwp = ss::hap_major_words(M);
+    a.hbits = w.hbits;
+    a.seg = w.seg;
+    SS_HIP(ss::launch_transpose(h->bits, h->words_per_site, h->n_haps, M, a.mwp, w.hbits, s));
+    SS_HIP(ss::launch_segments(M, h->pos_bp, h->gpos_cm, p->gap_scale_bp, p->max_gap_bp, w.seg, s));
     if ((rc = launch_timed_walk(a, ss::MODE_CORE, M, s)) != SS_OK) return rc;
     SS_HIP(ss::launch_combine(ss::MODE_CORE, M, w.walk_flag, w.dihh, w.dstatus, w.dsteps, d_ihh1,
                               d_ihh0, d_unstd, d_status, d_steps, s));
@@ -307,8 +330,9 @@ int ss_xpehh(const ss_hapmat *ha, const ss_hapmat *hb, const ss_params *p, doubl
         return fail(SS_EARG, "null output pointer");
     ScanWs w = carve_scan(d_ws, ha->n_sites, 1);
     if (!d_ws || ws_bytes < w.bytes) return fail(SS_EWS, "workspace smaller than ss_workspace_bytes()");
-    const ss::WalkShape sh = ss::walk_shape((int32_t)ha->n_haps, (int32_t)hb->n_haps, ss::MODE_POOLED);
-    if ((rc = check_lds(sh.lds)) != SS_OK) return rc;
+    if ((rc = check_lds(scan_walk_lds((int32_t)ha->n_haps, (int32_t)hb->n_haps, ss::MODE_POOLED))) !=
+        SS_OK)
+        return rc;
     hipStream_t s = (hipStream_t)stream;
     const int64_t M = ha->n_sites;
     ss::WalkArgs a = walk_args(ha, hb, p);
@@ -318,6 +342,8 @@ int ss_xpehh(const ss_hapmat *ha, const ss_hapmat *hb, const ss_params *p, doubl
     a.ihh = w.dihh;
     a.dstatus = w.dstatus;
     a.steps = w.dsteps;
+    a.seg = w.seg;
+    SS_HIP(ss::launch_segments(M, ha->pos_bp, ha->gpos_cm, p->gap_scale_bp, p->max_gap_bp, w.seg, s));
     if ((rc = launch_timed_walk(a, ss::MODE_POOLED, M, s)) != SS_OK) return rc;
     SS_HIP(ss::launch_combine(ss::MODE_POOLED, M, nullptr, w.dihh, w.dstatus, w.dsteps, d_ihhA,
                               d_ihhB, d_unstd, d_status, d_steps, s));
@@ -328,6 +354,14 @@ int ss_xpehh(const ss_hapmat *ha, const ss_hapmat *hb, const ss_params *p, doubl
 int ss_set_walk_kernel(int kind) {
     if (kind < ss::WALK_AUTO || kind > ss::WALK_REG_MASKS) return fail(SS_EARG, "unknown walk kernel");
     g_walk_kind = kind;
+    return SS_OK;
+}
+
+int ss_set_mask_lanes(int lanes_per_class) {
+    if (lanes_per_class != 0 && lanes_per_class != 1 && lanes_per_class != 2 &&
+        lanes_per_class != 4 && lanes_per_class != 8)
+        return fail(SS_EARG, "lanes_per_class must be 0, 1, 2, 4 or 8");
+    g_mask_lpc = lanes_per_class;
     return SS_OK;
 }
 

@@ -37,13 +37,19 @@ struct WalkArgs {
     int64_t site0;
     int32_t kmax;               // class-table capacity in LDS
     double *ihh;                // [M][2 dirs][2]
-    int32_t *dstatus;           // [M][2 dirs]
+    int32_t *dstatus;           // [M][2 dirs][2] (per core for iHS walks split by core)
     int32_t *steps;             // [M][2 dirs][2]
     // ss_ehh trace outputs (one site only)
     uint64_t *trS;              // [2][cap+1][2]
     uint32_t *trSizes;          // [2][cap+1][n] or null
     int64_t *trLen;             // [2]
     int64_t cap;
+    // haplotype-major copy of population A (pairwise phase of the iHS walk)
+    const uint64_t *hbits;      // [nA][mwp], null: no pairwise phase
+    int64_t mwp;
+    // per-segment genetic lengths with the gap rules applied (segment k-1 -> k
+    // at index k; -1 marks an abort gap); null: walks compute them
+    const double *seg;
 };
 
 struct WalkShape {
@@ -57,14 +63,32 @@ WalkShape walk_shape(int32_t nA, int32_t nB, int mode);
 // Walk kernel variants: class ids in LDS (any haplotype count) or class
 // bitmasks in registers (up to 512 haplotypes).
 enum WalkKind : int { WALK_AUTO = 0, WALK_LDS_IDS = 1, WALK_REG_MASKS = 2 };
+
+// Launch shape of the register-bitmask walk: mask words per class (padded to
+// 1, 2, 4 or 8), lanes per class, rows of 64/lpc classes, LDS bytes.
+struct MaskShape {
+    bool ok;
+    int words;
+    int lpc;
+    int rows;
+    int pair_cap;   // pairs held in LDS by the pairwise phase (0: none)
+    size_t lds;
+};
+MaskShape mask_walk_shape(int32_t nA, int32_t nB, int mode, int lpc);
 bool mask_walk_supported(int32_t nA, int32_t nB, int mode);
-hipError_t launch_mask_walk(const WalkArgs &a, int mode, int64_t n_blocks, hipStream_t s);
+hipError_t launch_mask_walk(const WalkArgs &a, int mode, int lpc, int64_t n_blocks, hipStream_t s);
 hipError_t launch_walk(const WalkArgs &a, int mode, bool trace, int64_t n_blocks,
                        hipStream_t s);
 
 // Site-level kernels.
 hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps,
                        uint64_t *bits, hipStream_t s);
+hipError_t launch_segments(int64_t M, const int64_t *pos, const double *gpos, int64_t gap_scale,
+                           int64_t max_gap, double *seg, hipStream_t s);
+// Haplotype-major transposed matrix: [n][mwp] words, mwp = ceil(M/64) + 2.
+inline int64_t hap_major_words(int64_t M) { return (M + 63) / 64 + 2; }
+hipError_t launch_transpose(const uint64_t *bits, int64_t wps, int64_t n, int64_t M, int64_t mwp,
+                            uint64_t *hbits, hipStream_t s);
 hipError_t launch_site_stats(const uint64_t *bits, int64_t wps, int64_t n, int64_t M,
                              double maf_cutoff, int32_t nbins, double *freq,
                              int32_t *bin, uint8_t *walk_flag, int8_t *status,

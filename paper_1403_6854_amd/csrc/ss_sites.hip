@@ -32,6 +32,57 @@ __global__ void __launch_bounds__(kBlock) pack_kernel(const uint8_t *__restrict_
     if (lane == 0) bits[item] = word;
 }
 
+// Haplotype-major copy of the bit matrix for the pairwise phase of the walk:
+// row h holds haplotype h's alleles at every site, 64 sites per word, with
+// one zero word of padding on each side (word w covers sites 64(w-1) ..
+// 64(w-1)+63), so that any 64 consecutive sites are two neighbouring words.
+// One wave per (64-site block, 64-haplotype word): lane i loads the word of
+// site i of the block, and 64 ballots transpose the 64 x 64 bit block.
+__global__ void __launch_bounds__(kBlock) transpose_kernel(const uint64_t *__restrict__ bits,
+                                                           int64_t wps, int64_t n, int64_t M,
+                                                           int64_t mwp,
+                                                           uint64_t *__restrict__ hbits) {
+    const int lane = threadIdx.x & 63;
+    const int64_t words = (n + 63) / 64;
+    const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (item >= mwp * words) return;
+    const int64_t wp = item / words;          // padded block of 64 sites
+    const int64_t w = item - wp * words;      // word of 64 haplotypes
+    const int64_t site = (wp - 1) * 64 + lane;
+    const uint64_t v = (site >= 0 && site < M) ? bits[site * wps + w] : 0ull;
+    uint64_t out = 0ull;
+    for (int l = 0; l < 64; ++l) {
+        const uint64_t col = __ballot(((v >> l) & 1ull) != 0ull);
+        if (lane == l) out = col;
+    }
+    const int64_t h = w * 64 + lane;
+    if (h < n) hbits[h * mwp + wp] = out;
+}
+
+// Genetic length of every segment between neighbouring sites, with the gap
+// rules of Sec. 1.2 applied once per scan instead of once per walk step:
+// seg[k] is the length of the segment from site k-1 to site k, scaled by
+// gap_scale / b when its physical length b exceeds gap_scale, or -1 when
+// b > max_gap (the walk aborts there).  seg[0] is unused.
+__global__ void __launch_bounds__(kBlock) segment_kernel(int64_t M, const int64_t *__restrict__ pos,
+                                                         const double *__restrict__ gpos,
+                                                         int64_t gap_scale, int64_t max_gap,
+                                                         double *__restrict__ seg) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= M) return;
+    if (k == 0) {
+        seg[0] = -1.0;
+        return;
+    }
+    const int64_t b = pos[k] - pos[k - 1];
+    double g = -1.0;
+    if (b <= max_gap) {
+        g = gpos[k] - gpos[k - 1];
+        if (b > gap_scale) g = g * ((double)gap_scale / (double)b);
+    }
+    seg[k] = g;
+}
+
 // Per-site derived count n1, derived frequency, frequency bin, MAF filter
 // (Sec. 1.2: sites with MAF < cutoff are not scored) and the cores' sizes
 // (a core with fewer than two haplotypes leaves the score undefined).
@@ -89,7 +140,10 @@ __global__ void __launch_bounds__(kBlock) combine_kernel(
         }
         return;   // status already set by the site pass
     }
-    const int32_t sd = dstatus[2 * j], su = dstatus[2 * j + 1];
+    // a direction aborts if the walk of either core aborted (iHS walks may be
+    // split by core; joint walks write the same status to both slots)
+    const int32_t sd = dstatus[4 * j + 0] != ST_OK ? dstatus[4 * j + 0] : dstatus[4 * j + 1];
+    const int32_t su = dstatus[4 * j + 2] != ST_OK ? dstatus[4 * j + 2] : dstatus[4 * j + 3];
     int32_t st = sd != ST_OK ? sd : su;
     // slot 0 of a direction holds core 0 (iHS) or population A (XPEHH),
     // slot 1 holds core 1 or population B
@@ -238,6 +292,23 @@ hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps
     const int64_t blocks = (items + kBlock / 64 - 1) / (kBlock / 64);
     hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, alleles, n, M,
                        wps, bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_segments(int64_t M, const int64_t *pos, const double *gpos, int64_t gap_scale,
+                           int64_t max_gap, double *seg, hipStream_t s) {
+    const int64_t blocks = (M + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(segment_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, M, pos, gpos,
+                       gap_scale, max_gap, seg);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const uint64_t *bits, int64_t wps, int64_t n, int64_t M, int64_t mwp,
+                            uint64_t *hbits, hipStream_t s) {
+    const int64_t items = mwp * ((n + 63) / 64);
+    const int64_t blocks = (items + kBlock / 64 - 1) / (kBlock / 64);
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, bits, wps, n, M,
+                       mwp, hbits);
     return hipGetLastError();
 }
 

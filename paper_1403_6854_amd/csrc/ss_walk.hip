@@ -396,7 +396,8 @@ done:
         if (!TRACE) {
             a.ihh[o * 2 + 0] = ihh0;
             a.ihh[o * 2 + 1] = ihh1;
-            a.dstatus[o] = status;
+            a.dstatus[o * 2 + 0] = status;
+            a.dstatus[o * 2 + 1] = status;
             a.steps[o * 2 + 0] = steps0;
             a.steps[o * 2 + 1] = steps1;
         } else {

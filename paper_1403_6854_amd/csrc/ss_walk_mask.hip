@@ -1,28 +1,42 @@
-// EHH walk with the partition held as per-class haplotype bitmasks in
-// registers: one wave per (core site, direction), one class per lane (and
-// per slot when there can be more than 64 classes).  Used for haplotype
-// counts up to 512 (pooled, for XPEHH).
+// EHH walk with the partition held as haplotype bitmasks in registers, one
+// wave per walk, for walks over up to 512 haplotypes.
 //
 // What it computes is the same partition refinement as ss_walk.hip
 // (Sec. 1.1, Eqs. 1-3: classes of identical haplotypes from x0 out to x_i;
 // Sec. 1.2, Eq. 4 and the rules below it; Sec. 1.3, Eq. 7 for the pooled
-// walk of XPEHH); only the representation differs:
-//   * class c is a bitmask over the haplotypes (W 64-bit words, marker-major
-//     packing) held by lane c % 64 in slot c / 64.  Splitting a class by the
-//     alleles at marker k is an AND with row k and a popcount, so a marker
-//     costs a few VALU instructions per word for all classes at once, with no
-//     LDS traffic and no barrier;
+// walk of XPEHH); the representation is what differs:
+//   * a class is a bitmask over the haplotypes (W 64-bit words in the
+//     marker-major packing).  LPC lanes share one class, each holding
+//     W / LPC of its words, so a row of the wave holds 64 / LPC classes and
+//     rows are processed only while they hold classes.  Splitting a class by
+//     the alleles at marker k is an AND with row k and a popcount, summed
+//     over the class's lanes with DPP;
+//   * for iHS each core allele is walked by its own wave (the two cores never
+//     share a class, Eq. 2), so a wave carries only one core's classes; the
+//     locus-level rules are recombined afterwards: a direction aborts if a
+//     walk of either core aborted, which is exactly when the joint walk would
+//     have met the end of the data or the gap while that core was active;
 //   * the child with the allele-1 members stays in place if it has >= 2
-//     members, else the allele-0 child; when both children survive, the
-//     second one is appended through LDS (a rare event once the first few
-//     markers have separated the founder groups);
-//   * the stop test EHH_c = S_c / C(n_c,2) < cutoff is evaluated on integers:
+//     members, else the allele-0 child; when both survive, the second one is
+//     appended through LDS (rare once the first markers have separated the
+//     founder groups); children with < 2 members are dropped for good;
+//   * the stop test EHH = S / C(n,2) < cutoff is evaluated on integers:
 //     correctly rounded division is monotone in S, so fl(S/P) < cutoff holds
 //     exactly for S <= thr, with thr found once per walk by testing 64
 //     candidates around cutoff * P with the same IEEE division;
 //   * the FP64 trapezoid terms of 64 markers are formed lane-parallel after
 //     the markers have been refined, and added to iHH one by one in marker
-//     order, so the sums round exactly as the definition's left-to-right sum.
+//     order, so the sums round exactly as the definition's left-to-right sum;
+//   * pairwise phase (iHS walks): sum_h C(n_h, 2) counts the pairs of
+//     haplotypes still identical from x0 to x_i.  Once that count S is at most
+//     kPairCap, the classes are expanded into an explicit list of those pairs
+//     in LDS, and each pass then covers 64 markers: a pair's 64-bit keys
+//     (its haplotypes' alleles at the next 64 markers, read from a
+//     haplotype-major copy of the matrix) are XORed, the lowest set bit is
+//     the marker where the pair splits, a 64-bin histogram of those markers
+//     gives S at each of the 64 markers, and the surviving pairs are compacted
+//     in place.  Long walks then cost a few instructions per pair per 64
+//     markers instead of a full refinement per marker.
 #include "ss_internal.hpp"
 
 namespace ss {
@@ -33,11 +47,6 @@ __device__ __forceinline__ uint32_t choose2(uint32_t x) { return (x * (x - 1u)) 
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return __ockl_wfred_add_u32(v); }
 
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int i) {
     const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, i);
     const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), i);
@@ -46,6 +55,29 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int i) {
 
 __device__ __forceinline__ double readlane_f64(double v, int i) {
     return __builtin_bit_cast(double, readlane64(__builtin_bit_cast(uint64_t, v), i));
+}
+
+// Sum of v over the LPC consecutive lanes of a class (LPC = 1, 2, 4 or 8).
+template <int LPC>
+__device__ __forceinline__ uint32_t group_sum(uint32_t v) {
+    if (LPC >= 2) v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    if (LPC >= 4) v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    if (LPC >= 8) v += (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);             // lane ^ 4
+    return v;
+}
+
+// Pairs the pairwise phase keeps in LDS (4 KB; LDS per wave bounds how
+// many walks a CU keeps in flight).
+constexpr int kPairCap = 1024;
+
+// Inclusive prefix sum over the 64 lanes (once per 64-marker pass).
+__device__ __forceinline__ uint32_t wave_prefix(uint32_t v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
 }
 
 // Largest S in [0, P] with (double)S / (double)P < cutoff (P >= 1), found by
@@ -62,369 +94,559 @@ __device__ __forceinline__ uint32_t stop_threshold(uint32_t P, double cutoff, in
     return (uint32_t)__builtin_amdgcn_readlane((uint32_t)s, top);
 }
 
-// Class record in the staging area for appends and compaction: W mask words
-// followed by one word holding countA | countB << 16 | core << 31.
-template <int W>
-struct Staging {
-    uint64_t *base;
-    __device__ uint64_t *at(int c) const { return base + (size_t)c * (W + 1); }
-};
-
-template <int MODE, int W, int NS>
+// W: mask words per class (pooled: A's words, then B's); LPC: lanes per
+// class; NR: rows of 64 / LPC classes (capacity NR * 64 / LPC classes).
+template <int MODE, int W, int LPC, int NR>
 __global__ void __launch_bounds__(64) mask_walk_kernel(WalkArgs a) {
+    constexpr int WPL = W / LPC;    // words per lane
+    constexpr int CPR = 64 / LPC;   // classes per row
+    constexpr int PCAP = MODE == MODE_CORE ? kPairCap : 0;
     extern __shared__ uint64_t lds64[];
+    // LDS regions; the pairwise phase stages no rows and compacts no classes,
+    // so its buffers share space with those of the per-marker phase.
+    constexpr int kStageWords = NR * CPR * (W + 1);
+    constexpr int kUnionWords = kStageWords > PCAP / 2 ? kStageWords : PCAP / 2;
+    uint64_t *rowbuf = lds64;                  // [64][W] rows of the staged markers
+    uint64_t *keys = rowbuf;                   // [64 W] 64-marker keys (pairwise phase)
+    uint16_t *mem = (uint16_t *)rowbuf;        // [64 W] members of one class (pair-list build)
+    uint64_t *stage = rowbuf + 64 * W;         // [NR * CPR][W + 1] class records
+    uint32_t *pairs = (uint32_t *)stage;       // [PCAP] a | b << 16 (pairwise phase)
+    uint32_t *hist = (uint32_t *)(stage + kUnionWords);   // [64] splits per marker
+
     const int lane = threadIdx.x;
+    const int q = lane / LPC;     // class slot within a row
+    const int g = lane % LPC;     // word group within the class
+    const bool leader = g == 0;
     const int d = blockIdx.y;
     const int dir = d == 0 ? 1 : -1;
+    const int core = blockIdx.z;  // CORE mode: the allele whose carriers this wave walks
     const int64_t j = a.site0 + (int64_t)blockIdx.x;
     if (j >= a.M) return;
     if (a.walk_flag && !a.walk_flag[j]) return;
-    const Staging<W> stage{lds64};
-    const int WA = a.WA;
+    const int Wused = MODE == MODE_CORE ? a.WA : a.WA + a.WB;
 
-    // Word w of the pooled row at site k (A's words, then B's).
+    auto is_a = [&](int w) -> bool { return MODE == MODE_CORE || w < a.WA; };
     auto rowword = [&](int w, int64_t k) -> uint64_t {
-        return w < WA ? a.bitsA[k * a.wpsA + w] : a.bitsB[k * a.wpsB + (w - WA)];
+        if (w >= Wused) return 0ull;
+        return is_a(w) ? a.bitsA[k * a.wpsA + w] : a.bitsB[k * a.wpsB + (w - a.WA)];
     };
     auto validmask = [&](int w) -> uint64_t {
-        const int nv = w < WA ? a.nA - 64 * w : a.nB - 64 * (w - WA);
+        if (w >= Wused) return 0ull;
+        const int nv = is_a(w) ? a.nA - 64 * w : a.nB - 64 * (w - a.WA);
         return nv >= 64 ? ~0ull : (nv <= 0 ? 0ull : ((1ull << nv) - 1ull));
     };
 
-    // ---- classes at x0: lane 0 = allele 0, lane 1 = allele 1 --------------
-    uint64_t m[NS][W];
-    uint32_t ca[NS], cb[NS], cr[NS];   // counts in A and B, core allele (CORE mode)
+    // ---- classes at x0 ------------------------------------------------------
+    // CORE: one class, the carriers of `core`.  POOLED: allele 0 and allele 1.
+    uint64_t m[NR][WPL];
+    uint32_t ca[NR], cb[NR];   // class counts in A and B (replicated over the LPC lanes)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        ca[s] = cb[s] = cr[s] = 0u;
+    for (int r = 0; r < NR; ++r) {
+        ca[r] = cb[r] = 0u;
 #pragma unroll
-        for (int w = 0; w < W; ++w) m[s][w] = 0ull;
+        for (int t = 0; t < WPL; ++t) m[r][t] = 0ull;
     }
     uint32_t n0a = 0, n0b = 0, n1a = 0, n1b = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-        const uint64_t r = rowword(w, j) & validmask(w);
-        const uint64_t z = ~r & validmask(w);
-        if (lane == 0) m[0][w] = z;
-        if (lane == 1) m[0][w] = r;
-        if (w < WA) { n0a += __popcll(z); n1a += __popcll(r); }
-        else        { n0b += __popcll(z); n1b += __popcll(r); }
+        const uint64_t r1 = rowword(w, j) & validmask(w);
+        const uint64_t r0 = ~r1 & validmask(w);
+        if (is_a(w)) { n0a += __popcll(r0); n1a += __popcll(r1); }
+        else         { n0b += __popcll(r0); n1b += __popcll(r1); }
+        if (w / WPL == g) {
+            const int t = w % WPL;
+            if (MODE == MODE_CORE) {
+                if (q == 0) m[0][t] = core ? r1 : r0;
+            } else {
+                if (q == 0) m[0][t] = r0;
+                if (q == 1) m[0][t] = r1;
+            }
+        }
     }
-    if (lane == 0) { ca[0] = n0a; cb[0] = n0b; cr[0] = 0u; }
-    if (lane == 1) { ca[0] = n1a; cb[0] = n1b; cr[0] = 1u; }
-    if (lane < 2 && ca[0] + cb[0] < 2u) { ca[0] = cb[0] = 0u; }
-    int kend = 2;   // class indices in use (uniform)
+    int kend;
+    if (MODE == MODE_CORE) {
+        const uint32_t nc = core ? n1a : n0a;
+        if (q == 0) ca[0] = nc >= 2u ? nc : 0u;
+        kend = 1;
+    } else {
+        if (q == 0) { ca[0] = n0a; cb[0] = n0b; }
+        if (q == 1) { ca[0] = n1a; cb[0] = n1b; }
+        if (q < 2 && ca[0] + cb[0] < 2u) ca[0] = cb[0] = 0u;
+        kend = 2;
+    }
+
+    // ---- staging of 64-marker batches ------------------------------------------
+    // Lane i fetches step i of a batch: its row words (per-marker phase only)
+    // and its segment's genetic length.  The next batch is fetched while the
+    // current one is processed, so the loads' latency overlaps the work.
+    auto fetch = [&](int st, bool rows, uint64_t (&rv)[W], double &sv, bool &inr) {
+        const int64_t kb = j + (int64_t)dir * (int64_t)(st + 1 + lane);
+        inr = kb >= 0 && kb < a.M;
+#pragma unroll
+        for (int w = 0; w < W; ++w) rv[w] = (rows && inr) ? rowword(w, kb) : 0ull;
+        if (!inr) {
+            sv = 0.0;
+        } else if (a.seg) {
+            sv = a.seg[dir > 0 ? kb : kb + 1];
+        } else {
+            const int64_t lo = dir > 0 ? kb - 1 : kb;
+            const int64_t b = a.pos[lo + 1] - a.pos[lo];
+            double gg = -1.0;
+            if (b <= a.max_gap) {
+                gg = a.gpos[lo + 1] - a.gpos[lo];
+                if (b > a.gap_scale) gg = gg * ((double)a.gap_scale / (double)b);
+            }
+            sv = gg;
+        }
+    };
+    uint64_t pf_rows[W];
+    double pf_seg;
+    bool pf_inr;
+    int pf_step = 0;
+    fetch(0, true, pf_rows, pf_seg, pf_inr);
 
     // ---- per-walk constants -------------------------------------------------
-    // Per-class sums are reduced once per marker: two 16-bit fields in one
-    // 32-bit lane value when every sum fits (C(n,2) < 2^16), else two values.
-    bool act0, act1;
-    uint32_t thr0 = 0, thr1 = 0, thrP = 0;
-    double P0, P1, ep0, ep1;
-    bool pack16;
+    // CORE: one statistic S = sum over the classes of C(n_h, 2), EHH = S / P.
+    // POOLED: S_A and S_B (16-bit fields of one value when they fit) and
+    // S_pool, which alone decides where the walk stops.
+    bool act;
+    uint32_t thr;
+    double PA, PB = 1.0, epA, epB = 0.0;
+    bool pack16 = true;
     if (MODE == MODE_CORE) {
-        P0 = (double)choose2(n0a);
-        P1 = (double)choose2(n1a);
-        act0 = n0a >= 2u;
-        act1 = n1a >= 2u;
-        if (act0) thr0 = stop_threshold(choose2(n0a), a.cutoff, lane);
-        if (act1) thr1 = stop_threshold(choose2(n1a), a.cutoff, lane);
-        ep0 = 1.0;
-        ep1 = 1.0;
-        pack16 = choose2(n0a) < 65536u && choose2(n1a) < 65536u;
+        const uint32_t nc = core ? n1a : n0a;
+        PA = (double)choose2(nc);
+        act = nc >= 2u;
+        thr = act ? stop_threshold(choose2(nc), a.cutoff, lane) : 0u;
+        epA = 1.0;
     } else {
-        P0 = (double)choose2((uint32_t)a.nA);
-        P1 = (double)choose2((uint32_t)a.nB);
-        thrP = stop_threshold(choose2((uint32_t)(a.nA + a.nB)), a.cutoff, lane);
-        ep0 = (double)(choose2(n0a) + choose2(n1a)) / P0;
-        ep1 = (double)(choose2(n0b) + choose2(n1b)) / P1;
-        act0 = true;
-        act1 = false;
+        PA = (double)choose2((uint32_t)a.nA);
+        PB = (double)choose2((uint32_t)a.nB);
+        thr = stop_threshold(choose2((uint32_t)(a.nA + a.nB)), a.cutoff, lane);
+        // x0 is part of the haplotype: each population's curve starts at its
+        // whole-sample EHH at x0
+        epA = (double)(choose2(n0a) + choose2(n1a)) / PA;
+        epB = (double)(choose2(n0b) + choose2(n1b)) / PB;
+        act = true;
         pack16 = choose2((uint32_t)a.nA) < 65536u && choose2((uint32_t)a.nB) < 65536u;
     }
-    double ihh0 = 0.0, ihh1 = 0.0;
-    int32_t steps0 = 0, steps1 = 0;
+    double ihhA = 0.0, ihhB = 0.0;
+    int32_t steps = 0;
     int32_t status = ST_OK;
     int step = 0;
 
-    // Write every live class (and the second child of every split) to LDS at
-    // dense indices and read them back: live classes first, then the children.
-    auto compact = [&](const bool (&split)[NS], const uint64_t (&zm)[NS][W],
-                       const uint32_t (&za)[NS], const uint32_t (&zb)[NS]) {
+    // Dense re-indexing of the live classes through LDS, with the second
+    // child of every split appended after them.
+    auto compact = [&](const bool (&split)[NR], const uint64_t (&zm)[NR][WPL],
+                       const uint32_t (&za)[NR], const uint32_t (&zb)[NR]) {
+        const uint64_t below_group = (q == 0) ? 0ull : ((1ull << (q * LPC)) - 1ull);
         int nlive = 0;
-        int offs[NS];
+        int at[NR];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const uint64_t lm = __ballot(ca[s] + cb[s] >= 2u);
-            offs[s] = nlive + (int)lanes_below(lm);
+        for (int r = 0; r < NR; ++r) {
+            const uint64_t lm = __ballot(leader && ca[r] + cb[r] >= 2u);
+            at[r] = nlive + __popcll(lm & below_group);
             nlive += __popcll(lm);
         }
         int nsp = nlive;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            if (ca[s] + cb[s] >= 2u) {
-                uint64_t *e = stage.at(offs[s]);
+        for (int r = 0; r < NR; ++r) {
+            if (ca[r] + cb[r] >= 2u) {
+                uint64_t *e = stage + (size_t)at[r] * (W + 1);
 #pragma unroll
-                for (int w = 0; w < W; ++w) e[w] = m[s][w];
-                e[W] = (uint64_t)(ca[s] | (cb[s] << 16) | (cr[s] << 31));
+                for (int t = 0; t < WPL; ++t) e[g * WPL + t] = m[r][t];
+                if (leader) e[W] = (uint64_t)(ca[r] | (cb[r] << 16));
             }
-            const uint64_t sm = __ballot(split[s]);
-            if (split[s]) {
-                uint64_t *e = stage.at(nsp + (int)lanes_below(sm));
+            const uint64_t sm = __ballot(leader && split[r]);
+            if (split[r]) {
+                uint64_t *e = stage + (size_t)(nsp + __popcll(sm & below_group)) * (W + 1);
 #pragma unroll
-                for (int w = 0; w < W; ++w) e[w] = zm[s][w];
-                e[W] = (uint64_t)(za[s] | (zb[s] << 16) | (cr[s] << 31));
+                for (int t = 0; t < WPL; ++t) e[g * WPL + t] = zm[r][t];
+                if (leader) e[W] = (uint64_t)(za[r] | (zb[r] << 16));
             }
             nsp += __popcll(sm);
         }
         __syncthreads();
         kend = nsp;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int c = 64 * s + lane;
+        for (int r = 0; r < NR; ++r) {
+            const int c = r * CPR + q;
             if (c < kend) {
-                const uint64_t *e = stage.at(c);
+                const uint64_t *e = stage + (size_t)c * (W + 1);
 #pragma unroll
-                for (int w = 0; w < W; ++w) m[s][w] = e[w];
+                for (int t = 0; t < WPL; ++t) m[r][t] = e[g * WPL + t];
                 const uint32_t x = (uint32_t)e[W];
-                ca[s] = x & 0xFFFFu;
-                cb[s] = (x >> 16) & 0x7FFFu;
-                cr[s] = x >> 31;
+                ca[r] = x & 0xFFFFu;
+                cb[r] = x >> 16;
             } else {
-                ca[s] = cb[s] = 0u;
+                ca[r] = cb[r] = 0u;
             }
         }
         __syncthreads();
     };
 
-    while (act0 || act1) {
-        // ---- lane i stages step i of the next 64: its row words (read back
-        // with readlane, so no memory latency sits on the per-marker chain)
-        // and its segment: end of data, abort gap, or scaled genetic length
-        const int64_t kb = j + (int64_t)dir * (int64_t)(step + 1 + lane);
-        const bool inr = kb >= 0 && kb < a.M;
-        uint64_t rowv[W];
+    // ---- pairwise phase -------------------------------------------------------
+    bool pmode = false;
+    int npairs = 0;
+    uint32_t s_now = 0;   // S after the last marker processed
+    if (MODE == MODE_CORE) s_now = choose2(core ? n1a : n0a);
+    const bool can_pair = PCAP > 0 && a.hbits != nullptr;
+
+    // Expand the live classes into the list of their member pairs; the class
+    // masks are read from the registers of the lanes holding them.
+    auto build_pairs = [&]() {
+        npairs = 0;
+        for (int c = 0; c < kend; ++c) {
+            const int rr = c / CPR, qq = c % CPR;
+            uint32_t cnt = 0;
 #pragma unroll
-        for (int w = 0; w < W; ++w) rowv[w] = inr ? rowword(w, kb) : 0ull;
+            for (int r = 0; r < NR; ++r)
+                if (r == rr) cnt = __builtin_amdgcn_readlane(ca[r], qq * LPC);
+            if (cnt < 2u) continue;   // an empty slot left by a class that died
+            int sz = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                uint64_t mw = 0;
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    if (r == rr) mw = readlane64(m[r][w % WPL], qq * LPC + w / WPL);
+                const uint64_t below = lane ? (mw & ((1ull << lane) - 1ull)) : 0ull;
+                if ((mw >> lane) & 1ull) mem[sz + __popcll(below)] = (uint16_t)(64 * w + lane);
+                sz += __popcll(mw);
+            }
+            __syncthreads();
+            for (int y = 1; y < sz; ++y) {
+                const uint32_t my = mem[y];
+                const int base = npairs + y * (y - 1) / 2;
+                for (int x0 = 0; x0 < y; x0 += 64) {
+                    const int x = x0 + lane;
+                    if (x < y) pairs[base + x] = (uint32_t)mem[x] | (my << 16);
+                }
+            }
+            npairs += sz * (sz - 1) / 2;
+            __syncthreads();
+        }
+    };
+
+    // Alleles of haplotype h at the 64 markers from k0 onwards in the walk's
+    // direction, bit i = marker k0 + dir * i.
+    auto key_of = [&](int h, int64_t k0) -> uint64_t {
+        const uint64_t *row = a.hbits + (size_t)h * a.mwp;
+        const int64_t b = dir > 0 ? k0 + 64 : k0 + 1;   // padded index of the lowest marker
+        const int64_t wi = b >> 6;
+        const int sh = (int)(b & 63);
+        const uint64_t lo = wi < a.mwp ? row[wi] : 0ull;
+        const uint64_t hi = wi + 1 < a.mwp ? row[wi + 1] : 0ull;
+        const uint64_t x = sh ? ((lo >> sh) | (hi << (64 - sh))) : lo;
+        return dir > 0 ? x : __builtin_bitreverse64(x);
+    };
+
+    if (can_pair && act && s_now <= (uint32_t)PCAP) {
+        build_pairs();
+        pmode = true;
+    }
+
+    while (act) {
+        // Long walks decide how long a whole scan takes: once a walk has gone
+        // past a few hundred markers its wave takes issue priority over the
+        // short walks sharing its SIMD.
+        if (step >= 384) __builtin_amdgcn_s_setprio(3);
+        else if (step >= 256) __builtin_amdgcn_s_setprio(2);
+        else if (step >= 128) __builtin_amdgcn_s_setprio(1);
+
+        // ---- lane i holds step i of the next 64: its row words go to LDS,
+        // its segment (end of data, abort gap, or scaled genetic length)
+        // stays in registers for the FP64 pass
+        if (pf_step != step) fetch(step, !pmode, pf_rows, pf_seg, pf_inr);
+        if (!pmode) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) rowbuf[lane * W + w] = pf_rows[w];
+        }
+        const bool inr = pf_inr;
+        const double segv = pf_seg;
+        fetch(step + 64, !pmode, pf_rows, pf_seg, pf_inr);   // next batch, if the walk goes on
+        pf_step = step + 64;
         int32_t stl = ST_OK;
         double gl = 0.0;
-        if (!inr) {
-            stl = ST_EDGE;
-        } else {
-            const int64_t lo = dir > 0 ? kb - 1 : kb;
-            const int64_t b = a.pos[lo + 1] - a.pos[lo];
-            if (b > a.max_gap) {
-                stl = ST_GAP;
-            } else {
-                double g = a.gpos[lo + 1] - a.gpos[lo];
-                if (b > a.gap_scale) g = g * ((double)a.gap_scale / (double)b);
-                gl = g;
-            }
-        }
+        if (!inr) stl = ST_EDGE;
+        else if (segv < 0.0) stl = ST_GAP;
+        else gl = segv;
         const uint64_t abort_mask = __ballot(stl != ST_OK);
         const int nb = abort_mask ? (int)__builtin_ctzll(abort_mask) : 64;
         const int32_t abort_st = abort_mask ? (int32_t)__builtin_amdgcn_readlane(stl, nb) : ST_OK;
+        __syncthreads();
 
-        // per-step sums of this batch: lane i holds step i's values
-        uint32_t sbA = 0, sbB = 0, sbP = 0;
-        const bool was0 = act0, was1 = act1;
-        int nterm0 = 0, nterm1 = 0;   // trapezoid terms added in this batch
+        uint32_t sb = 0, sbB = 0;   // lane i: step i's S (A|B packed, or A) and S_B
+        int nterm = 0;              // trapezoid terms of this batch
         int i = 0;
-        for (; i < 64 && (act0 || act1); ++i) {
-            if (i == nb) { status = abort_st; break; }
-            uint64_t r[W];
+        bool to_pairs = false;
+        if (pmode) {
+            // ---- one pass over the pair list covers the next 64 markers ----
+            const int64_t k0 = j + (int64_t)dir * (int64_t)(step + 1);
+            for (int h = lane; h < a.nA; h += 64) keys[h] = key_of(h, k0);
+            hist[lane] = 0u;
+            __syncthreads();
+            int wpos = 0;
+            for (int p0 = 0; p0 < npairs; p0 += 64) {
+                const int p = p0 + lane;
+                const bool in = p < npairs;
+                const uint32_t pr = in ? pairs[p] : 0u;
+                const uint64_t x = keys[pr & 0xFFFFu] ^ keys[pr >> 16];
+                const int L = x ? (int)__builtin_ctzll(x) : 64;
+                if (in && L < 64) atomicAdd(&hist[L], 1u);
+                const bool surv = in && L == 64;
+                const uint64_t sm = __ballot(surv);
+                const uint64_t below = lane ? (sm & ((1ull << lane) - 1ull)) : 0ull;
+                if (surv) pairs[wpos + __popcll(below)] = pr;   // wpos <= p0: in place
+                wpos += __popcll(sm);
+            }
+            __syncthreads();
+            const uint32_t si = s_now - wave_prefix(hist[lane], lane);   // S after step `lane`
+            const uint64_t valid = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+            const uint64_t stopm = __ballot(si <= thr) & valid;
+            if (stopm) {
+                i = (int)__builtin_ctzll(stopm) + 1;
+                nterm = i - 1;
+                act = false;
+            } else if (nb < 64) {
+                i = nb;
+                nterm = nb;
+                status = abort_st;
+            } else {
+                i = 64;
+                nterm = 64;
+            }
+            steps += i;
+            sb = si;
+            s_now = (uint32_t)__builtin_amdgcn_readlane(si, 63);
+            npairs = wpos;
+            __syncthreads();
+        } else {
+        uint64_t rn[WPL];
 #pragma unroll
-            for (int w = 0; w < W; ++w) r[w] = readlane64(rowv[w], i);
+        for (int t = 0; t < WPL; ++t) rn[t] = rowbuf[g * WPL + t];
+        for (; i < 64 && act; ++i) {
+            if (i == nb) { status = abort_st; break; }
+            uint64_t rw[WPL];
+#pragma unroll
+            for (int t = 0; t < WPL; ++t) rw[t] = rn[t];
+            if (i + 1 < 64) {
+#pragma unroll
+                for (int t = 0; t < WPL; ++t) rn[t] = rowbuf[(i + 1) * W + g * WPL + t];
+            }
 
-            uint32_t accA = 0, accB = 0, accP = 0;
-            bool split[NS];
-            uint64_t zm[NS][W];
-            uint32_t za[NS], zb[NS];
+            uint32_t acc = 0, accB = 0, accP = 0;
+            bool split[NR];
+            uint64_t zm[NR][WPL];
+            uint32_t za[NR], zb[NR];
             uint64_t anysplit = 0;
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                split[s] = false;
-                za[s] = zb[s] = 0u;
-                if (64 * s >= kend) continue;   // uniform
-                uint32_t oa = 0, ob = 0;
-                uint64_t m1[W];
+            for (int r = 0; r < NR; ++r) {
+                split[r] = false;
+                za[r] = zb[r] = 0u;
+                if (r * CPR >= kend) continue;   // uniform
+                uint32_t ow = 0;                 // ones in my words, A | B << 16
+                uint64_t m1[WPL];
 #pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    m1[w] = m[s][w] & r[w];
-                    zm[s][w] = m[s][w] & ~r[w];
-                    if (w < WA) oa += __popcll(m1[w]);
-                    else        ob += __popcll(m1[w]);
+                for (int t = 0; t < WPL; ++t) {
+                    m1[t] = m[r][t] & rw[t];
+                    zm[r][t] = m[r][t] & ~rw[t];
+                    const uint32_t pc = (uint32_t)__popcll(m1[t]);
+                    ow += is_a(g * WPL + t) ? pc : (pc << 16);
                 }
-                const uint32_t zA = ca[s] - oa, zB = cb[s] - ob;
+                const uint32_t os = group_sum<LPC>(ow);
+                const uint32_t oa = os & 0xFFFFu, ob = os >> 16;
+                const uint32_t zA = ca[r] - oa, zB = cb[r] - ob;
+                const bool live = ca[r] + cb[r] >= 2u;
                 bool ko, kz;
                 if (MODE == MODE_CORE) {
-                    const bool live = ca[s] >= 2u && (cr[s] ? act1 : act0);
-                    const uint32_t sc = live ? choose2(oa) + choose2(zA) : 0u;
-                    if (pack16) {
-                        accA += sc << (16u * cr[s]);
-                    } else {
-                        accA += cr[s] ? 0u : sc;
-                        accB += cr[s] ? sc : 0u;
-                    }
+                    if (leader && live) acc += choose2(oa) + choose2(zA);
                     ko = live && oa >= 2u;
                     kz = live && zA >= 2u;
                 } else {
-                    const bool live = ca[s] + cb[s] >= 2u;
-                    if (live) {
+                    if (leader && live) {
                         const uint32_t sa = choose2(oa) + choose2(zA);
-                        const uint32_t sb = choose2(ob) + choose2(zB);
+                        const uint32_t sbv = choose2(ob) + choose2(zB);
                         if (pack16) {
-                            accA += sa | (sb << 16);
+                            acc += sa | (sbv << 16);
                         } else {
-                            accA += sa;
-                            accB += sb;
+                            acc += sa;
+                            accB += sbv;
                         }
                         accP += choose2(oa + ob) + choose2(zA + zB);
                     }
                     ko = live && oa + ob >= 2u;
                     kz = live && zA + zB >= 2u;
                 }
-                split[s] = ko && kz;
-                // the allele-1 child stays if it survives, else the allele-0
-                // child; a class with no surviving child becomes empty
+                split[r] = ko && kz;
 #pragma unroll
-                for (int w = 0; w < W; ++w) m[s][w] = ko ? m1[w] : zm[s][w];
-                za[s] = zA;
-                zb[s] = zB;
-                ca[s] = ko ? oa : (kz ? zA : 0u);
-                cb[s] = ko ? ob : (kz ? zB : 0u);
-                anysplit |= __ballot(split[s]);
+                for (int t = 0; t < WPL; ++t) m[r][t] = ko ? m1[t] : zm[r][t];
+                za[r] = zA;
+                zb[r] = zB;
+                ca[r] = ko ? oa : (kz ? zA : 0u);
+                cb[r] = ko ? ob : (kz ? zB : 0u);
+                anysplit |= __ballot(leader && split[r]);
             }
-            uint32_t SA, SB, SP = 0u;
-            if (pack16) {
-                const uint32_t t = wave_sum(accA);
-                SA = t & 0xFFFFu;
-                SB = t >> 16;
-            } else {
-                SA = wave_sum(accA);
-                SB = wave_sum(accB);
+            const uint32_t S = wave_sum(acc);
+            uint32_t SB = 0u, SP = 0u;
+            if (MODE == MODE_POOLED) {
+                SP = wave_sum(accP);
+                if (!pack16) SB = wave_sum(accB);
             }
-            if (MODE == MODE_POOLED) SP = wave_sum(accP);
-
             if (anysplit) {
                 compact(split, zm, za, zb);
-            } else if (NS > 1 && kend > 64 && (i & 7) == 7) {
+            } else if (NR > 1 && kend > CPR && (i & 7) == 7) {
                 // reclaim the holes left by classes that died, so that the
-                // upper slots stop being processed once they are empty
-                bool none[NS];
+                // upper rows stop being processed once they are empty
+                bool none[NR];
 #pragma unroll
-                for (int s = 0; s < NS; ++s) none[s] = false;
+                for (int r = 0; r < NR; ++r) none[r] = false;
                 compact(none, zm, za, zb);
             }
 
             // ---- record the step's sums and apply the stop rule -----------
-            if (lane == i) { sbA = SA; sbB = SB; sbP = SP; }
-            if (MODE == MODE_CORE) {
-                if (act0) {
-                    steps0 += 1;
-                    if (SA <= thr0) act0 = false; else nterm0 = i + 1;
-                }
-                if (act1) {
-                    steps1 += 1;
-                    if (SB <= thr1) act1 = false; else nterm1 = i + 1;
-                }
-            } else {
-                steps0 += 1;
-                if (SP <= thrP) act0 = false; else nterm0 = i + 1;
+            if (lane == i) { sb = S; sbB = SB; }
+            steps += 1;
+            const uint32_t Sst = MODE == MODE_CORE ? S : SP;
+            if (Sst <= thr) act = false; else nterm = i + 1;
+            s_now = S;
+            if (can_pair && act && S <= (uint32_t)PCAP) {
+                to_pairs = true;   // continue pairwise after this marker
+                ++i;
+                break;
             }
+        }
         }
         step += i;
 
         // ---- FP64 trapezoid of this batch: terms lane-parallel, sum in order
-        const double g = gl;
-        if (MODE == MODE_CORE) {
-            if (was0 && nterm0 > 0) {
-                const double e = (double)sbA / P0;
+        if (nterm > 0) {
+            const double g64 = gl;
+            if (MODE == MODE_CORE) {
+                const double e = (double)sb / PA;
                 double prev = __shfl_up(e, 1, 64);
-                if (lane == 0) prev = ep0;
-                const double term = 0.5 * (prev + e) * g;
-                for (int q = 0; q < nterm0; ++q) ihh0 += readlane_f64(term, q);
-                ep0 = readlane_f64(e, nterm0 - 1);
+                if (lane == 0) prev = epA;
+                const double term = 0.5 * (prev + e) * g64;
+                for (int t = 0; t < nterm; ++t) ihhA += readlane_f64(term, t);
+                epA = readlane_f64(e, nterm - 1);
+            } else {
+                const uint32_t sA = pack16 ? (sb & 0xFFFFu) : sb;
+                const uint32_t sB = pack16 ? (sb >> 16) : sbB;
+                const double eA = (double)sA / PA;
+                const double eB = (double)sB / PB;
+                double pA = __shfl_up(eA, 1, 64);
+                double pB = __shfl_up(eB, 1, 64);
+                if (lane == 0) { pA = epA; pB = epB; }
+                const double tA = 0.5 * (pA + eA) * g64;
+                const double tB = 0.5 * (pB + eB) * g64;
+                for (int t = 0; t < nterm; ++t) {
+                    ihhA += readlane_f64(tA, t);
+                    ihhB += readlane_f64(tB, t);
+                }
+                epA = readlane_f64(eA, nterm - 1);
+                epB = readlane_f64(eB, nterm - 1);
             }
-            if (was1 && nterm1 > 0) {
-                const double e = (double)sbB / P1;
-                double prev = __shfl_up(e, 1, 64);
-                if (lane == 0) prev = ep1;
-                const double term = 0.5 * (prev + e) * g;
-                for (int q = 0; q < nterm1; ++q) ihh1 += readlane_f64(term, q);
-                ep1 = readlane_f64(e, nterm1 - 1);
-            }
-        } else if (nterm0 > 0) {
-            const double eA = (double)sbA / P0;
-            const double eB = (double)sbB / P1;
-            double pA = __shfl_up(eA, 1, 64);
-            double pB = __shfl_up(eB, 1, 64);
-            if (lane == 0) { pA = ep0; pB = ep1; }
-            const double tA = 0.5 * (pA + eA) * g;
-            const double tB = 0.5 * (pB + eB) * g;
-            for (int q = 0; q < nterm0; ++q) {
-                ihh0 += readlane_f64(tA, q);
-                ihh1 += readlane_f64(tB, q);
-            }
-            ep0 = readlane_f64(eA, nterm0 - 1);
-            ep1 = readlane_f64(eB, nterm0 - 1);
         }
         if (status != ST_OK) break;
+        __syncthreads();   // the next batch overwrites the staged rows
+        if (to_pairs) {
+            build_pairs();
+            pmode = true;
+        }
     }
 
     if (lane == 0) {
         const size_t o = (size_t)j * 2 + d;
-        a.ihh[o * 2 + 0] = ihh0;
-        a.ihh[o * 2 + 1] = ihh1;
-        a.dstatus[o] = status;
-        a.steps[o * 2 + 0] = steps0;
-        a.steps[o * 2 + 1] = steps1;
+        if (MODE == MODE_CORE) {
+            a.ihh[o * 2 + core] = ihhA;
+            a.dstatus[o * 2 + core] = status;
+            a.steps[o * 2 + core] = steps;
+        } else {
+            a.ihh[o * 2 + 0] = ihhA;
+            a.ihh[o * 2 + 1] = ihhB;
+            a.dstatus[o * 2 + 0] = status;
+            a.dstatus[o * 2 + 1] = status;
+            a.steps[o * 2 + 0] = steps;
+            a.steps[o * 2 + 1] = 0;
+        }
     }
 }
 
-template <int MODE, int W>
-hipError_t launch_ns(const WalkArgs &a, int ns, int64_t n_blocks, hipStream_t s) {
-    dim3 grid((unsigned)n_blocks, 2u, 1u);
-    const size_t lds = (size_t)64 * ns * (W + 1) * sizeof(uint64_t);
-    switch (ns) {
-        case 1: hipLaunchKernelGGL((mask_walk_kernel<MODE, W, 1>), grid, dim3(64), lds, s, a); break;
-        case 2: hipLaunchKernelGGL((mask_walk_kernel<MODE, W, 2>), grid, dim3(64), lds, s, a); break;
-        case 4: hipLaunchKernelGGL((mask_walk_kernel<MODE, W, 4>), grid, dim3(64), lds, s, a); break;
+template <int MODE, int W, int LPC>
+hipError_t launch_nr(const WalkArgs &a, int nr, size_t lds, int64_t n_blocks, hipStream_t s) {
+    dim3 grid((unsigned)n_blocks, 2u, MODE == MODE_CORE ? 2u : 1u);
+    switch (nr) {
+        case 1: hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 1>), grid, dim3(64), lds, s, a); break;
+        case 2: hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 2>), grid, dim3(64), lds, s, a); break;
+        case 4: hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 4>), grid, dim3(64), lds, s, a); break;
+        case 8: hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 8>), grid, dim3(64), lds, s, a); break;
+        case 16: hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 16>), grid, dim3(64), lds, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int MODE>
-hipError_t launch_w(const WalkArgs &a, int words, int ns, int64_t n_blocks, hipStream_t s) {
-    switch (words) {
-        case 1: return launch_ns<MODE, 1>(a, ns, n_blocks, s);
-        case 2: return launch_ns<MODE, 2>(a, ns, n_blocks, s);
-        case 3: return launch_ns<MODE, 3>(a, ns, n_blocks, s);
-        case 4: return launch_ns<MODE, 4>(a, ns, n_blocks, s);
-        case 5: return launch_ns<MODE, 5>(a, ns, n_blocks, s);
-        case 6: return launch_ns<MODE, 6>(a, ns, n_blocks, s);
-        case 7: return launch_ns<MODE, 7>(a, ns, n_blocks, s);
-        case 8: return launch_ns<MODE, 8>(a, ns, n_blocks, s);
+template <int MODE, int W>
+hipError_t launch_lpc(const WalkArgs &a, const MaskShape &sh, int64_t n_blocks, hipStream_t s) {
+    switch (sh.lpc) {
+        case 1: return launch_nr<MODE, W, 1>(a, sh.rows, sh.lds, n_blocks, s);
+        case 2: return launch_nr<MODE, W, (W >= 2 ? 2 : 1)>(a, sh.rows, sh.lds, n_blocks, s);
+        case 4: return launch_nr<MODE, W, (W >= 4 ? 4 : 1)>(a, sh.rows, sh.lds, n_blocks, s);
+        case 8: return launch_nr<MODE, W, (W >= 8 ? 8 : 1)>(a, sh.rows, sh.lds, n_blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-}  // namespace
-
-bool mask_walk_supported(int32_t nA, int32_t nB, int mode) {
-    const int words = (nA + 63) / 64 + (mode == MODE_POOLED ? (nB + 63) / 64 : 0);
-    const int n = nA + (mode == MODE_POOLED ? nB : 0);
-    return words <= 8 && n <= 512;
+int pow2_at_least(int x) {
+    int p = 1;
+    while (p < x) p *= 2;
+    return p;
 }
 
-hipError_t launch_mask_walk(const WalkArgs &a, int mode, int64_t n_blocks, hipStream_t s) {
-    const int words = a.WA + (mode == MODE_POOLED ? a.WB : 0);
-    const int n = a.nA + (mode == MODE_POOLED ? a.nB : 0);
-    const int ns = n <= 128 ? 1 : (n <= 256 ? 2 : 4);   // room for n/2 classes
+}  // namespace
+
+MaskShape mask_walk_shape(int32_t nA, int32_t nB, int mode, int lpc) {
+    MaskShape sh{};
+    const int words = (nA + 63) / 64 + (mode == MODE_POOLED ? (nB + 63) / 64 : 0);
+    const int n = nA + (mode == MODE_POOLED ? nB : 0);
+    if (words > 8 || n > 512) return sh;
+    sh.words = pow2_at_least(words);   // 1, 2, 4 or 8
+    if (lpc <= 0) lpc = 1;   // default: one class per lane (64 classes per row)
+    if (lpc > sh.words || (lpc & (lpc - 1))) return MaskShape{};
+    sh.lpc = lpc;
+    const int cpr = 64 / lpc;
+    const int kmax = n / 2 + 2;   // classes with >= 2 members, plus the two at x0
+    sh.rows = pow2_at_least((kmax + cpr - 1) / cpr);
+    if (sh.rows > 16) return MaskShape{};
+    sh.pair_cap = mode == MODE_CORE ? kPairCap : 0;
+    const size_t stage_words = (size_t)sh.rows * cpr * (sh.words + 1);
+    const size_t union_words = stage_words > (size_t)sh.pair_cap / 2 ? stage_words
+                                                                      : (size_t)sh.pair_cap / 2;
+    sh.lds = ((size_t)64 * sh.words + union_words) * sizeof(uint64_t) + 64 * sizeof(uint32_t);
+    sh.ok = true;
+    return sh;
+}
+
+bool mask_walk_supported(int32_t nA, int32_t nB, int mode) {
+    return mask_walk_shape(nA, nB, mode, 0).ok;
+}
+
+hipError_t launch_mask_walk(const WalkArgs &a, int mode, int lpc, int64_t n_blocks, hipStream_t s) {
+    const MaskShape sh = mask_walk_shape(a.nA, a.nB, mode, lpc);
+    if (!sh.ok) return hipErrorInvalidValue;
     if (n_blocks <= 0) return hipSuccess;
-    if (mode == MODE_CORE) return launch_w<MODE_CORE>(a, words, ns, n_blocks, s);
-    return launch_w<MODE_POOLED>(a, words, ns, n_blocks, s);
+    const bool core = mode == MODE_CORE;
+    switch (sh.words) {
+        case 1: return core ? launch_lpc<MODE_CORE, 1>(a, sh, n_blocks, s)
+                            : launch_lpc<MODE_POOLED, 1>(a, sh, n_blocks, s);
+        case 2: return core ? launch_lpc<MODE_CORE, 2>(a, sh, n_blocks, s)
+                            : launch_lpc<MODE_POOLED, 2>(a, sh, n_blocks, s);
+        case 4: return core ? launch_lpc<MODE_CORE, 4>(a, sh, n_blocks, s)
+                            : launch_lpc<MODE_POOLED, 4>(a, sh, n_blocks, s);
+        case 8: return core ? launch_lpc<MODE_CORE, 8>(a, sh, n_blocks, s)
+                            : launch_lpc<MODE_POOLED, 8>(a, sh, n_blocks, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace ss

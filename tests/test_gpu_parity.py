@@ -229,6 +229,42 @@ def test_ihs_ragged_haplotype_counts(ss, walk, n):
     check_ihs(got, ref, "n=%d" % n)
 
 
+@pytest.mark.parametrize("lpc", [1, 2, 4, 8])
+@pytest.mark.parametrize("n", [65, 204, 300, 510])
+def test_ihs_mask_lanes(ss, lpc, n):
+    # every lanes-per-class setting of the bitmask walk gives the same answer
+    d = hapgen.random_haplotypes(n, 900, 70 + n, n_founders=max(2, n // 10), switch_p=0.006)
+    say("ss_ihs %d x 900 mask lanes=%d" % (n, lpc))
+    ss.set_walk_kernel(2)
+    ss.set_mask_lanes(lpc)
+    try:
+        h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
+        got = _np(ss.ihs(h, steps=True))
+    finally:
+        ss.set_mask_lanes(0)
+        ss.set_walk_kernel(0)
+    ref = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm)
+    check_ihs(got, ref, "n=%d lpc=%d" % (n, lpc))
+
+
+@pytest.mark.parametrize("lpc", [1, 2, 4, 8])
+def test_xpehh_mask_lanes(ss, lpc):
+    a = hapgen.random_haplotypes(200, 800, 5, n_founders=15, switch_p=0.004)
+    b = hapgen.random_haplotypes(190, 800, 6, n_founders=12, switch_p=0.004)
+    say("ss_xpehh 200+190 x 800 mask lanes=%d" % lpc)
+    ss.set_walk_kernel(2)
+    ss.set_mask_lanes(lpc)
+    try:
+        ha = _hm(ss, a.alleles, a.pos_bp, a.gpos_cm)
+        hb = _hm(ss, b.alleles, a.pos_bp, a.gpos_cm)
+        got = _np(ss.xpehh(ha, hb, steps=True))
+    finally:
+        ss.set_mask_lanes(0)
+        ss.set_walk_kernel(0)
+    ref = oracle.xpehh(a.alleles, b.alleles, a.pos_bp, a.gpos_cm)
+    check_xpehh(got, ref, "xpehh lpc=%d" % lpc)
+
+
 def test_ihs_is_deterministic(ss, walk):
     d = hapgen.config_input(1)
     say("ss_ihs twice")
