@@ -84,6 +84,7 @@ struct ScanWs {
     double *binstat;      // [nbins][3]
     uint64_t *hbits;      // [n][mwp] haplotype-major copy (iHS only)
     double *seg;          // [M] segment lengths with the gap rules applied
+    int32_t *redo;        // [1 + 2M] overflow count, then the walks to redo
     size_t bytes;
 };
 
@@ -104,6 +105,7 @@ ScanWs carve_scan(void *base, int64_t M, int nbins, int64_t n_hapmajor = 0) {
     w.hbits = n_hapmajor ? (uint64_t *)take(8 * (size_t)n_hapmajor * (size_t)ss::hap_major_words(M))
                          : nullptr;
     w.seg = (double *)take(8 * (size_t)M);
+    w.redo = (int32_t *)take(4 * (1 + 2 * (size_t)M));
     w.bytes = off;
     return w;
 }
@@ -167,6 +169,10 @@ size_t scan_walk_lds(int32_t nA, int32_t nB, int mode) {
     return ss::walk_shape(nA, nB, mode).lds;
 }
 
+// Workgroups of the pass that redoes, with the class-id walk, the walks the
+// bitmask kernel could not hold; it exits at once when there are none.
+constexpr int kRedoBlocks = 256;
+
 int launch_timed_walk(const ss::WalkArgs &a, int mode, int64_t blocks, hipStream_t s) {
     std::unique_lock<std::mutex> lk(g_timing.mu);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -177,6 +183,8 @@ int launch_timed_walk(const ss::WalkArgs &a, int mode, int64_t blocks, hipStream
         SS_HIP(hipEventRecord(e0, s));
     }
     SS_HIP(launch_scan_walk(a, mode, blocks, s));
+    if (a.redo_count && use_mask_walk(a.nA, a.nB, mode))
+        SS_HIP(ss::launch_walk_list(a, mode, kRedoBlocks, s));
     if (g_timing.on) {
         SS_HIP(hipEventRecord(e1, s));
         g_timing.pending.emplace_back(e0, e1);
@@ -307,8 +315,11 @@ int ss_ihs(const ss_hapmat *h, const ss_params *p, double *d_ihh1, double *d_ihh
     a.mwp = ss::hap_major_words(M);
     a.hbits = w.hbits;
     a.seg = w.seg;
+    a.redo_count = w.redo;
+    a.redo_list = w.redo + 1;
     SS_HIP(ss::launch_transpose(h->bits, h->words_per_site, h->n_haps, M, a.mwp, w.hbits, s));
-    SS_HIP(ss::launch_segments(M, h->pos_bp, h->gpos_cm, p->gap_scale_bp, p->max_gap_bp, w.seg, s));
+    SS_HIP(ss::launch_segments(M, h->pos_bp, h->gpos_cm, p->gap_scale_bp, p->max_gap_bp, w.seg,
+                               w.redo, s));
     if ((rc = launch_timed_walk(a, ss::MODE_CORE, M, s)) != SS_OK) return rc;
     SS_HIP(ss::launch_combine(ss::MODE_CORE, M, w.walk_flag, w.dihh, w.dstatus, w.dsteps, d_ihh1,
                               d_ihh0, d_unstd, d_status, d_steps, s));
@@ -343,7 +354,10 @@ int ss_xpehh(const ss_hapmat *ha, const ss_hapmat *hb, const ss_params *p, doubl
     a.dstatus = w.dstatus;
     a.steps = w.dsteps;
     a.seg = w.seg;
-    SS_HIP(ss::launch_segments(M, ha->pos_bp, ha->gpos_cm, p->gap_scale_bp, p->max_gap_bp, w.seg, s));
+    a.redo_count = w.redo;
+    a.redo_list = w.redo + 1;
+    SS_HIP(ss::launch_segments(M, ha->pos_bp, ha->gpos_cm, p->gap_scale_bp, p->max_gap_bp, w.seg,
+                               w.redo, s));
     if ((rc = launch_timed_walk(a, ss::MODE_POOLED, M, s)) != SS_OK) return rc;
     SS_HIP(ss::launch_combine(ss::MODE_POOLED, M, nullptr, w.dihh, w.dstatus, w.dsteps, d_ihhA,
                               d_ihhB, d_unstd, d_status, d_steps, s));

@@ -50,6 +50,10 @@ struct WalkArgs {
     // per-segment genetic lengths with the gap rules applied (segment k-1 -> k
     // at index k; -1 marks an abort gap); null: walks compute them
     const double *seg;
+    // walks the bitmask kernel could not hold (more live classes than its
+    // registers): entries 2 * site + direction, redone by the class-id walk
+    int32_t *redo_list;         // [2 M]
+    int32_t *redo_count;        // [1], zeroed by the segment pass
 };
 
 struct WalkShape {
@@ -79,12 +83,13 @@ bool mask_walk_supported(int32_t nA, int32_t nB, int mode);
 hipError_t launch_mask_walk(const WalkArgs &a, int mode, int lpc, int64_t n_blocks, hipStream_t s);
 hipError_t launch_walk(const WalkArgs &a, int mode, bool trace, int64_t n_blocks,
                        hipStream_t s);
+hipError_t launch_walk_list(const WalkArgs &a, int mode, int blocks, hipStream_t s);
 
 // Site-level kernels.
 hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps,
                        uint64_t *bits, hipStream_t s);
 hipError_t launch_segments(int64_t M, const int64_t *pos, const double *gpos, int64_t gap_scale,
-                           int64_t max_gap, double *seg, hipStream_t s);
+                           int64_t max_gap, double *seg, int32_t *zero_me, hipStream_t s);
 // Haplotype-major transposed matrix: [n][mwp] words, mwp = ceil(M/64) + 2.
 inline int64_t hap_major_words(int64_t M) { return (M + 63) / 64 + 2; }
 hipError_t launch_transpose(const uint64_t *bits, int64_t wps, int64_t n, int64_t M, int64_t mwp,

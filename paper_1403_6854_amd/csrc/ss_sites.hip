@@ -67,8 +67,10 @@ __global__ void __launch_bounds__(kBlock) transpose_kernel(const uint64_t *__res
 __global__ void __launch_bounds__(kBlock) segment_kernel(int64_t M, const int64_t *__restrict__ pos,
                                                          const double *__restrict__ gpos,
                                                          int64_t gap_scale, int64_t max_gap,
-                                                         double *__restrict__ seg) {
+                                                         double *__restrict__ seg,
+                                                         int32_t *__restrict__ zero_me) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k == 0 && zero_me) *zero_me = 0;   // the walk's overflow-list counter
     if (k >= M) return;
     if (k == 0) {
         seg[0] = -1.0;
@@ -296,10 +298,10 @@ hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps
 }
 
 hipError_t launch_segments(int64_t M, const int64_t *pos, const double *gpos, int64_t gap_scale,
-                           int64_t max_gap, double *seg, hipStream_t s) {
+                           int64_t max_gap, double *seg, int32_t *zero_me, hipStream_t s) {
     const int64_t blocks = (M + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(segment_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, M, pos, gpos,
-                       gap_scale, max_gap, seg);
+                       gap_scale, max_gap, seg, zero_me);
     return hipGetLastError();
 }
 

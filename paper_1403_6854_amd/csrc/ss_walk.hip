@@ -70,17 +70,17 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 
 // Size word of a class: CORE mode = count | core << 31; POOLED mode =
 // countA | countB << 16.  Ones-counter words use the same split.
+// One walk: core site j, direction d (0 downstream, 1 upstream), by the whole
+// workgroup.
 template <int MODE, bool TRACE, int R>
-__global__ void __launch_bounds__(1024) walk_kernel(WalkArgs a) {
+__device__ void walk_one(const WalkArgs &a, int64_t j, int d) {
     extern __shared__ uint32_t smem[];
     const int T = blockDim.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wpg = T >> 6;
-    const int d = blockIdx.y;
     const int dir = d == 0 ? 1 : -1;
-    const int64_t j = a.sites ? (int64_t)a.sites[blockIdx.x] : a.site0 + (int64_t)blockIdx.x;
     if (j >= a.M) return;
     if (a.walk_flag && !a.walk_flag[j]) return;
 
@@ -409,6 +409,23 @@ done:
     }
 }
 
+template <int MODE, bool TRACE, int R>
+__global__ void __launch_bounds__(1024) walk_kernel(WalkArgs a) {
+    walk_one<MODE, TRACE, R>(a, a.site0 + (int64_t)blockIdx.x, (int)blockIdx.y);
+}
+
+// Walks listed by another kernel (entry = 2 * site + direction), count on the
+// device; each workgroup takes every gridDim.x-th entry.
+template <int MODE, int R>
+__global__ void __launch_bounds__(1024) walk_list_kernel(WalkArgs a) {
+    const int32_t n = *a.redo_count;
+    for (int32_t e = blockIdx.x; e < n; e += gridDim.x) {
+        const int32_t v = a.redo_list[e];
+        walk_one<MODE, false, R>(a, (int64_t)(v >> 1), v & 1);
+        __syncthreads();
+    }
+}
+
 template <int MODE, bool TRACE>
 hipError_t launch_r(const WalkArgs &a, const WalkShape &sh, int64_t n_blocks, hipStream_t s) {
     dim3 grid((unsigned)n_blocks, 2u, 1u);
@@ -427,6 +444,22 @@ hipError_t launch_r(const WalkArgs &a, const WalkShape &sh, int64_t n_blocks, hi
 
 }  // namespace
 
+template <int MODE>
+hipError_t launch_list_r(const WalkArgs &a, const WalkShape &sh, int blocks, hipStream_t s) {
+    dim3 grid((unsigned)blocks, 1u, 1u);
+    dim3 block((unsigned)sh.threads, 1u, 1u);
+    switch (sh.slots) {
+        case 1: hipLaunchKernelGGL((walk_list_kernel<MODE, 1>), grid, block, sh.lds, s, a); break;
+        case 2: hipLaunchKernelGGL((walk_list_kernel<MODE, 2>), grid, block, sh.lds, s, a); break;
+        case 4: hipLaunchKernelGGL((walk_list_kernel<MODE, 4>), grid, block, sh.lds, s, a); break;
+        case 8: hipLaunchKernelGGL((walk_list_kernel<MODE, 8>), grid, block, sh.lds, s, a); break;
+        case 16: hipLaunchKernelGGL((walk_list_kernel<MODE, 16>), grid, block, sh.lds, s, a); break;
+        case 32: hipLaunchKernelGGL((walk_list_kernel<MODE, 32>), grid, block, sh.lds, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 WalkShape walk_shape(int32_t nA, int32_t nB, int mode) {
     WalkShape sh;
     const int words = (nA + 63) / 64 + (mode == MODE_POOLED ? (nB + 63) / 64 : 0);
@@ -443,6 +476,13 @@ WalkShape walk_shape(int32_t nA, int32_t nB, int mode) {
     const int64_t kmax = n / 2 + 2;
     sh.lds = (size_t)(4 * kmax + 8 * kmax + 8 * kmax + 32 + 8 + 8);
     return sh;
+}
+
+hipError_t launch_walk_list(const WalkArgs &a, int mode, int blocks, hipStream_t s) {
+    const WalkShape sh = walk_shape(a.nA, a.nB, mode);
+    if (sh.threads > 1024) return hipErrorInvalidConfiguration;
+    return mode == MODE_CORE ? launch_list_r<MODE_CORE>(a, sh, blocks, s)
+                             : launch_list_r<MODE_POOLED>(a, sh, blocks, s);
 }
 
 hipError_t launch_walk(const WalkArgs &a, int mode, bool trace, int64_t n_blocks, hipStream_t s) {

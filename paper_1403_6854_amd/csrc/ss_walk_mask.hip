@@ -237,17 +237,21 @@ __global__ void __launch_bounds__(64) mask_walk_kernel(WalkArgs a) {
 
     // Dense re-indexing of the live classes through LDS, with the second
     // child of every split appended after them.
+    // Returns false, changing nothing, when the classes do not fit in the
+    // wave's NR rows.
     auto compact = [&](const bool (&split)[NR], const uint64_t (&zm)[NR][WPL],
-                       const uint32_t (&za)[NR], const uint32_t (&zb)[NR]) {
+                       const uint32_t (&za)[NR], const uint32_t (&zb)[NR]) -> bool {
         const uint64_t below_group = (q == 0) ? 0ull : ((1ull << (q * LPC)) - 1ull);
-        int nlive = 0;
+        int nlive = 0, nsplit = 0;
         int at[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const uint64_t lm = __ballot(leader && ca[r] + cb[r] >= 2u);
             at[r] = nlive + __popcll(lm & below_group);
             nlive += __popcll(lm);
+            nsplit += __popcll(__ballot(leader && split[r]));
         }
+        if (nlive + nsplit > NR * CPR) return false;
         int nsp = nlive;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -283,10 +287,12 @@ __global__ void __launch_bounds__(64) mask_walk_kernel(WalkArgs a) {
             }
         }
         __syncthreads();
+        return true;
     };
 
     // ---- pairwise phase -------------------------------------------------------
     bool pmode = false;
+    bool overflow = false;   // the classes outgrew the wave: the walk is redone elsewhere
     int npairs = 0;
     uint32_t s_now = 0;   // S after the last marker processed
     if (MODE == MODE_CORE) s_now = choose2(core ? n1a : n0a);
@@ -494,7 +500,10 @@ __global__ void __launch_bounds__(64) mask_walk_kernel(WalkArgs a) {
                 if (!pack16) SB = wave_sum(accB);
             }
             if (anysplit) {
-                compact(split, zm, za, zb);
+                if (!compact(split, zm, za, zb)) {   // more classes than rows
+                    overflow = true;
+                    break;
+                }
             } else if (NR > 1 && kend > CPR && (i & 7) == 7) {
                 // reclaim the holes left by classes that died, so that the
                 // upper rows stop being processed once they are empty
@@ -518,6 +527,7 @@ __global__ void __launch_bounds__(64) mask_walk_kernel(WalkArgs a) {
         }
         }
         step += i;
+        if (overflow) break;
 
         // ---- FP64 trapezoid of this batch: terms lane-parallel, sum in order
         if (nterm > 0) {
@@ -555,6 +565,11 @@ __global__ void __launch_bounds__(64) mask_walk_kernel(WalkArgs a) {
         }
     }
 
+    if (overflow) {
+        // the class-id walk redoes this site and direction for both cores
+        if (lane == 0) a.redo_list[atomicAdd(a.redo_count, 1)] = (int32_t)(j * 2 + d);
+        return;
+    }
     if (lane == 0) {
         const size_t o = (size_t)j * 2 + d;
         if (MODE == MODE_CORE) {
@@ -616,7 +631,11 @@ MaskShape mask_walk_shape(int32_t nA, int32_t nB, int mode, int lpc) {
     sh.lpc = lpc;
     const int cpr = 64 / lpc;
     const int kmax = n / 2 + 2;   // classes with >= 2 members, plus the two at x0
-    sh.rows = pow2_at_least((kmax + cpr - 1) / cpr);
+    // iHS walks keep one row of classes in registers: walks that would need
+    // more (rare: a core split into more than 64 / lpc multi-member classes)
+    // are listed for the class-id walk.  Pooled walks hold their full
+    // capacity.
+    sh.rows = mode == MODE_CORE ? 1 : pow2_at_least((kmax + cpr - 1) / cpr);
     if (sh.rows > 16) return MaskShape{};
     sh.pair_cap = mode == MODE_CORE ? kPairCap : 0;
     const size_t stage_words = (size_t)sh.rows * cpr * (sh.words + 1);

@@ -265,6 +265,40 @@ def test_xpehh_mask_lanes(ss, lpc):
     check_xpehh(got, ref, "xpehh lpc=%d" % lpc)
 
 
+def _many_classes(seed):
+    """A core whose walk holds more than 64 multi-member classes at once while
+    its EHH is still high: 200 identical carriers plus 70 distinct identical
+    pairs, told apart by a 7-marker code right after the core."""
+    rng = np.random.default_rng(seed)
+    n1, n0, M, core = 340, 24, 160, 60
+    n = n1 + n0
+    H = (rng.random((M, n)) < 0.5).astype(np.uint8)
+    H[core, :n1] = 1
+    H[core, n1:] = 0
+    group = np.zeros(n1, dtype=np.int64)
+    group[200:] = 1 + (np.arange(n1 - 200) // 2)          # 70 pairs, codes 1..70
+    for direction in (+1, -1):
+        for b in range(7):
+            H[core + direction * (b + 1), :n1] = (group >> b) & 1
+        for t in range(8, 30):                            # identical within groups for a while
+            col = rng.integers(0, 2, size=71)
+            H[core + direction * t, :n1] = col[group]
+    pos = (np.arange(M, dtype=np.int64) + 1) * 1000
+    return H, pos, pos * 1e-6, core
+
+
+def test_ihs_more_classes_than_a_wave_row(ss, walk):
+    H, pos, gpos, core = _many_classes(3)
+    say("ss_ihs many classes walk=%d" % walk)
+    h = _hm(ss, H, pos, gpos)
+    params = oracle.Params(maf_cutoff=0.0)
+    got = _np(ss.ihs(h, ss.Params(**vars(params)), steps=True))
+    ref = oracle.ihs(H, pos, gpos, params)
+    check_ihs(got, ref, "many classes")
+    assert ref["status"][core] in (0, 5)
+    assert ref["steps"][core, 0, 1] > 8
+
+
 def test_ihs_is_deterministic(ss, walk):
     d = hapgen.config_input(1)
     say("ss_ihs twice")
