@@ -82,6 +82,7 @@ struct ScanWs {
     int32_t *dstatus;     // [M][2][2]
     int32_t *dsteps;      // [M][2][2]
     double *binstat;      // [nbins][3]
+    double *binpart;      // per-tile partial sums of the bin statistics
     uint64_t *hbits;      // [n][mwp] haplotype-major copy (iHS only)
     double *seg;          // [M] segment lengths with the gap rules applied
     int32_t *redo;        // [1 + 2M] overflow count, then the walks to redo
@@ -102,6 +103,7 @@ ScanWs carve_scan(void *base, int64_t M, int nbins, int64_t n_hapmajor = 0) {
     w.dstatus = (int32_t *)take(16 * (size_t)M);
     w.dsteps = (int32_t *)take(16 * (size_t)M);
     w.binstat = (double *)take(24 * (size_t)nbins);
+    w.binpart = (double *)take(8 * (size_t)ss::standardize_scratch_doubles(M, nbins));
     w.hbits = n_hapmajor ? (uint64_t *)take(8 * (size_t)n_hapmajor * (size_t)ss::hap_major_words(M))
                          : nullptr;
     w.seg = (double *)take(8 * (size_t)M);
@@ -149,13 +151,11 @@ hipEvent_t take_event() {
 int g_walk_kind = ss::WALK_AUTO;
 int g_mask_lpc = 0;   // lanes per class of the bitmask walk; 0 = default
 
-// Automatic choice: the bitmask walk (with its pairwise phase) for iHS when
-// the haplotypes fit; the class-id walk for XPEHH, whose pooled walks are short
-// and whose bitmask form needs twice the registers.
+// Automatic choice: the bitmask walk whenever the haplotypes fit (up to 512
+// in the walk), the class-id walk otherwise.
 bool use_mask_walk(int32_t nA, int32_t nB, int mode) {
     if (g_walk_kind == ss::WALK_LDS_IDS) return false;
-    if (!ss::mask_walk_shape(nA, nB, mode, g_mask_lpc).ok) return false;
-    return g_walk_kind == ss::WALK_REG_MASKS || mode == ss::MODE_CORE;
+    return ss::mask_walk_shape(nA, nB, mode, g_mask_lpc).ok;
 }
 
 hipError_t launch_scan_walk(const ss::WalkArgs &a, int mode, int64_t blocks, hipStream_t s) {
@@ -323,7 +323,8 @@ int ss_ihs(const ss_hapmat *h, const ss_params *p, double *d_ihh1, double *d_ihh
     if ((rc = launch_timed_walk(a, ss::MODE_CORE, M, s)) != SS_OK) return rc;
     SS_HIP(ss::launch_combine(ss::MODE_CORE, M, w.walk_flag, w.dihh, w.dstatus, w.dsteps, d_ihh1,
                               d_ihh0, d_unstd, d_status, d_steps, s));
-    SS_HIP(ss::launch_standardize(M, d_unstd, d_status, w.bin, nbins, w.binstat, d_std, s));
+    SS_HIP(ss::launch_standardize(M, d_unstd, d_status, w.bin, nbins, w.binstat, w.binpart, d_std,
+                                  s));
     return SS_OK;
 }
 
@@ -361,7 +362,7 @@ int ss_xpehh(const ss_hapmat *ha, const ss_hapmat *hb, const ss_params *p, doubl
     if ((rc = launch_timed_walk(a, ss::MODE_POOLED, M, s)) != SS_OK) return rc;
     SS_HIP(ss::launch_combine(ss::MODE_POOLED, M, nullptr, w.dihh, w.dstatus, w.dsteps, d_ihhA,
                               d_ihhB, d_unstd, d_status, d_steps, s));
-    SS_HIP(ss::launch_standardize(M, d_unstd, d_status, nullptr, 1, w.binstat, d_std, s));
+    SS_HIP(ss::launch_standardize(M, d_unstd, d_status, nullptr, 1, w.binstat, w.binpart, d_std, s));
     return SS_OK;
 }
 

@@ -103,9 +103,10 @@ hipError_t launch_combine(int mode, int64_t M, const uint8_t *walk_flag,
                           const int32_t *dsteps, double *out_a, double *out_b,
                           double *unstd, int8_t *status, int32_t *steps_out,
                           hipStream_t s);
+int64_t standardize_scratch_doubles(int64_t M, int32_t nbins);
 hipError_t launch_standardize(int64_t M, const double *unstd, int8_t *status,
                               const int32_t *bin, int32_t nbins, double *binstat,
-                              double *z, hipStream_t s);
+                              double *scratch, double *z, hipStream_t s);
 hipError_t launch_ehh_finish(int64_t n, int64_t cap, const uint64_t *S, const int64_t *len,
                              const double *dihh, const int32_t *dstatus, double *ehh,
                              double *ihh, int8_t *status, hipStream_t s);

@@ -179,50 +179,92 @@ __global__ void __launch_bounds__(kBlock) combine_kernel(
     }
 }
 
-__device__ double block_sum(double v, double *red) {
-    const int t = threadIdx.x;
-    red[t] = v;
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (t < s) red[t] = red[t] + red[t + s];
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
+// Frequency-bin statistics (Eq. 6; Eq. 9 with one bin): count, mean and N-1
+// standard deviation of the OK scores of each bin, in two passes like the
+// definition (mean first, then squared deviations from it).  Sites are cut
+// into tiles of kTile, one per workgroup; each thread holds kTile / kBlock
+// sites, and for every bin the workgroup sums them with fixed-order wave
+// butterflies; the per-tile partial sums are then added in tile order.  The
+// summation order is fixed, so results are identical from run to run.
+constexpr int kTile = 1024;
+
+// Butterfly sum over the 64 lanes of a wave (fixed order: deterministic).
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
-// Mean and N-1 standard deviation of the OK scores in each bin (Eq. 6; Eq. 9
-// with one bin), two passes, fixed summation order.  One workgroup per bin.
-__global__ void __launch_bounds__(kBlock) bin_stats_kernel(int64_t M,
-                                                           const double *__restrict__ u,
-                                                           const int8_t *__restrict__ status,
-                                                           const int32_t *__restrict__ bin,
-                                                           double *__restrict__ binstat) {
-    __shared__ double red[kBlock];
-    const int b = blockIdx.x;
-    double s = 0.0, c = 0.0;
-    for (int64_t j = threadIdx.x; j < M; j += kBlock) {
-        if (status[j] == ST_OK && (bin == nullptr || bin[j] == b)) {
-            s += u[j];
+__global__ void __launch_bounds__(kBlock) bin_partial_kernel(
+    int64_t M, const double *__restrict__ u, const int8_t *__restrict__ status,
+    const int32_t *__restrict__ bin, int32_t nbins, int64_t ntiles,
+    const double *__restrict__ binstat, double *__restrict__ part) {
+    constexpr int kPer = kTile / kBlock;   // sites per thread
+    __shared__ double wpart[kBlock / 64][2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t t0 = (int64_t)blockIdx.x * kTile;
+    double uv[kPer];
+    int32_t bv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int64_t jj = t0 + threadIdx.x + (int64_t)q * kBlock;
+        const bool ok = jj < M && status[jj] == ST_OK;
+        bv[q] = ok ? (bin ? bin[jj] : 0) : -1;
+        uv[q] = ok ? u[jj] : 0.0;
+    }
+    for (int b = 0; b < nbins; ++b) {
+        // second pass: squared deviations from the bin's mean
+        const double mean = binstat ? binstat[3 * b + 1] : 0.0;
+        double c = 0.0, acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            if (bv[q] != b) continue;
             c += 1.0;
+            if (binstat) {
+                const double dlt = uv[q] - mean;
+                acc += dlt * dlt;
+            } else {
+                acc += uv[q];
+            }
         }
-    }
-    const double N = block_sum(c, red);
-    const double sum = block_sum(s, red);
-    const double mean = N > 0.0 ? sum / N : __builtin_nan("");
-    double q = 0.0;
-    for (int64_t j = threadIdx.x; j < M; j += kBlock) {
-        if (status[j] == ST_OK && (bin == nullptr || bin[j] == b)) {
-            const double dlt = u[j] - mean;
-            q += dlt * dlt;
+        c = wave_sum_f64(c);
+        acc = wave_sum_f64(acc);
+        if (lane == 0) {
+            wpart[wave][0] = c;
+            wpart[wave][1] = acc;
         }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double cc = 0.0, aa = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                cc += wpart[w][0];
+                aa += wpart[w][1];
+            }
+            part[((int64_t)blockIdx.x * nbins + b) * 2 + 0] = cc;
+            part[((int64_t)blockIdx.x * nbins + b) * 2 + 1] = aa;
+        }
+        __syncthreads();
     }
-    const double ss = block_sum(q, red);
-    if (threadIdx.x == 0) {
+}
+
+// binstat[b] = {N, mean, sd}: after the first pass N and the mean, after the
+// second pass the standard deviation, from the per-tile partial sums added in
+// tile order.
+__global__ void __launch_bounds__(kBlock) bin_final_kernel(int32_t nbins, int64_t ntiles,
+                                                           const double *__restrict__ part,
+                                                           int second, double *__restrict__ binstat) {
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= nbins) return;
+    double N = 0.0, acc = 0.0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        N += part[(t * nbins + b) * 2 + 0];
+        acc += part[(t * nbins + b) * 2 + 1];
+    }
+    if (!second) {
         binstat[3 * b + 0] = N;
-        binstat[3 * b + 1] = mean;
-        binstat[3 * b + 2] = N > 1.0 ? sqrt(ss / (N - 1.0)) : __builtin_nan("");
+        binstat[3 * b + 1] = N > 0.0 ? acc / N : __builtin_nan("");
+    } else {
+        binstat[3 * b + 2] = N > 1.0 ? sqrt(acc / (N - 1.0)) : __builtin_nan("");
     }
 }
 
@@ -334,12 +376,31 @@ hipError_t launch_combine(int mode, int64_t M, const uint8_t *walk_flag, const d
     return hipGetLastError();
 }
 
+int64_t standardize_scratch_doubles(int64_t M, int32_t nbins) {
+    const int64_t ntiles = (M + kTile - 1) / kTile;
+    return 2 * 2 * ntiles * (int64_t)nbins;
+}
+
 hipError_t launch_standardize(int64_t M, const double *unstd, int8_t *status, const int32_t *bin,
-                              int32_t nbins, double *binstat, double *z, hipStream_t s) {
-    hipLaunchKernelGGL(bin_stats_kernel, dim3((unsigned)nbins), dim3(kBlock), 0, s, M, unstd,
-                       status, bin, binstat);
+                              int32_t nbins, double *binstat, double *scratch, double *z,
+                              hipStream_t s) {
+    const int64_t ntiles = (M + kTile - 1) / kTile;
+    double *first = scratch;
+    double *second = scratch + 2 * ntiles * (int64_t)nbins;
+    const dim3 fin((unsigned)((nbins + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(bin_partial_kernel, dim3((unsigned)ntiles), dim3(kBlock), 0, s, M, unstd,
+                       status, bin, nbins, ntiles, (const double *)nullptr, first);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bin_final_kernel, fin, dim3(kBlock), 0, s, nbins, ntiles,
+                       (const double *)first, 0, binstat);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(bin_partial_kernel, dim3((unsigned)ntiles), dim3(kBlock), 0, s, M, unstd,
+                       status, bin, nbins, ntiles, (const double *)binstat, second);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(bin_final_kernel, fin, dim3(kBlock), 0, s, nbins, ntiles,
+                       (const double *)second, 1, binstat);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t blocks = (M + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(standardize_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, M, unstd,
                        status, bin, binstat, z);

@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(64) mask_walk_kernel(WalkArgs a) {
         pmode = true;
     }
 
-    while (act) {
+    while (act && !pmode) {
         // Long walks decide how long a whole scan takes: once a walk has gone
         // past a few hundred markers its wave takes issue priority over the
         // short walks sharing its SIMD.
@@ -363,14 +363,12 @@ __global__ void __launch_bounds__(64) mask_walk_kernel(WalkArgs a) {
         // ---- lane i holds step i of the next 64: its row words go to LDS,
         // its segment (end of data, abort gap, or scaled genetic length)
         // stays in registers for the FP64 pass
-        if (pf_step != step) fetch(step, !pmode, pf_rows, pf_seg, pf_inr);
-        if (!pmode) {
+        if (pf_step != step) fetch(step, true, pf_rows, pf_seg, pf_inr);
 #pragma unroll
-            for (int w = 0; w < W; ++w) rowbuf[lane * W + w] = pf_rows[w];
-        }
+        for (int w = 0; w < W; ++w) rowbuf[lane * W + w] = pf_rows[w];
         const bool inr = pf_inr;
         const double segv = pf_seg;
-        fetch(step + 64, !pmode, pf_rows, pf_seg, pf_inr);   // next batch, if the walk goes on
+        fetch(step + 64, true, pf_rows, pf_seg, pf_inr);   // next batch, if the walk goes on
         pf_step = step + 64;
         int32_t stl = ST_OK;
         double gl = 0.0;
@@ -386,48 +384,6 @@ __global__ void __launch_bounds__(64) mask_walk_kernel(WalkArgs a) {
         int nterm = 0;              // trapezoid terms of this batch
         int i = 0;
         bool to_pairs = false;
-        if (pmode) {
-            // ---- one pass over the pair list covers the next 64 markers ----
-            const int64_t k0 = j + (int64_t)dir * (int64_t)(step + 1);
-            for (int h = lane; h < a.nA; h += 64) keys[h] = key_of(h, k0);
-            hist[lane] = 0u;
-            __syncthreads();
-            int wpos = 0;
-            for (int p0 = 0; p0 < npairs; p0 += 64) {
-                const int p = p0 + lane;
-                const bool in = p < npairs;
-                const uint32_t pr = in ? pairs[p] : 0u;
-                const uint64_t x = keys[pr & 0xFFFFu] ^ keys[pr >> 16];
-                const int L = x ? (int)__builtin_ctzll(x) : 64;
-                if (in && L < 64) atomicAdd(&hist[L], 1u);
-                const bool surv = in && L == 64;
-                const uint64_t sm = __ballot(surv);
-                const uint64_t below = lane ? (sm & ((1ull << lane) - 1ull)) : 0ull;
-                if (surv) pairs[wpos + __popcll(below)] = pr;   // wpos <= p0: in place
-                wpos += __popcll(sm);
-            }
-            __syncthreads();
-            const uint32_t si = s_now - wave_prefix(hist[lane], lane);   // S after step `lane`
-            const uint64_t valid = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
-            const uint64_t stopm = __ballot(si <= thr) & valid;
-            if (stopm) {
-                i = (int)__builtin_ctzll(stopm) + 1;
-                nterm = i - 1;
-                act = false;
-            } else if (nb < 64) {
-                i = nb;
-                nterm = nb;
-                status = abort_st;
-            } else {
-                i = 64;
-                nterm = 64;
-            }
-            steps += i;
-            sb = si;
-            s_now = (uint32_t)__builtin_amdgcn_readlane(si, 63);
-            npairs = wpos;
-            __syncthreads();
-        } else {
         uint64_t rn[WPL];
 #pragma unroll
         for (int t = 0; t < WPL; ++t) rn[t] = rowbuf[g * WPL + t];
@@ -525,7 +481,6 @@ __global__ void __launch_bounds__(64) mask_walk_kernel(WalkArgs a) {
                 break;
             }
         }
-        }
         step += i;
         if (overflow) break;
 
@@ -563,6 +518,112 @@ __global__ void __launch_bounds__(64) mask_walk_kernel(WalkArgs a) {
             build_pairs();
             pmode = true;
         }
+    }
+
+    // ---- pairwise phase: one pass over the pair list per 64 markers
+    while (act && !overflow && status == ST_OK) {
+        // Long walks decide how long a whole scan takes: once a walk has gone
+        // past a few hundred markers its wave takes issue priority over the
+        // short walks sharing its SIMD.
+        if (step >= 384) __builtin_amdgcn_s_setprio(3);
+        else if (step >= 256) __builtin_amdgcn_s_setprio(2);
+        else if (step >= 128) __builtin_amdgcn_s_setprio(1);
+
+        // ---- lane i holds step i of the next 64: its row words go to LDS,
+        // its segment (end of data, abort gap, or scaled genetic length)
+        // stays in registers for the FP64 pass
+        if (pf_step != step) fetch(step, false, pf_rows, pf_seg, pf_inr);
+        const bool inr = pf_inr;
+        const double segv = pf_seg;
+        fetch(step + 64, false, pf_rows, pf_seg, pf_inr);   // next batch, if the walk goes on
+        pf_step = step + 64;
+        int32_t stl = ST_OK;
+        double gl = 0.0;
+        if (!inr) stl = ST_EDGE;
+        else if (segv < 0.0) stl = ST_GAP;
+        else gl = segv;
+        const uint64_t abort_mask = __ballot(stl != ST_OK);
+        const int nb = abort_mask ? (int)__builtin_ctzll(abort_mask) : 64;
+        const int32_t abort_st = abort_mask ? (int32_t)__builtin_amdgcn_readlane(stl, nb) : ST_OK;
+        __syncthreads();
+
+        uint32_t sb = 0, sbB = 0;   // lane i: step i's S (A|B packed, or A) and S_B
+        int nterm = 0;              // trapezoid terms of this batch
+        int i = 0;
+        {
+            // ---- one pass over the pair list covers the next 64 markers ----
+            const int64_t k0 = j + (int64_t)dir * (int64_t)(step + 1);
+            for (int h = lane; h < a.nA; h += 64) keys[h] = key_of(h, k0);
+            hist[lane] = 0u;
+            __syncthreads();
+            int wpos = 0;
+            for (int p0 = 0; p0 < npairs; p0 += 64) {
+                const int p = p0 + lane;
+                const bool in = p < npairs;
+                const uint32_t pr = in ? pairs[p] : 0u;
+                const uint64_t x = keys[pr & 0xFFFFu] ^ keys[pr >> 16];
+                const int L = x ? (int)__builtin_ctzll(x) : 64;
+                if (in && L < 64) atomicAdd(&hist[L], 1u);
+                const bool surv = in && L == 64;
+                const uint64_t sm = __ballot(surv);
+                const uint64_t below = lane ? (sm & ((1ull << lane) - 1ull)) : 0ull;
+                if (surv) pairs[wpos + __popcll(below)] = pr;   // wpos <= p0: in place
+                wpos += __popcll(sm);
+            }
+            __syncthreads();
+            const uint32_t si = s_now - wave_prefix(hist[lane], lane);   // S after step `lane`
+            const uint64_t valid = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+            const uint64_t stopm = __ballot(si <= thr) & valid;
+            if (stopm) {
+                i = (int)__builtin_ctzll(stopm) + 1;
+                nterm = i - 1;
+                act = false;
+            } else if (nb < 64) {
+                i = nb;
+                nterm = nb;
+                status = abort_st;
+            } else {
+                i = 64;
+                nterm = 64;
+            }
+            steps += i;
+            sb = si;
+            s_now = (uint32_t)__builtin_amdgcn_readlane(si, 63);
+            npairs = wpos;
+            __syncthreads();
+        }
+        step += i;
+
+        // ---- FP64 trapezoid of this batch: terms lane-parallel, sum in order
+        if (nterm > 0) {
+            const double g64 = gl;
+            if (MODE == MODE_CORE) {
+                const double e = (double)sb / PA;
+                double prev = __shfl_up(e, 1, 64);
+                if (lane == 0) prev = epA;
+                const double term = 0.5 * (prev + e) * g64;
+                for (int t = 0; t < nterm; ++t) ihhA += readlane_f64(term, t);
+                epA = readlane_f64(e, nterm - 1);
+            } else {
+                const uint32_t sA = pack16 ? (sb & 0xFFFFu) : sb;
+                const uint32_t sB = pack16 ? (sb >> 16) : sbB;
+                const double eA = (double)sA / PA;
+                const double eB = (double)sB / PB;
+                double pA = __shfl_up(eA, 1, 64);
+                double pB = __shfl_up(eB, 1, 64);
+                if (lane == 0) { pA = epA; pB = epB; }
+                const double tA = 0.5 * (pA + eA) * g64;
+                const double tB = 0.5 * (pB + eB) * g64;
+                for (int t = 0; t < nterm; ++t) {
+                    ihhA += readlane_f64(tA, t);
+                    ihhB += readlane_f64(tB, t);
+                }
+                epA = readlane_f64(eA, nterm - 1);
+                epB = readlane_f64(eB, nterm - 1);
+            }
+        }
+        if (status != ST_OK) break;
+        __syncthreads();   // the next batch overwrites the staged rows
     }
 
     if (overflow) {
@@ -631,11 +692,11 @@ MaskShape mask_walk_shape(int32_t nA, int32_t nB, int mode, int lpc) {
     sh.lpc = lpc;
     const int cpr = 64 / lpc;
     const int kmax = n / 2 + 2;   // classes with >= 2 members, plus the two at x0
-    // iHS walks keep one row of classes in registers: walks that would need
-    // more (rare: a core split into more than 64 / lpc multi-member classes)
-    // are listed for the class-id walk.  Pooled walks hold their full
-    // capacity.
-    sh.rows = mode == MODE_CORE ? 1 : pow2_at_least((kmax + cpr - 1) / cpr);
+    // Walks keep one row of classes in registers; walks that would need more
+    // (rare: more than 64 / lpc multi-member classes at once) are listed for
+    // the class-id walk.
+    (void)kmax;
+    sh.rows = 1;
     if (sh.rows > 16) return MaskShape{};
     sh.pair_cap = mode == MODE_CORE ? kPairCap : 0;
     const size_t stage_words = (size_t)sh.rows * cpr * (sh.words + 1);
