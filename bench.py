@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 int32 lanes/clk x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_traffic.json")
-WALK_SRC = os.path.join(ROOT, "paper_1403_6854_amd", "csrc", "ss_walk.hip")
+WALK_SRC = os.path.join(ROOT, "paper_1403_6854_amd", "csrc", "ss_walk_mask.hip")
 
 
 def log(msg):
@@ -162,7 +162,8 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_INT32_TOPS, 3),
                 "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 5),
                 "traffic": traffic,
-                "kernel": "walk_kernel<MODE_CORE,false,4>", "kernel_ms": round(walk_ms, 5),
+                "kernel": "mask_walk_kernel<CORE,4,1,1> (+ walk_list_kernel overflow pass)",
+                "kernel_ms": round(walk_ms, 5),
                 "work_cells": W, "ops_per_cell": 1,
                 "algorithmic_bytes": W // 8,
                 "algorithmic_GBps": round(W / 8 / (walk_ms * 1e-3) / 1e9, 3)}
