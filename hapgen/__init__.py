@@ -39,7 +39,8 @@ import numpy as np
 __all__ = [
     "HapData", "draw_positions", "draw_founders", "derive_founders",
     "copy_haplotypes", "plant_sweep", "copying_model", "config_input",
-    "random_haplotypes", "CONFIGS",
+    "random_haplotypes", "CONFIGS", "CopyEvents", "draw_copy_events", "render_alleles",
+    "plant_sweep_tensor", "large_batch_input", "poisson_arrivals", "log_uniform_int",
 ]
 
 
@@ -112,6 +113,98 @@ def copy_haplotypes(rng: np.random.Generator, founders: np.ndarray, n_haps: int,
         del sw, step, path, block, flips
     del hap_idx
     return out
+
+
+@dataclasses.dataclass
+class CopyEvents:
+    """The copying model's random draws in sparse form, for large matrices.
+
+    The same model as :func:`copy_haplotypes` (a Bernoulli(switch_p) switch
+    before every site after the first, a Bernoulli(flip_p) flip of every
+    allele), drawn per haplotype as event lists instead of one uniform per
+    (site, haplotype): given its count K ~ Binomial(m, p), the set of sites
+    where a Bernoulli(p) process fires is a uniform K-subset.
+    """
+    n_haps: int
+    n_sites: int
+    n_founders: int
+    start: np.ndarray     # int64 [n_haps] founder copied at site 0
+    sw_hap: np.ndarray    # int64 [K] haplotype of each switch
+    sw_site: np.ndarray   # int64 [K] site from which the new founder is copied (>= 1)
+    sw_step: np.ndarray   # int64 [K] new founder = (old + step) mod n_founders, step in [1, F-1]
+    fl_hap: np.ndarray    # int64 [K'] haplotype of each flipped allele
+    fl_site: np.ndarray   # int64 [K'] its site
+
+
+def _subsets(rng: np.random.Generator, counts: np.ndarray, m: int, offset: int) -> np.ndarray:
+    parts = [np.sort(rng.choice(m, size=int(k), replace=False)) + offset if k else
+             np.empty(0, dtype=np.int64) for k in counts]
+    return np.concatenate(parts).astype(np.int64) if parts else np.empty(0, dtype=np.int64)
+
+
+def draw_copy_events(rng: np.random.Generator, n_haps: int, n_sites: int, n_founders: int,
+                     switch_p: float, flip_p: float) -> CopyEvents:
+    start = rng.integers(0, n_founders, size=n_haps).astype(np.int64)
+    ks = rng.binomial(max(0, n_sites - 1), switch_p, size=n_haps) if n_sites > 1 \
+        else np.zeros(n_haps, dtype=np.int64)
+    sw_site = _subsets(rng, ks, max(1, n_sites - 1), 1)
+    sw_hap = np.repeat(np.arange(n_haps, dtype=np.int64), ks)
+    if n_founders >= 2:
+        sw_step = rng.integers(1, n_founders, size=len(sw_site)).astype(np.int64)
+    else:
+        sw_step = np.zeros(len(sw_site), dtype=np.int64)
+    kf = rng.binomial(n_sites, flip_p, size=n_haps)
+    fl_site = _subsets(rng, kf, n_sites, 0)
+    fl_hap = np.repeat(np.arange(n_haps, dtype=np.int64), kf)
+    return CopyEvents(n_haps, n_sites, n_founders, start, sw_hap, sw_site, sw_step, fl_hap, fl_site)
+
+
+def render_alleles(founders: np.ndarray, ev: CopyEvents, device="cpu", chunk: int = 65536):
+    """The site-major uint8 allele matrix of a CopyEvents draw, as a torch
+    tensor on ``device`` (integer operations only, so every device gives the
+    same matrix)."""
+    import torch
+    F, M = founders.shape
+    n = ev.n_haps
+    fd = torch.from_numpy(np.ascontiguousarray(founders)).to(device)
+    out = torch.empty((M, n), dtype=torch.uint8, device=device)
+    order = np.argsort(ev.sw_site, kind="stable")
+    sites, haps, steps = ev.sw_site[order], ev.sw_hap[order], ev.sw_step[order]
+    cur = torch.from_numpy(ev.start).to(device)
+    for s0 in range(0, M, chunk):
+        s1 = min(M, s0 + chunk)
+        i0, i1 = np.searchsorted(sites, [s0, s1])
+        delta = torch.zeros((s1 - s0, n), dtype=torch.int64, device=device)
+        if i1 > i0:
+            delta[torch.from_numpy(sites[i0:i1] - s0).to(device),
+                  torch.from_numpy(haps[i0:i1]).to(device)] = torch.from_numpy(steps[i0:i1]).to(device)
+        path = torch.remainder(cur[None, :] + torch.cumsum(delta, dim=0), F)
+        cur = path[-1].clone()
+        col = torch.arange(s0, s1, device=device)[:, None]
+        out[s0:s1] = fd[path, col]
+        del delta, path
+    if len(ev.fl_site):
+        fs = torch.from_numpy(ev.fl_site).to(device)
+        fh = torch.from_numpy(ev.fl_hap).to(device)
+        out[fs, fh] = out[fs, fh] ^ 1
+    return out
+
+
+def plant_sweep_tensor(rng: np.random.Generator, alleles, pos_bp: np.ndarray, site: int,
+                       phi: float, block_bp: int = 400_000) -> None:
+    """:func:`plant_sweep` on a torch allele matrix (same draws, same result)."""
+    import torch
+    n_haps = alleles.shape[1]
+    k = int(round(phi * n_haps))
+    carriers = rng.choice(n_haps, size=k, replace=False)
+    lo = int(np.searchsorted(pos_bp, pos_bp[site] - block_bp // 2, side="left"))
+    hi = int(np.searchsorted(pos_bp, pos_bp[site] + block_bp // 2, side="right"))
+    ct = torch.from_numpy(carriers.astype(np.int64)).to(alleles.device)
+    if k > 0:
+        template = alleles[lo:hi, int(carriers[0])].clone()
+        alleles[lo:hi, ct] = template[:, None].expand(hi - lo, k)
+    alleles[site, :] = 0
+    alleles[site, ct] = 1
 
 
 def plant_sweep(rng: np.random.Generator, alleles: np.ndarray, pos_bp: np.ndarray,
@@ -204,20 +297,31 @@ def config_input(idx: int, scale_sites: Optional[int] = None):
         b = HapData(alleles, a.pos_bp, a.gpos_cm, fb, ())
         return a, b
     if idx == 3:
-        c = CONFIGS[3]
-        m = c["n_sites"] if scale_sites is None else int(scale_sites)
-        length = c["length_bp"] if scale_sites is None else max(m, int(c["length_bp"] * m / c["n_sites"]))
-        rng = np.random.default_rng(1003)
-        pos, gpos = draw_positions(rng, m, length)
-        founders = draw_founders(rng, c["n_founders"], m)
-        alleles = copy_haplotypes(rng, founders, c["n_haps"], c["switch_p"], 0.001)
-        n_sw = c["n_sweeps"] if scale_sites is None else max(1, min(c["n_sweeps"], m // 5000))
-        sites = [int((k + 0.5) * m / n_sw) for k in range(n_sw)]
-        phis = rng.uniform(*c["phi_range"], size=n_sw)
-        for s, phi in zip(sites, phis):
-            plant_sweep(rng, alleles, pos, s, float(phi))
-        return HapData(alleles, pos, gpos, founders, tuple(sites))
+        alleles, pos, gpos, sites = large_batch_input(scale_sites, device="cpu")
+        return HapData(alleles.numpy(), pos, gpos, None, sites)
     raise KeyError(idx)
+
+
+def large_batch_input(scale_sites: Optional[int] = None, device="cpu"):
+    """The 5,000-haplotype x 10^6-site workload (seed 1003), built with the
+    sparse copying-model draws and rendered on ``device``: returns (alleles
+    torch uint8 [M, n], pos_bp, gpos_cm, sweep sites).  ``scale_sites`` keeps
+    the density and haplotype count on fewer sites."""
+    c = CONFIGS[3]
+    m = c["n_sites"] if scale_sites is None else int(scale_sites)
+    length = c["length_bp"] if scale_sites is None else max(m, int(c["length_bp"] * m / c["n_sites"]))
+    rng = np.random.default_rng(1003)
+    pos, gpos = draw_positions(rng, m, length)
+    founders = draw_founders(rng, c["n_founders"], m)
+    ev = draw_copy_events(rng, c["n_haps"], m, c["n_founders"], c["switch_p"], 0.001)
+    alleles = render_alleles(founders, ev, device=device)
+    del founders, ev
+    n_sw = c["n_sweeps"] if scale_sites is None else max(1, min(c["n_sweeps"], m // 5000))
+    sites = [int((k + 0.5) * m / n_sw) for k in range(n_sw)]
+    phis = rng.uniform(*c["phi_range"], size=n_sw)
+    for s, phi in zip(sites, phis):
+        plant_sweep_tensor(rng, alleles, pos, s, float(phi))
+    return alleles, pos, gpos, tuple(sites)
 
 
 def random_haplotypes(n_haps: int, n_sites: int, seed: int, p: float = 0.5,

@@ -174,13 +174,91 @@ int ss_xpehh(const ss_hapmat *a, const ss_hapmat *b, const ss_params *p,
 /*
  * ss_set_walk_kernel -- choose the EHH-walk kernel used by ss_ihs / ss_xpehh
  * (process-wide; results are identical, only speed differs):
- *   0 = automatic (bitmask kernel when it applies, else class ids),
- *   1 = class ids in LDS (any haplotype count),
+ *   0 = automatic (bitmask kernel when it applies, else the persistent
+ *       walk of ss_scan_batch, else class ids),
+ *   1 = class ids in LDS (any haplotype count): the plain kernel, one
+ *       workgroup per (site, direction), launched over every site,
  *   2 = class bitmasks in registers (up to 512 haplotypes in the walk,
- *       pooled for XPEHH; larger inputs use class ids).
+ *       pooled for XPEHH; larger inputs use class ids),
+ *   3 = the persistent walk of ss_scan_batch with its current configuration
+ *       (ss_set_batch_config); inputs it cannot take use class ids.
  * Errors: SS_EARG for any other value.
  */
 int ss_set_walk_kernel(int kind);
+
+/*
+ * Batched scans.  One call scans many regions -- iHS regions and XPEHH
+ * region pairs of any sizes -- and runs the EHH walks of all of them in one
+ * persistent launch: a grid sized to the GPU takes work items (region, site,
+ * direction[, core]) from a device counter, so walks of very uneven length
+ * and regions of different haplotype counts share the launch.  Every result
+ * is the one ss_ihs / ss_xpehh gives for that region alone (Sec. 1.2 and
+ * Sec. 1.3; standardization is per region).
+ */
+typedef struct ss_scan_request {
+    int32_t op;          /* SS_OP_IHS or SS_OP_XPEHH                                */
+    ss_hapmat a;         /* the haplotypes (iHS), population A (XPEHH)              */
+    ss_hapmat b;         /* population B (XPEHH only; same sites as a)              */
+    double *d_ihh_x;     /* [n_sites] iHS: iHH_1; XPEHH: iHH_A                      */
+    double *d_ihh_y;     /* [n_sites] iHS: iHH_0; XPEHH: iHH_B                      */
+    double *d_unstd;     /* [n_sites]                                               */
+    double *d_std;       /* [n_sites]                                               */
+    double *d_freq;      /* [n_sites] iHS derived frequency; ignored for XPEHH      */
+    int8_t *d_status;    /* [n_sites]                                               */
+    int32_t *d_steps;    /* NULL, or the layout of ss_ihs / ss_xpehh                */
+} ss_scan_request;
+
+/* Workspace of ss_scan_batch for these requests (0 for invalid arguments). */
+size_t ss_batch_workspace_bytes(const ss_scan_request *reqs, int32_t n_reqs,
+                                const ss_params *p);
+
+/*
+ * ss_scan_batch -- every request's scan, as one sequence on `stream`.
+ * The requests' output buffers must not overlap.  With graphs enabled
+ * (ss_set_graph) and a non-NULL stream, the sequence is captured into a HIP
+ * graph the first time a call with identical arguments is made, and replayed
+ * afterwards.
+ * Errors: SS_EARG, SS_ESHAPE, SS_EWS, SS_EDEV (with the failing request's
+ * index in ss_last_error()).
+ */
+int ss_scan_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_params *p,
+                  void *d_ws, size_t ws_bytes, void *stream);
+
+/* Launch configuration of the persistent walk (process-wide). */
+typedef struct ss_batch_config {
+    int32_t threads;        /* workgroup size: 256, 512 or 1024 (kernel 0);
+                               128, 256 or 512 (kernel 1)                               */
+    int32_t pair_cap;       /* pairs, and haplotypes, the pairwise phase holds: 0..16384 */
+    int32_t chunk;          /* work items taken per grab of the counter, >= 1            */
+    int32_t blocks_per_cu;  /* persistent workgroups per CU; 0 = as many as fit          */
+    int32_t order;          /* 0: regions in the order given; 1: most haplotypes first   */
+    int32_t small_kernel;   /* 1: regions of <= 512 haplotypes in the walk use the
+                               bitmask kernel; 0: the persistent launch takes them too  */
+    int32_t kernel;         /* 0: class ids per haplotype with a pairwise tail, one item
+                               per (site, direction) [default]; 1: per-core walks over
+                               sorted member lists, one item per (site, direction, core) */
+} ss_batch_config;
+
+int ss_get_batch_config(ss_batch_config *c);
+/* Errors: SS_EARG for a field out of range. */
+int ss_set_batch_config(const ss_batch_config *c);
+
+/*
+ * ss_autotune_batch -- time candidate configurations of the persistent walk on
+ * these requests (the walks of the first sample_items work items, or all if
+ * sample_items <= 0), keep the fastest as the process-wide configuration and
+ * return it with its time.  Blocks until the timings are done; the outputs of
+ * the requests are left undefined (run ss_scan_batch afterwards).
+ * Errors: as ss_scan_batch.
+ */
+int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_params *p,
+                      void *d_ws, size_t ws_bytes, void *stream, int64_t sample_items,
+                      ss_batch_config *best, double *best_ms);
+
+/* Graph capture of ss_scan_batch on (1) or off (0, default); ss_graph_clear
+ * destroys the cached graphs (call before freeing buffers they use). */
+int ss_set_graph(int on);
+int ss_graph_clear(void);
 
 /*
  * ss_set_mask_lanes -- tuning of the bitmask walk kernel (process-wide):

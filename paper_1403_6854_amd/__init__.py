@@ -51,6 +51,21 @@ class _HapMat(ctypes.Structure):
                 ("pos_bp", ctypes.c_void_p), ("gpos_cm", ctypes.c_void_p)]
 
 
+class _Request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("a", _HapMat), ("b", _HapMat),
+                ("d_ihh_x", ctypes.c_void_p), ("d_ihh_y", ctypes.c_void_p),
+                ("d_unstd", ctypes.c_void_p), ("d_std", ctypes.c_void_p),
+                ("d_freq", ctypes.c_void_p), ("d_status", ctypes.c_void_p),
+                ("d_steps", ctypes.c_void_p)]
+
+
+class _BatchConfig(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("pair_cap", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("small_kernel", ctypes.c_int32),
+                ("kernel", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -78,8 +93,20 @@ def lib():
         L.ss_timing_enable.argtypes = [ctypes.c_int]
         L.ss_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                      ctypes.c_int]
+        RQ = ctypes.POINTER(_Request)
+        BC = ctypes.POINTER(_BatchConfig)
+        L.ss_batch_workspace_bytes.argtypes = [RQ, ctypes.c_int32, PR]
+        L.ss_batch_workspace_bytes.restype = sz
+        L.ss_scan_batch.argtypes = [RQ, ctypes.c_int32, PR, P, sz, P]
+        L.ss_get_batch_config.argtypes = [BC]
+        L.ss_set_batch_config.argtypes = [BC]
+        L.ss_autotune_batch.argtypes = [RQ, ctypes.c_int32, PR, P, sz, P, i64, BC,
+                                        ctypes.POINTER(ctypes.c_double)]
+        L.ss_set_graph.argtypes = [ctypes.c_int]
+        L.ss_graph_clear.argtypes = []
         for f in ("ss_pack", "ss_ehh", "ss_ihs", "ss_xpehh", "ss_set_walk_kernel", "ss_set_mask_lanes",
-                  "ss_timing_enable", "ss_timing_read"):
+                  "ss_timing_enable", "ss_timing_read", "ss_scan_batch", "ss_get_batch_config",
+                  "ss_set_batch_config", "ss_autotune_batch", "ss_set_graph", "ss_graph_clear"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -300,12 +327,152 @@ def ehh(h: HapMat, core: int, params: Optional[Params] = None, cap: int = 4096,
     return out
 
 
-WALK_AUTO, WALK_LDS_IDS, WALK_REG_MASKS = 0, 1, 2
+WALK_AUTO, WALK_LDS_IDS, WALK_REG_MASKS, WALK_WIDE = 0, 1, 2, 3
 
 
 def set_walk_kernel(kind: int):
-    """Select the EHH-walk kernel (0 auto, 1 class ids in LDS, 2 register bitmasks)."""
+    """Select the EHH-walk kernel (0 auto, 1 class ids in LDS, 2 register
+    bitmasks, 3 the persistent list walk)."""
     _check(lib().ss_set_walk_kernel(int(kind)))
+
+
+# ---- batched scans ------------------------------------------------------------------
+
+@dataclasses.dataclass
+class ScanRequest:
+    """One region of a batch: iHS over ``a`` (b None) or XPEHH of a against b.
+    ``out`` holds the device outputs (allocated by :func:`alloc_outputs`)."""
+    a: HapMat
+    b: Optional[HapMat] = None
+    out: Optional[dict] = None
+
+    @property
+    def op(self) -> int:
+        return OP_IHS if self.b is None else OP_XPEHH
+
+
+def alloc_outputs(req: ScanRequest, steps: bool = False) -> dict:
+    M = req.a.n_sites
+    dev = req.a.bits.device
+    if req.b is None:
+        names = ("ihh1", "ihh0", "unstd", "std", "freq")
+    else:
+        names = ("ihhA", "ihhB", "unstd", "std")
+    out = {k: torch.empty(M, dtype=torch.float64, device=dev) for k in names}
+    out["status"] = torch.empty(M, dtype=torch.int8, device=dev)
+    if steps:
+        shape = (M, 2, 2) if req.b is None else (M, 2)
+        out["steps"] = torch.empty(shape, dtype=torch.int32, device=dev)
+    req.out = out
+    return out
+
+
+def _requests(reqs):
+    arr = (_Request * len(reqs))()
+    empty = _HapMat(None, 0, 0, 0, None, None)
+    for i, r in enumerate(reqs):
+        o = r.out
+        if o is None:
+            raise ValueError("request %d has no outputs (alloc_outputs)" % i)
+        if r.b is None:
+            x, y, f = o["ihh1"], o["ihh0"], o["freq"]
+        else:
+            x, y, f = o["ihhA"], o["ihhB"], None
+        arr[i] = _Request(r.op, r.a.desc(), r.b.desc() if r.b is not None else empty,
+                          x.data_ptr(), y.data_ptr(), o["unstd"].data_ptr(), o["std"].data_ptr(),
+                          f.data_ptr() if f is not None else None, o["status"].data_ptr(),
+                          o["steps"].data_ptr() if "steps" in o else None)
+    return arr
+
+
+def batch_workspace_bytes(reqs, params: Optional[Params] = None) -> int:
+    arr = _requests(reqs)
+    cp = _cparams(params)
+    n = lib().ss_batch_workspace_bytes(arr, len(reqs), ctypes.byref(cp))
+    if n == 0:
+        raise SelscanError(SS_EARG, lib().ss_last_error().decode() or "invalid batch")
+    return int(n)
+
+
+def scan_batch(reqs, params: Optional[Params] = None, stream=None,
+               ws: Optional[torch.Tensor] = None, validate: bool = True):
+    """Scan every request of ``reqs`` (a list of ScanRequest with outputs)
+    in one sequence; the EHH walks of all regions run in one persistent
+    launch.  Returns the workspace tensor (reuse it for the next call)."""
+    if validate:
+        for r in reqs:
+            r.a.validate()
+            if r.b is not None:
+                r.b.validate()
+                if r.a.n_sites != r.b.n_sites or not torch.equal(r.a.pos_bp, r.b.pos_bp) \
+                        or not torch.equal(r.a.gpos_cm, r.b.gpos_cm):
+                    raise ValueError("XPEHH populations must share their sites")
+    arr = _requests(reqs)
+    cp = _cparams(params)
+    nb = lib().ss_batch_workspace_bytes(arr, len(reqs), ctypes.byref(cp))
+    if nb == 0:
+        raise SelscanError(SS_EARG, lib().ss_last_error().decode() or "invalid batch")
+    dev = reqs[0].a.bits.device
+    ws = _workspace(int(nb), dev, ws)
+    base = _aligned(ws)
+    _check(lib().ss_scan_batch(arr, len(reqs), ctypes.byref(cp), ctypes.c_void_p(base),
+                               ws.numel() - (base - ws.data_ptr()), _stream(stream)))
+    return ws
+
+
+@dataclasses.dataclass
+class BatchConfig:
+    """Launch configuration of the persistent walk (see ss_batch_config)."""
+    threads: int = 512
+    pair_cap: int = 2048
+    chunk: int = 1
+    blocks_per_cu: int = 0
+    order: int = 0
+    small_kernel: int = 1
+    kernel: int = 0
+
+
+def get_batch_config() -> BatchConfig:
+    c = _BatchConfig()
+    _check(lib().ss_get_batch_config(ctypes.byref(c)))
+    return BatchConfig(c.threads, c.pair_cap, c.chunk, c.blocks_per_cu, c.order, c.small_kernel,
+                       c.kernel)
+
+
+def set_batch_config(cfg: BatchConfig):
+    c = _BatchConfig(int(cfg.threads), int(cfg.pair_cap), int(cfg.chunk), int(cfg.blocks_per_cu),
+                     int(cfg.order), int(cfg.small_kernel), int(cfg.kernel))
+    _check(lib().ss_set_batch_config(ctypes.byref(c)))
+
+
+def autotune_batch(reqs, params: Optional[Params] = None, stream=None,
+                   ws: Optional[torch.Tensor] = None, sample_items: int = 0):
+    """Time configurations of the persistent walk on these requests and keep
+    the fastest (process-wide).  Returns (BatchConfig, ms, workspace)."""
+    arr = _requests(reqs)
+    cp = _cparams(params)
+    nb = lib().ss_batch_workspace_bytes(arr, len(reqs), ctypes.byref(cp))
+    if nb == 0:
+        raise SelscanError(SS_EARG, lib().ss_last_error().decode() or "invalid batch")
+    ws = _workspace(int(nb), reqs[0].a.bits.device, ws)
+    base = _aligned(ws)
+    best = _BatchConfig()
+    ms = ctypes.c_double(0.0)
+    _check(lib().ss_autotune_batch(arr, len(reqs), ctypes.byref(cp), ctypes.c_void_p(base),
+                                   ws.numel() - (base - ws.data_ptr()), _stream(stream),
+                                   int(sample_items), ctypes.byref(best), ctypes.byref(ms)))
+    cfg = BatchConfig(best.threads, best.pair_cap, best.chunk, best.blocks_per_cu, best.order,
+                      best.small_kernel, best.kernel)
+    return cfg, float(ms.value), ws
+
+
+def set_graph(on: bool = True):
+    """Capture scan_batch sequences into HIP graphs and replay them."""
+    _check(lib().ss_set_graph(1 if on else 0))
+
+
+def graph_clear():
+    _check(lib().ss_graph_clear())
 
 
 def set_mask_lanes(lanes_per_class: int):

@@ -1,10 +1,14 @@
 // C ABI of the library (declared in include/selscan_hip.h): argument checks,
-// workspace layout, and the launch sequences of ss_ehh / ss_ihs / ss_xpehh.
-// Host code only; every step of the scans runs in the HIP kernels of
-// ss_walk.hip and ss_sites.hip.
+// workspace layout, the choice of walk kernel, and the launch sequences of
+// ss_ehh / ss_ihs / ss_xpehh / ss_scan_batch (with graph capture and the
+// autotuner of the persistent walk).  Host code only; every step of the scans
+// runs in the HIP kernels of ss_walk*.hip and ss_sites.hip.
 #include <math.h>
 #include <stdio.h>
+#include <string.h>
 
+#include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -26,6 +30,12 @@ int fail(int code, const std::string &msg) {
         hipError_t e_ = (call);                                                        \
         if (e_ != hipSuccess)                                                          \
             return fail(SS_EDEV, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+#define SS_TRY(call)                      \
+    do {                                  \
+        const int rc_ = (call);           \
+        if (rc_ != SS_OK) return rc_;     \
     } while (0)
 
 constexpr int32_t kMaxHaps = 32767;   // class sizes are packed into 15/16-bit fields
@@ -64,17 +74,30 @@ int check_hapmat(const ss_hapmat *h, const char *name) {
     return SS_OK;
 }
 
-int check_lds(size_t lds) {
+int max_lds_per_block() {
     int dev = 0, maxlds = 0;
-    SS_HIP(hipGetDevice(&dev));
-    SS_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    return maxlds;
+}
+
+int check_lds(size_t lds) {
+    const int maxlds = max_lds_per_block();
     if (lds > (size_t)maxlds)
-        return fail(SS_EDEV, "class table needs " + std::to_string(lds) +
+        return fail(SS_EDEV, "walk needs " + std::to_string(lds) +
                                  " bytes of LDS, device allows " + std::to_string(maxlds));
     return SS_OK;
 }
 
-// Workspace of the scans.
+int device_cus() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return n;
+}
+
+// Workspace of one scan.
 struct ScanWs {
     uint8_t *walk_flag;   // [M]
     int32_t *bin;         // [M]
@@ -83,13 +106,15 @@ struct ScanWs {
     int32_t *dsteps;      // [M][2][2]
     double *binstat;      // [nbins][3]
     double *binpart;      // per-tile partial sums of the bin statistics
-    uint64_t *hbits;      // [n][mwp] haplotype-major copy (iHS only)
+    uint64_t *hbits;      // [nA (+ nB)][mwp] haplotype-major copies
     double *seg;          // [M] segment lengths with the gap rules applied
     int32_t *redo;        // [1 + 2M] overflow count, then the walks to redo
+    ss::Region *region;   // [1] descriptor for the persistent walk
+    unsigned long long *counter;   // [1] its work counter
     size_t bytes;
 };
 
-ScanWs carve_scan(void *base, int64_t M, int nbins, int64_t n_hapmajor = 0) {
+ScanWs carve_scan(void *base, int64_t M, int nbins, int64_t n_hapmajor) {
     ScanWs w;
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -104,10 +129,11 @@ ScanWs carve_scan(void *base, int64_t M, int nbins, int64_t n_hapmajor = 0) {
     w.dsteps = (int32_t *)take(16 * (size_t)M);
     w.binstat = (double *)take(24 * (size_t)nbins);
     w.binpart = (double *)take(8 * (size_t)ss::standardize_scratch_doubles(M, nbins));
-    w.hbits = n_hapmajor ? (uint64_t *)take(8 * (size_t)n_hapmajor * (size_t)ss::hap_major_words(M))
-                         : nullptr;
+    w.hbits = (uint64_t *)take(8 * (size_t)n_hapmajor * (size_t)ss::hap_major_words(M));
     w.seg = (double *)take(8 * (size_t)M);
     w.redo = (int32_t *)take(4 * (1 + 2 * (size_t)M));
+    w.region = (ss::Region *)take(sizeof(ss::Region));
+    w.counter = (unsigned long long *)take(sizeof(unsigned long long));
     w.bytes = off;
     return w;
 }
@@ -150,47 +176,104 @@ hipEvent_t take_event() {
 
 int g_walk_kind = ss::WALK_AUTO;
 int g_mask_lpc = 0;   // lanes per class of the bitmask walk; 0 = default
+ss_batch_config g_bcfg = {512, 2048, 1, 0, 0, 1, 0};
+bool g_graph_on = false;
+bool g_capturing = false;   // timing events are not recorded into graphs
 
-// Automatic choice: the bitmask walk whenever the haplotypes fit (up to 512
-// in the walk), the class-id walk otherwise.
-bool use_mask_walk(int32_t nA, int32_t nB, int mode) {
-    if (g_walk_kind == ss::WALK_LDS_IDS) return false;
-    return ss::mask_walk_shape(nA, nB, mode, g_mask_lpc).ok;
+int check_batch_config(const ss_batch_config &c) {
+    if (c.kernel != 0 && c.kernel != 1) return fail(SS_EARG, "kernel must be 0 or 1");
+    if (c.kernel == 0 && c.threads != 256 && c.threads != 512 && c.threads != 1024)
+        return fail(SS_EARG, "threads must be 256, 512 or 1024 for kernel 0");
+    if (c.kernel == 1 && c.threads != 128 && c.threads != 256 && c.threads != 512)
+        return fail(SS_EARG, "threads must be 128, 256 or 512 for kernel 1");
+    if (c.pair_cap < 0 || c.pair_cap > 16384) return fail(SS_EARG, "pair_cap must be in [0, 16384]");
+    if (c.chunk < 1 || c.chunk > 4096) return fail(SS_EARG, "chunk must be in [1, 4096]");
+    if (c.blocks_per_cu < 0 || c.blocks_per_cu > 64) return fail(SS_EARG, "blocks_per_cu must be in [0, 64]");
+    if (c.order != 0 && c.order != 1) return fail(SS_EARG, "order must be 0 or 1");
+    if (c.small_kernel != 0 && c.small_kernel != 1) return fail(SS_EARG, "small_kernel must be 0 or 1");
+    return SS_OK;
 }
 
-hipError_t launch_scan_walk(const ss::WalkArgs &a, int mode, int64_t blocks, hipStream_t s) {
-    if (use_mask_walk(a.nA, a.nB, mode)) return ss::launch_mask_walk(a, mode, g_mask_lpc, blocks, s);
-    return ss::launch_walk(a, mode, false, blocks, s);
+// Launch configuration of the persistent walk for the largest list lmax and
+// the widest row wmax of its regions; false if it cannot run.
+bool make_wide_cfg(const ss_batch_config &bc, int lmax, int wmax, ss::WideCfg &c) {
+    c.kernel = bc.kernel;
+    c.threads = bc.threads;
+    c.pair_cap = bc.pair_cap;
+    c.chunk = bc.chunk;
+    c.lmax = lmax;
+    c.wmax = wmax;
+    if (bc.kernel == 0) {
+        // the member list of the pairwise tail holds as many haplotypes as
+        // there are pairs; walks with more members wait in the per-marker phase
+        c.key_cap = std::min(bc.pair_cap, 32767);
+        c.lds = ss::ids_lds_bytes(c.threads, lmax, wmax, c.pair_cap, c.key_cap);
+    } else {
+        // a pair list of P pairs holds at most ~P / 4 haplotypes in classes of
+        // a few members; walks with more wait in the per-marker phase
+        c.key_cap = std::min(std::max(256, bc.pair_cap / 4), ss::wide_max_list(bc.threads));
+        c.lds = ss::wide_lds_bytes(c.threads, lmax, wmax, c.pair_cap, c.key_cap);
+    }
+    if (c.lds == 0 || c.lds > (size_t)max_lds_per_block()) return false;
+    const int occ = bc.kernel == 0 ? ss::ids_blocks_per_cu(c) : ss::wide_blocks_per_cu(c);
+    if (occ < 1) return false;
+    const int per = bc.blocks_per_cu > 0 ? std::min(bc.blocks_per_cu, occ) : occ;
+    c.blocks = std::max(1, device_cus() * per);
+    return true;
 }
 
-// LDS needed by the walk chosen for this shape.
-size_t scan_walk_lds(int32_t nA, int32_t nB, int mode) {
-    if (use_mask_walk(nA, nB, mode)) return ss::mask_walk_shape(nA, nB, mode, g_mask_lpc).lds;
-    return ss::walk_shape(nA, nB, mode).lds;
+// Which kernel walks a scan.
+enum Route { RT_MASK, RT_WIDE, RT_IDS };
+
+int list_len(int32_t nA, int32_t nB, int mode) { return nA + (mode == ss::MODE_POOLED ? nB : 0); }
+int row_words(int32_t nA, int32_t nB, int mode) {
+    return (nA + 63) / 64 + (mode == ss::MODE_POOLED ? (nB + 63) / 64 : 0);
+}
+
+// in_batch: the bitmask kernel takes small scans only if the batch
+// configuration says so; a single scan uses it whenever it applies.
+Route route_for(int32_t nA, int32_t nB, int mode, bool in_batch) {
+    if (g_walk_kind == ss::WALK_LDS_IDS) return RT_IDS;
+    const bool mask_ok = ss::mask_walk_shape(nA, nB, mode, g_mask_lpc).ok;
+    if (g_walk_kind == ss::WALK_REG_MASKS) return mask_ok ? RT_MASK : RT_IDS;
+    if (g_walk_kind == ss::WALK_AUTO && mask_ok && (!in_batch || g_bcfg.small_kernel)) return RT_MASK;
+    ss::WideCfg c;
+    if (make_wide_cfg(g_bcfg, list_len(nA, nB, mode), row_words(nA, nB, mode), c)) return RT_WIDE;
+    return RT_IDS;
+}
+
+size_t route_lds(Route r, int32_t nA, int32_t nB, int mode) {
+    if (r == RT_MASK) return ss::mask_walk_shape(nA, nB, mode, g_mask_lpc).lds;
+    if (r == RT_IDS) return ss::walk_shape(nA, nB, mode).lds;
+    return 0;   // checked by make_wide_cfg
 }
 
 // Workgroups of the pass that redoes, with the class-id walk, the walks the
 // bitmask kernel could not hold; it exits at once when there are none.
 constexpr int kRedoBlocks = 256;
 
-int launch_timed_walk(const ss::WalkArgs &a, int mode, int64_t blocks, hipStream_t s) {
-    std::unique_lock<std::mutex> lk(g_timing.mu);
+// Events around a walk launch while timing is enabled.
+struct TimedRegion {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (g_timing.on) {
+    hipStream_t s;
+    explicit TimedRegion(hipStream_t st) : s(st) {}
+    int begin() {
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        if (!g_timing.on || g_capturing) return SS_OK;
         e0 = take_event();
         e1 = take_event();
         if (!e0 || !e1) return fail(SS_EDEV, "hipEventCreate failed");
         SS_HIP(hipEventRecord(e0, s));
+        return SS_OK;
     }
-    SS_HIP(launch_scan_walk(a, mode, blocks, s));
-    if (a.redo_count && use_mask_walk(a.nA, a.nB, mode))
-        SS_HIP(ss::launch_walk_list(a, mode, kRedoBlocks, s));
-    if (g_timing.on) {
+    int end() {
+        if (!e0) return SS_OK;
+        std::lock_guard<std::mutex> lk(g_timing.mu);
         SS_HIP(hipEventRecord(e1, s));
         g_timing.pending.emplace_back(e0, e1);
+        return SS_OK;
     }
-    return SS_OK;
-}
+};
 
 ss::WalkArgs walk_args(const ss_hapmat *a, const ss_hapmat *b, const ss_params *p) {
     ss::WalkArgs w{};
@@ -213,6 +296,323 @@ ss::WalkArgs walk_args(const ss_hapmat *a, const ss_hapmat *b, const ss_params *
     return w;
 }
 
+// ---- one scan: preparation, walk and finish -----------------------------------
+// A scan request in internal form.
+struct Scan {
+    int mode;               // MODE_CORE (iHS) or MODE_POOLED (XPEHH)
+    const ss_hapmat *a, *b;
+    double *out_x, *out_y, *unstd, *stdz, *freq;
+    int8_t *status;
+    int32_t *steps;
+    int nbins;
+    Route route;
+    ScanWs w;
+    ss::WalkArgs args;
+};
+
+int64_t hapmajor_rows(int mode, const ss_hapmat *a, const ss_hapmat *b) {
+    return a->n_haps + (mode == ss::MODE_POOLED ? b->n_haps : 0);
+}
+
+int validate_scan(int mode, const ss_hapmat *a, const ss_hapmat *b, const ss_params *p,
+                  const void *x, const void *y, const void *u, const void *z, const void *f,
+                  const void *st) {
+    if (mode == ss::MODE_CORE) {
+        SS_TRY(check_hapmat(a, "hapmat"));
+        if (!x || !y || !u || !z || !f || !st) return fail(SS_EARG, "null output pointer");
+    } else {
+        SS_TRY(check_hapmat(a, "population a"));
+        SS_TRY(check_hapmat(b, "population b"));
+        if (a->n_sites != b->n_sites) return fail(SS_ESHAPE, "populations have different n_sites");
+        if (a->n_haps + b->n_haps > kMaxHaps) return fail(SS_EARG, "n_haps(a) + n_haps(b) > 32767");
+        if (!x || !y || !u || !z || !st) return fail(SS_EARG, "null output pointer");
+    }
+    return check_params(p);
+}
+
+size_t scan_bytes(int mode, const ss_hapmat *a, const ss_hapmat *b, const ss_params *p) {
+    const int nbins = mode == ss::MODE_CORE ? nbins_of(p) : 1;
+    return carve_scan(nullptr, a->n_sites, nbins, hapmajor_rows(mode, a, b)).bytes;
+}
+
+void init_scan(Scan &sc, void *base, const ss_params *p) {
+    const int nbins = sc.mode == ss::MODE_CORE ? nbins_of(p) : 1;
+    sc.w = carve_scan(base, sc.a->n_sites, nbins, hapmajor_rows(sc.mode, sc.a, sc.b));
+    sc.args = walk_args(sc.a, sc.mode == ss::MODE_POOLED ? sc.b : nullptr, p);
+    ss::WalkArgs &a = sc.args;
+    a.walk_flag = sc.mode == ss::MODE_CORE ? sc.w.walk_flag : nullptr;
+    a.site0 = 0;
+    a.kmax = (int32_t)(list_len(a.nA, a.nB, sc.mode) / 2 + 2);
+    a.ihh = sc.w.dihh;
+    a.dstatus = sc.w.dstatus;
+    a.steps = sc.w.dsteps;
+    a.mwp = ss::hap_major_words(a.M);
+    a.hbits = sc.mode == ss::MODE_CORE ? sc.w.hbits : nullptr;
+    a.seg = sc.w.seg;
+    a.redo_count = sc.w.redo;
+    a.redo_list = sc.w.redo + 1;
+}
+
+ss::Region region_of(const Scan &sc) {
+    const ss::WalkArgs &a = sc.args;
+    ss::Region r{};
+    r.bitsA = a.bitsA;
+    r.bitsB = a.bitsB;
+    r.hbitsA = sc.w.hbits;
+    r.hbitsB = sc.mode == ss::MODE_POOLED ? sc.w.hbits + (size_t)a.nA * (size_t)a.mwp : nullptr;
+    r.seg = sc.w.seg;
+    r.walk_flag = a.walk_flag;
+    r.ihh = sc.w.dihh;
+    r.dstatus = sc.w.dstatus;
+    r.steps = sc.w.dsteps;
+    r.wpsA = a.wpsA;
+    r.wpsB = a.wpsB;
+    r.M = a.M;
+    r.mwp = a.mwp;
+    r.item0 = 0;
+    r.cutoff = a.cutoff;
+    r.nA = a.nA;
+    r.nB = sc.mode == ss::MODE_POOLED ? a.nB : 0;
+    r.mode = sc.mode;
+    return r;
+}
+
+// Per-site passes before the walk.
+int prepare_scan(const Scan &sc, const ss_params *p, hipStream_t s) {
+    const ss::WalkArgs &a = sc.args;
+    const int64_t M = a.M;
+    if (sc.mode == ss::MODE_CORE)
+        SS_HIP(ss::launch_site_stats(a.bitsA, a.wpsA, a.nA, M, p->maf_cutoff, nbins_of(p), sc.freq,
+                                     sc.w.bin, sc.w.walk_flag, sc.status, s));
+    // haplotype-major copies feed the pairwise phases
+    const bool need_a = sc.route == RT_WIDE || (sc.route == RT_MASK && sc.mode == ss::MODE_CORE);
+    const bool need_b = sc.route == RT_WIDE && sc.mode == ss::MODE_POOLED;
+    if (need_a) SS_HIP(ss::launch_transpose(a.bitsA, a.wpsA, a.nA, M, a.mwp, sc.w.hbits, s));
+    if (need_b)
+        SS_HIP(ss::launch_transpose(a.bitsB, a.wpsB, a.nB, M, a.mwp,
+                                    sc.w.hbits + (size_t)a.nA * (size_t)a.mwp, s));
+    SS_HIP(ss::launch_segments(M, a.pos, a.gpos, p->gap_scale_bp, p->max_gap_bp, sc.w.seg,
+                               sc.w.redo, s));
+    return SS_OK;
+}
+
+// Walk of a scan by the bitmask or class-id kernel (not the persistent one).
+int walk_direct(const Scan &sc, hipStream_t s) {
+    const ss::WalkArgs &a = sc.args;
+    if (sc.route == RT_MASK) {
+        SS_HIP(ss::launch_mask_walk(a, sc.mode, g_mask_lpc, a.M, s));
+        SS_HIP(ss::launch_walk_list(a, sc.mode, kRedoBlocks, s));
+    } else {
+        SS_HIP(ss::launch_walk(a, sc.mode, false, a.M, s));
+    }
+    return SS_OK;
+}
+
+int finish_scan(const Scan &sc, hipStream_t s) {
+    const int64_t M = sc.args.M;
+    SS_HIP(ss::launch_combine(sc.mode, M, sc.mode == ss::MODE_CORE ? sc.w.walk_flag : nullptr,
+                              sc.w.dihh, sc.w.dstatus, sc.w.dsteps, sc.out_x, sc.out_y, sc.unstd,
+                              sc.status, sc.steps, s));
+    if (sc.mode == ss::MODE_CORE)
+        SS_HIP(ss::launch_standardize(M, sc.unstd, sc.status, sc.w.bin, sc.nbins, sc.w.binstat,
+                                      sc.w.binpart, sc.stdz, s));
+    else
+        SS_HIP(ss::launch_standardize(M, sc.unstd, sc.status, nullptr, 1, sc.w.binstat, sc.w.binpart,
+                                      sc.stdz, s));
+    return SS_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Walk of one scan, timed when timing is enabled.
+int walk_scan(Scan &sc, hipStream_t s) {
+    if (sc.route == RT_WIDE) {
+        ss::Region r = region_of(sc);
+        const int64_t items = ss::region_items(sc.mode, sc.args.M, g_bcfg.kernel);
+        ss::WideCfg c;
+        if (!make_wide_cfg(g_bcfg, list_len(r.nA, r.nB, sc.mode), row_words(r.nA, r.nB, sc.mode), c))
+            return fail(SS_EDEV, "persistent walk does not fit this device");
+        SS_HIP(ss::launch_fill_regions(&r, 1, sc.w.region, s));
+        SS_HIP(ss::launch_zero_u64(sc.w.counter, 1, s));
+        TimedRegion t(s);
+        SS_TRY(t.begin());
+        SS_HIP(c.kernel == 0 ? ss::launch_ids_batch(sc.w.region, 1, items, sc.w.counter, c, s)
+                             : ss::launch_wide_walk(sc.w.region, 1, items, sc.w.counter, c, s));
+        return t.end();
+    }
+    TimedRegion t(s);
+    SS_TRY(t.begin());
+    SS_TRY(walk_direct(sc, s));
+    return t.end();
+}
+
+// ---- batches -------------------------------------------------------------------
+struct Batch {
+    std::vector<Scan> scans;
+    std::vector<int> wide;            // scans walked by the persistent kernel, in item order
+    std::vector<ss::Region> regions;  // their descriptors (item0 set)
+    ss::Region *d_regions = nullptr;
+    unsigned long long *d_counter = nullptr;
+    int64_t total_items = 0;
+    int lmax = 0, wmax = 0;
+};
+
+struct BatchLayout {
+    std::vector<size_t> offs;
+    size_t regions = 0, counter = 0, bytes = 0;
+};
+
+int op_mode(int32_t op) { return op == SS_OP_IHS ? ss::MODE_CORE : ss::MODE_POOLED; }
+
+int check_requests(const ss_scan_request *reqs, int32_t n, const ss_params *p) {
+    if (!reqs || n < 1) return fail(SS_EARG, "no requests");
+    if (n > 65535) return fail(SS_EARG, "more than 65535 requests");
+    SS_TRY(check_params(p));
+    for (int32_t i = 0; i < n; ++i) {
+        const ss_scan_request &r = reqs[i];
+        if (r.op != SS_OP_IHS && r.op != SS_OP_XPEHH) return fail(SS_EARG, "request " + std::to_string(i) + ": unknown op");
+        const int rc = validate_scan(op_mode(r.op), &r.a, &r.b, p, r.d_ihh_x, r.d_ihh_y, r.d_unstd,
+                                     r.d_std, r.d_freq, r.d_status);
+        if (rc != SS_OK) return fail(rc, "request " + std::to_string(i) + ": " + g_err);
+    }
+    return SS_OK;
+}
+
+BatchLayout batch_layout(const ss_scan_request *reqs, int32_t n, const ss_params *p) {
+    BatchLayout L;
+    size_t off = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        L.offs.push_back(off);
+        off += align256(scan_bytes(op_mode(reqs[i].op), &reqs[i].a, &reqs[i].b, p));
+    }
+    L.regions = off;
+    off += align256(sizeof(ss::Region) * (size_t)n);
+    L.counter = off;
+    off += 256;
+    L.bytes = off;
+    return L;
+}
+
+// Item numbering of the persistent walk's regions for a region order.
+void number_items(Batch &B, int order, int kernel) {
+    std::vector<int> idx(B.wide.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    if (order == 1) {
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+            const Scan &a = B.scans[B.wide[x]], &b = B.scans[B.wide[y]];
+            return list_len(a.args.nA, a.args.nB, a.mode) > list_len(b.args.nA, b.args.nB, b.mode);
+        });
+    }
+    B.regions.clear();
+    int64_t item = 0;
+    for (int i : idx) {
+        const Scan &sc = B.scans[B.wide[i]];
+        ss::Region r = region_of(sc);
+        r.item0 = item;
+        item += ss::region_items(sc.mode, sc.args.M, kernel);
+        B.regions.push_back(r);
+    }
+    B.total_items = item;
+}
+
+int build_batch(const ss_scan_request *reqs, int32_t n, const ss_params *p, void *d_ws,
+                size_t ws_bytes, Batch &B) {
+    SS_TRY(check_requests(reqs, n, p));
+    const BatchLayout L = batch_layout(reqs, n, p);
+    if (!d_ws || ws_bytes < L.bytes) return fail(SS_EWS, "workspace smaller than ss_batch_workspace_bytes()");
+    B.scans.resize((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        const ss_scan_request &r = reqs[i];
+        Scan &sc = B.scans[(size_t)i];
+        sc.mode = op_mode(r.op);
+        sc.a = &r.a;
+        sc.b = sc.mode == ss::MODE_POOLED ? &r.b : nullptr;
+        sc.out_x = r.d_ihh_x;
+        sc.out_y = r.d_ihh_y;
+        sc.unstd = r.d_unstd;
+        sc.stdz = r.d_std;
+        sc.freq = r.d_freq;
+        sc.status = r.d_status;
+        sc.steps = r.d_steps;
+        sc.nbins = sc.mode == ss::MODE_CORE ? nbins_of(p) : 1;
+        init_scan(sc, (char *)d_ws + L.offs[(size_t)i], p);
+        const int32_t nB = sc.mode == ss::MODE_POOLED ? (int32_t)r.b.n_haps : 0;
+        sc.route = route_for((int32_t)r.a.n_haps, nB, sc.mode, true);
+        if (sc.route != RT_WIDE) {
+            const int rc = check_lds(route_lds(sc.route, (int32_t)r.a.n_haps, nB, sc.mode));
+            if (rc != SS_OK) return fail(rc, "request " + std::to_string(i) + ": " + g_err);
+        } else {
+            B.wide.push_back(i);
+            B.lmax = std::max(B.lmax, list_len((int32_t)r.a.n_haps, nB, sc.mode));
+            B.wmax = std::max(B.wmax, row_words((int32_t)r.a.n_haps, nB, sc.mode));
+        }
+    }
+    B.d_regions = (ss::Region *)((char *)d_ws + L.regions);
+    B.d_counter = (unsigned long long *)((char *)d_ws + L.counter);
+    number_items(B, g_bcfg.order, g_bcfg.kernel);
+    return SS_OK;
+}
+
+// The persistent walk over the batch's regions (the first item_limit items
+// if item_limit >= 0).
+int launch_batch_wide(Batch &B, const ss_batch_config &bc, int64_t item_limit, hipStream_t s) {
+    if (B.wide.empty()) return SS_OK;
+    ss::WideCfg c;
+    if (!make_wide_cfg(bc, B.lmax, B.wmax, c))
+        return fail(SS_EDEV, "persistent walk configuration does not fit this device");
+    SS_HIP(ss::launch_fill_regions(B.regions.data(), (int)B.regions.size(), B.d_regions, s));
+    SS_HIP(ss::launch_zero_u64(B.d_counter, 1, s));
+    const int64_t total = item_limit >= 0 ? std::min(item_limit, B.total_items) : B.total_items;
+    SS_HIP(c.kernel == 0
+               ? ss::launch_ids_batch(B.d_regions, (int32_t)B.regions.size(), total, B.d_counter, c, s)
+               : ss::launch_wide_walk(B.d_regions, (int32_t)B.regions.size(), total, B.d_counter, c, s));
+    return SS_OK;
+}
+
+int enqueue_batch(Batch &B, const ss_params *p, hipStream_t s) {
+    for (auto &sc : B.scans) SS_TRY(prepare_scan(sc, p, s));
+    TimedRegion t(s);
+    SS_TRY(t.begin());
+    for (auto &sc : B.scans)
+        if (sc.route != RT_WIDE) SS_TRY(walk_direct(sc, s));
+    SS_TRY(launch_batch_wide(B, g_bcfg, -1, s));
+    SS_TRY(t.end());
+    for (auto &sc : B.scans) SS_TRY(finish_scan(sc, s));
+    return SS_OK;
+}
+
+// Captured graphs of ss_scan_batch, keyed by everything the sequence depends on.
+struct GraphCache {
+    std::mutex mu;
+    std::map<std::string, std::pair<hipGraph_t, hipGraphExec_t>> g;
+};
+GraphCache g_graphs;
+
+template <typename T>
+void put(std::string &k, const T &v) {
+    k.append((const char *)&v, sizeof(T));
+}
+
+std::string graph_key(const ss_scan_request *reqs, int32_t n, const ss_params *p, void *d_ws,
+                      size_t ws_bytes, void *stream) {
+    std::string k;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    put(k, dev);
+    put(k, n);
+    k.append((const char *)reqs, sizeof(ss_scan_request) * (size_t)n);
+    put(k, *p);
+    put(k, d_ws);
+    put(k, ws_bytes);
+    put(k, stream);
+    put(k, g_bcfg);
+    put(k, g_walk_kind);
+    put(k, g_mask_lpc);
+    return k;
+}
+
 }  // namespace
 
 extern "C" {
@@ -226,7 +626,7 @@ void ss_default_params(ss_params *p) {
     p->bin_width = 0.025;
 }
 
-const char *ss_version(void) { return "selscan-hip 0.1 (gfx950)"; }
+const char *ss_version(void) { return "selscan-hip 0.2 (gfx950)"; }
 
 const char *ss_last_error(void) { return g_err.c_str(); }
 
@@ -246,10 +646,10 @@ size_t ss_workspace_bytes(int op, const ss_hapmat *a, const ss_hapmat *b, const 
     if (!a || !p || check_params(p) != SS_OK) return 0;
     switch (op) {
         case SS_OP_EHH: return carve_ehh(nullptr).bytes;
-        case SS_OP_IHS: return carve_scan(nullptr, a->n_sites, nbins_of(p), a->n_haps).bytes;
+        case SS_OP_IHS: return scan_bytes(ss::MODE_CORE, a, nullptr, p);
         case SS_OP_XPEHH:
             if (!b) return 0;
-            return carve_scan(nullptr, a->n_sites, 1).bytes;
+            return scan_bytes(ss::MODE_POOLED, a, b, p);
         default: return 0;
     }
 }
@@ -258,16 +658,15 @@ int ss_ehh(const ss_hapmat *h, int64_t core, const ss_params *p, int64_t cap, ui
            double *d_ehh, int64_t *d_len, uint32_t *d_class_sizes, double *d_ihh,
            int8_t *d_status, void *d_ws, size_t ws_bytes, void *stream) {
     g_err.clear();
-    int rc;
-    if ((rc = check_hapmat(h, "hapmat")) != SS_OK) return rc;
-    if ((rc = check_params(p)) != SS_OK) return rc;
+    SS_TRY(check_hapmat(h, "hapmat"));
+    SS_TRY(check_params(p));
     if (core < 0 || core >= h->n_sites) return fail(SS_EARG, "core out of range");
     if (cap < 1 || cap > ((int64_t)1 << 30)) return fail(SS_EARG, "cap must be in [1, 2^30]");
     if (!d_S || !d_ehh || !d_len || !d_ihh || !d_status) return fail(SS_EARG, "null output pointer");
     EhhWs w = carve_ehh(d_ws);
     if (!d_ws || ws_bytes < w.bytes) return fail(SS_EWS, "workspace smaller than ss_workspace_bytes()");
     const ss::WalkShape sh = ss::walk_shape((int32_t)h->n_haps, 0, ss::MODE_CORE);
-    if ((rc = check_lds(sh.lds)) != SS_OK) return rc;
+    SS_TRY(check_lds(sh.lds));
     hipStream_t s = (hipStream_t)stream;
     SS_HIP(hipMemsetAsync(d_S, 0, sizeof(uint64_t) * 2 * (size_t)(cap + 1), s));
     if (d_class_sizes)
@@ -288,86 +687,223 @@ int ss_ehh(const ss_hapmat *h, int64_t core, const ss_params *p, int64_t cap, ui
     return SS_OK;
 }
 
+static int run_single(Scan &sc, const ss_params *p, void *d_ws, size_t ws_bytes, hipStream_t s) {
+    const size_t need = scan_bytes(sc.mode, sc.a, sc.b, p);
+    if (!d_ws || ws_bytes < need) return fail(SS_EWS, "workspace smaller than ss_workspace_bytes()");
+    sc.nbins = sc.mode == ss::MODE_CORE ? nbins_of(p) : 1;
+    init_scan(sc, d_ws, p);
+    const int32_t nB = sc.mode == ss::MODE_POOLED ? (int32_t)sc.b->n_haps : 0;
+    sc.route = route_for((int32_t)sc.a->n_haps, nB, sc.mode, false);
+    if (sc.route != RT_WIDE) SS_TRY(check_lds(route_lds(sc.route, (int32_t)sc.a->n_haps, nB, sc.mode)));
+    SS_TRY(prepare_scan(sc, p, s));
+    SS_TRY(walk_scan(sc, s));
+    return finish_scan(sc, s);
+}
+
 int ss_ihs(const ss_hapmat *h, const ss_params *p, double *d_ihh1, double *d_ihh0,
            double *d_unstd, double *d_std, double *d_freq, int8_t *d_status, int32_t *d_steps,
            void *d_ws, size_t ws_bytes, void *stream) {
     g_err.clear();
-    int rc;
-    if ((rc = check_hapmat(h, "hapmat")) != SS_OK) return rc;
-    if ((rc = check_params(p)) != SS_OK) return rc;
-    if (!d_ihh1 || !d_ihh0 || !d_unstd || !d_std || !d_freq || !d_status)
-        return fail(SS_EARG, "null output pointer");
-    const int nbins = nbins_of(p);
-    ScanWs w = carve_scan(d_ws, h->n_sites, nbins, h->n_haps);
-    if (!d_ws || ws_bytes < w.bytes) return fail(SS_EWS, "workspace smaller than ss_workspace_bytes()");
-    if ((rc = check_lds(scan_walk_lds((int32_t)h->n_haps, 0, ss::MODE_CORE))) != SS_OK) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t M = h->n_sites;
-    SS_HIP(ss::launch_site_stats(h->bits, h->words_per_site, h->n_haps, M, p->maf_cutoff, nbins,
-                                 d_freq, w.bin, w.walk_flag, d_status, s));
-    ss::WalkArgs a = walk_args(h, nullptr, p);
-    a.walk_flag = w.walk_flag;
-    a.site0 = 0;
-    a.kmax = (int32_t)(h->n_haps / 2 + 2);
-    a.ihh = w.dihh;
-    a.dstatus = w.dstatus;
-    a.steps = w.dsteps;
-    a.mwp = ss::hap_major_words(M);
-    a.hbits = w.hbits;
-    a.seg = w.seg;
-    a.redo_count = w.redo;
-    a.redo_list = w.redo + 1;
-    SS_HIP(ss::launch_transpose(h->bits, h->words_per_site, h->n_haps, M, a.mwp, w.hbits, s));
-    SS_HIP(ss::launch_segments(M, h->pos_bp, h->gpos_cm, p->gap_scale_bp, p->max_gap_bp, w.seg,
-                               w.redo, s));
-    if ((rc = launch_timed_walk(a, ss::MODE_CORE, M, s)) != SS_OK) return rc;
-    SS_HIP(ss::launch_combine(ss::MODE_CORE, M, w.walk_flag, w.dihh, w.dstatus, w.dsteps, d_ihh1,
-                              d_ihh0, d_unstd, d_status, d_steps, s));
-    SS_HIP(ss::launch_standardize(M, d_unstd, d_status, w.bin, nbins, w.binstat, w.binpart, d_std,
-                                  s));
-    return SS_OK;
+    SS_TRY(validate_scan(ss::MODE_CORE, h, nullptr, p, d_ihh1, d_ihh0, d_unstd, d_std, d_freq,
+                         d_status));
+    Scan sc{};
+    sc.mode = ss::MODE_CORE;
+    sc.a = h;
+    sc.b = nullptr;
+    sc.out_x = d_ihh1;
+    sc.out_y = d_ihh0;
+    sc.unstd = d_unstd;
+    sc.stdz = d_std;
+    sc.freq = d_freq;
+    sc.status = d_status;
+    sc.steps = d_steps;
+    return run_single(sc, p, d_ws, ws_bytes, (hipStream_t)stream);
 }
 
 int ss_xpehh(const ss_hapmat *ha, const ss_hapmat *hb, const ss_params *p, double *d_ihhA,
              double *d_ihhB, double *d_unstd, double *d_std, int8_t *d_status, int32_t *d_steps,
              void *d_ws, size_t ws_bytes, void *stream) {
     g_err.clear();
-    int rc;
-    if ((rc = check_hapmat(ha, "population a")) != SS_OK) return rc;
-    if ((rc = check_hapmat(hb, "population b")) != SS_OK) return rc;
-    if ((rc = check_params(p)) != SS_OK) return rc;
-    if (ha->n_sites != hb->n_sites) return fail(SS_ESHAPE, "populations have different n_sites");
-    if (ha->n_haps + hb->n_haps > kMaxHaps) return fail(SS_EARG, "n_haps(a) + n_haps(b) > 32767");
-    if (!d_ihhA || !d_ihhB || !d_unstd || !d_std || !d_status)
-        return fail(SS_EARG, "null output pointer");
-    ScanWs w = carve_scan(d_ws, ha->n_sites, 1);
-    if (!d_ws || ws_bytes < w.bytes) return fail(SS_EWS, "workspace smaller than ss_workspace_bytes()");
-    if ((rc = check_lds(scan_walk_lds((int32_t)ha->n_haps, (int32_t)hb->n_haps, ss::MODE_POOLED))) !=
-        SS_OK)
-        return rc;
+    SS_TRY(validate_scan(ss::MODE_POOLED, ha, hb, p, d_ihhA, d_ihhB, d_unstd, d_std, nullptr,
+                         d_status));
+    Scan sc{};
+    sc.mode = ss::MODE_POOLED;
+    sc.a = ha;
+    sc.b = hb;
+    sc.out_x = d_ihhA;
+    sc.out_y = d_ihhB;
+    sc.unstd = d_unstd;
+    sc.stdz = d_std;
+    sc.freq = nullptr;
+    sc.status = d_status;
+    sc.steps = d_steps;
+    return run_single(sc, p, d_ws, ws_bytes, (hipStream_t)stream);
+}
+
+size_t ss_batch_workspace_bytes(const ss_scan_request *reqs, int32_t n_reqs, const ss_params *p) {
+    if (check_requests(reqs, n_reqs, p) != SS_OK) return 0;
+    return batch_layout(reqs, n_reqs, p).bytes;
+}
+
+int ss_scan_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_params *p, void *d_ws,
+                  size_t ws_bytes, void *stream) {
+    g_err.clear();
+    Batch B;
+    SS_TRY(build_batch(reqs, n_reqs, p, d_ws, ws_bytes, B));
     hipStream_t s = (hipStream_t)stream;
-    const int64_t M = ha->n_sites;
-    ss::WalkArgs a = walk_args(ha, hb, p);
-    a.walk_flag = nullptr;
-    a.site0 = 0;
-    a.kmax = (int32_t)((ha->n_haps + hb->n_haps) / 2 + 2);
-    a.ihh = w.dihh;
-    a.dstatus = w.dstatus;
-    a.steps = w.dsteps;
-    a.seg = w.seg;
-    a.redo_count = w.redo;
-    a.redo_list = w.redo + 1;
-    SS_HIP(ss::launch_segments(M, ha->pos_bp, ha->gpos_cm, p->gap_scale_bp, p->max_gap_bp, w.seg,
-                               w.redo, s));
-    if ((rc = launch_timed_walk(a, ss::MODE_POOLED, M, s)) != SS_OK) return rc;
-    SS_HIP(ss::launch_combine(ss::MODE_POOLED, M, nullptr, w.dihh, w.dstatus, w.dsteps, d_ihhA,
-                              d_ihhB, d_unstd, d_status, d_steps, s));
-    SS_HIP(ss::launch_standardize(M, d_unstd, d_status, nullptr, 1, w.binstat, w.binpart, d_std, s));
+    if (!g_graph_on || !stream) return enqueue_batch(B, p, s);
+
+    const std::string key = graph_key(reqs, n_reqs, p, d_ws, ws_bytes, stream);
+    std::lock_guard<std::mutex> lk(g_graphs.mu);
+    auto it = g_graphs.g.find(key);
+    if (it == g_graphs.g.end()) {
+        SS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        g_capturing = true;
+        const int rc = enqueue_batch(B, p, s);
+        g_capturing = false;
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s, &graph);
+        if (rc != SS_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (ec != hipSuccess) return fail(SS_EDEV, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(SS_EDEV, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        }
+        it = g_graphs.g.emplace(key, std::make_pair(graph, exec)).first;
+    }
+    TimedRegion t(s);
+    SS_TRY(t.begin());
+    SS_HIP(hipGraphLaunch(it->second.second, s));
+    return t.end();
+}
+
+int ss_get_batch_config(ss_batch_config *c) {
+    if (!c) return fail(SS_EARG, "config is null");
+    *c = g_bcfg;
+    return SS_OK;
+}
+
+int ss_set_batch_config(const ss_batch_config *c) {
+    if (!c) return fail(SS_EARG, "config is null");
+    SS_TRY(check_batch_config(*c));
+    g_bcfg = *c;
+    return SS_OK;
+}
+
+int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_params *p, void *d_ws,
+                      size_t ws_bytes, void *stream, int64_t sample_items, ss_batch_config *best,
+                      double *best_ms) {
+    g_err.clear();
+    Batch B;
+    SS_TRY(build_batch(reqs, n_reqs, p, d_ws, ws_bytes, B));
+    hipStream_t s = (hipStream_t)stream;
+    for (auto &sc : B.scans) SS_TRY(prepare_scan(sc, p, s));
+    ss_batch_config cur = g_bcfg;
+    double cur_ms = 0.0;
+    if (!B.wide.empty()) {
+        const bool whole = sample_items <= 0 || sample_items >= B.total_items;
+        const int64_t limit = whole ? -1 : sample_items;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        SS_HIP(hipEventCreate(&e0));
+        SS_HIP(hipEventCreate(&e1));
+        auto time_cfg = [&](const ss_batch_config &c, double &ms) -> int {
+            ss::WideCfg wc;
+            if (!make_wide_cfg(c, B.lmax, B.wmax, wc)) {
+                ms = 1e30;
+                return SS_OK;
+            }
+            number_items(B, c.order, c.kernel);
+            double bestv = 1e30;
+            for (int rep = 0; rep < 2; ++rep) {
+                SS_HIP(hipEventRecord(e0, s));
+                SS_TRY(launch_batch_wide(B, c, limit, s));
+                SS_HIP(hipEventRecord(e1, s));
+                SS_HIP(hipEventSynchronize(e1));
+                float f = 0.f;
+                SS_HIP(hipEventElapsedTime(&f, e0, e1));
+                bestv = std::min(bestv, (double)f);
+            }
+            ms = bestv;
+            return SS_OK;
+        };
+        SS_TRY(time_cfg(cur, cur_ms));   // warm-up and baseline
+        SS_TRY(time_cfg(cur, cur_ms));
+        // kernel and workgroup size together, then one setting at a time
+        for (int k : {0, 1}) {
+            for (int t : {128, 256, 512, 1024}) {
+                ss_batch_config c = cur;
+                c.kernel = k;
+                c.threads = t;
+                if (check_batch_config(c) != SS_OK) continue;
+                double ms;
+                SS_TRY(time_cfg(c, ms));
+                if (ms < cur_ms) { cur = c; cur_ms = ms; }
+            }
+        }
+        g_err.clear();
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int pc : {0, 1024, 2048, 4096, 8192}) {
+                ss_batch_config c = cur;
+                c.pair_cap = pc;
+                double ms;
+                SS_TRY(time_cfg(c, ms));
+                if (ms < cur_ms) { cur = c; cur_ms = ms; }
+            }
+            for (int bpc : {0, 1, 2, 3, 4}) {
+                ss_batch_config c = cur;
+                c.blocks_per_cu = bpc;
+                double ms;
+                SS_TRY(time_cfg(c, ms));
+                if (ms < cur_ms) { cur = c; cur_ms = ms; }
+            }
+            for (int ch : {1, 2, 8}) {
+                ss_batch_config c = cur;
+                c.chunk = ch;
+                double ms;
+                SS_TRY(time_cfg(c, ms));
+                if (ms < cur_ms) { cur = c; cur_ms = ms; }
+            }
+            if (whole && B.wide.size() > 1) {
+                for (int o : {0, 1}) {
+                    ss_batch_config c = cur;
+                    c.order = o;
+                    double ms;
+                    SS_TRY(time_cfg(c, ms));
+                    if (ms < cur_ms) { cur = c; cur_ms = ms; }
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    g_bcfg = cur;
+    if (best) *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    return SS_OK;
+}
+
+int ss_set_graph(int on) {
+    g_graph_on = on != 0;
+    return SS_OK;
+}
+
+int ss_graph_clear(void) {
+    std::lock_guard<std::mutex> lk(g_graphs.mu);
+    for (auto &kv : g_graphs.g) {
+        (void)hipGraphExecDestroy(kv.second.second);
+        (void)hipGraphDestroy(kv.second.first);
+    }
+    g_graphs.g.clear();
     return SS_OK;
 }
 
 int ss_set_walk_kernel(int kind) {
-    if (kind < ss::WALK_AUTO || kind > ss::WALK_REG_MASKS) return fail(SS_EARG, "unknown walk kernel");
+    if (kind < ss::WALK_AUTO || kind > ss::WALK_WIDE) return fail(SS_EARG, "unknown walk kernel");
     g_walk_kind = kind;
     return SS_OK;
 }

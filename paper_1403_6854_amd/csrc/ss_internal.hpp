@@ -66,7 +66,7 @@ WalkShape walk_shape(int32_t nA, int32_t nB, int mode);
 
 // Walk kernel variants: class ids in LDS (any haplotype count) or class
 // bitmasks in registers (up to 512 haplotypes).
-enum WalkKind : int { WALK_AUTO = 0, WALK_LDS_IDS = 1, WALK_REG_MASKS = 2 };
+enum WalkKind : int { WALK_AUTO = 0, WALK_LDS_IDS = 1, WALK_REG_MASKS = 2, WALK_WIDE = 3 };
 
 // Launch shape of the register-bitmask walk: mask words per class (padded to
 // 1, 2, 4 or 8), lanes per class, rows of 64/lpc classes, LDS bytes.
@@ -84,6 +84,67 @@ hipError_t launch_mask_walk(const WalkArgs &a, int mode, int lpc, int64_t n_bloc
 hipError_t launch_walk(const WalkArgs &a, int mode, bool trace, int64_t n_blocks,
                        hipStream_t s);
 hipError_t launch_walk_list(const WalkArgs &a, int mode, int blocks, hipStream_t s);
+
+// ---- batched walks over many regions (ss_walk_wide.hip) ----------------------
+// One region of a batch: a haplotype matrix (iHS) or a pair of them (XPEHH),
+// its precomputed segment lengths and haplotype-major copies, and where its
+// per-(site, direction, core) walk results go.  The batch's work items are
+// numbered region by region: an iHS region has 4 items per site (direction,
+// core allele), an XPEHH region 2 (direction); region r owns items
+// [item0, item0 + items).
+struct Region {
+    const uint64_t *bitsA;
+    const uint64_t *bitsB;
+    const uint64_t *hbitsA;     // [nA][mwp], null: no pairwise phase
+    const uint64_t *hbitsB;     // [nB][mwp] (XPEHH)
+    const double *seg;          // [M]
+    const uint8_t *walk_flag;   // [M] or null (every site)
+    double *ihh;                // [M][2][2]
+    int32_t *dstatus;           // [M][2][2]
+    int32_t *steps;             // [M][2][2]
+    int64_t wpsA, wpsB, M, mwp;
+    int64_t item0;
+    double cutoff;
+    int32_t nA, nB, mode, pad;
+};
+
+// Items per site: the class-id batch walk takes both cores of a site in one
+// item (2 per site, one per direction); the list walk walks each iHS core
+// separately (4 per site).
+inline int64_t region_items(int mode, int64_t M, int kernel) {
+    return M * (kernel == 1 && mode == MODE_CORE ? 4 : 2);
+}
+
+// Launch configuration of the persistent wide walk.
+struct WideCfg {
+    int kernel;      // 0: class ids with a pairwise tail (ss_walk_batch.hip); 1: lists (ss_walk_wide.hip)
+    int threads;     // workgroup size: 256, 512 or 1024 (kernel 0); 128, 256 or 512 (kernel 1)
+    int pair_cap;    // pairs held by the pairwise phase
+    int key_cap;     // haplotypes whose 64-marker keys the pairwise phase holds
+    int chunk;       // items taken per grab of the work counter
+    int blocks;      // workgroups of the persistent grid
+    int lmax;        // largest haplotype list of the batch (iHS: n, XPEHH: nA + nB)
+    int wmax;        // largest row width in words (iHS: W, XPEHH: WA + WB)
+    size_t lds;      // dynamic LDS bytes
+};
+
+// LDS bytes of the wide walk for a configuration (0 if it cannot run).
+size_t wide_lds_bytes(int threads, int lmax, int wmax, int pair_cap, int key_cap);
+// Workgroups per CU the wide walk reaches with this configuration.
+int wide_blocks_per_cu(const WideCfg &c);
+// Largest haplotype list a workgroup of this size can walk.
+inline int wide_max_list(int threads) { return 64 * threads < 16384 ? 64 * threads : 16384; }
+// Class-id batch walk: slots per thread (0 if the row is too wide), LDS
+// bytes (0 if invalid), workgroups per CU, launch.
+int ids_slots(int threads, int wmax);
+size_t ids_lds_bytes(int threads, int lmax, int wmax, int pair_cap, int key_cap);
+int ids_blocks_per_cu(const WideCfg &c);
+hipError_t launch_ids_batch(const Region *regs, int32_t nreg, int64_t total_items,
+                            unsigned long long *counter, const WideCfg &c, hipStream_t s);
+hipError_t launch_fill_regions(const Region *host, int n, Region *dev, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+hipError_t launch_wide_walk(const Region *regs, int32_t nreg, int64_t total_items,
+                            unsigned long long *counter, const WideCfg &c, hipStream_t s);
 
 // Site-level kernels.
 hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps,

@@ -22,14 +22,16 @@ __global__ void __launch_bounds__(kBlock) pack_kernel(const uint8_t *__restrict_
                                                       int64_t n, int64_t M, int64_t wps,
                                                       uint64_t *__restrict__ bits) {
     const int lane = threadIdx.x & 63;
-    const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (item >= M * wps) return;
-    const int64_t site = item / wps;
-    const int64_t w = item - site * wps;
-    const int64_t h = w * 64 + lane;
-    const bool one = h < n && alleles[site * n + h] != 0;
-    const uint64_t word = __ballot(one);
-    if (lane == 0) bits[item] = word;
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); item < M * wps;
+         item += stride) {
+        const int64_t site = item / wps;
+        const int64_t w = item - site * wps;
+        const int64_t h = w * 64 + lane;
+        const bool one = h < n && alleles[site * n + h] != 0;
+        const uint64_t word = __ballot(one);
+        if (lane == 0) bits[item] = word;
+    }
 }
 
 // Haplotype-major copy of the bit matrix for the pairwise phase of the walk:
@@ -44,19 +46,21 @@ __global__ void __launch_bounds__(kBlock) transpose_kernel(const uint64_t *__res
                                                            uint64_t *__restrict__ hbits) {
     const int lane = threadIdx.x & 63;
     const int64_t words = (n + 63) / 64;
-    const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (item >= mwp * words) return;
-    const int64_t wp = item / words;          // padded block of 64 sites
-    const int64_t w = item - wp * words;      // word of 64 haplotypes
-    const int64_t site = (wp - 1) * 64 + lane;
-    const uint64_t v = (site >= 0 && site < M) ? bits[site * wps + w] : 0ull;
-    uint64_t out = 0ull;
-    for (int l = 0; l < 64; ++l) {
-        const uint64_t col = __ballot(((v >> l) & 1ull) != 0ull);
-        if (lane == l) out = col;
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); item < mwp * words;
+         item += stride) {
+        const int64_t wp = item / words;          // padded block of 64 sites
+        const int64_t w = item - wp * words;      // word of 64 haplotypes
+        const int64_t site = (wp - 1) * 64 + lane;
+        const uint64_t v = (site >= 0 && site < M) ? bits[site * wps + w] : 0ull;
+        uint64_t out = 0ull;
+        for (int l = 0; l < 64; ++l) {
+            const uint64_t col = __ballot(((v >> l) & 1ull) != 0ull);
+            if (lane == l) out = col;
+        }
+        const int64_t h = w * 64 + lane;
+        if (h < n) hbits[h * mwp + wp] = out;
     }
-    const int64_t h = w * 64 + lane;
-    if (h < n) hbits[h * mwp + wp] = out;
 }
 
 // Genetic length of every segment between neighbouring sites, with the gap
@@ -94,30 +98,33 @@ __global__ void __launch_bounds__(kBlock) site_stats_kernel(
     int32_t nbins, double *__restrict__ freq, int32_t *__restrict__ bin,
     uint8_t *__restrict__ walk_flag, int8_t *__restrict__ status) {
     const int lane = threadIdx.x & 63;
-    const int64_t site = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (site >= M) return;
     const int64_t words = (n + 63) / 64;
-    uint32_t c = 0;
-    for (int64_t w = lane; w < words; w += 64) {
-        uint64_t x = bits[site * wps + w];
-        const int64_t valid = n - w * 64;
-        if (valid < 64) x &= (1ull << valid) - 1ull;
-        c += (uint32_t)__popcll(x);
-    }
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t site = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); site < M;
+         site += stride) {
+        uint32_t c = 0;
+        for (int64_t w = lane; w < words; w += 64) {
+            uint64_t x = bits[site * wps + w];
+            const int64_t valid = n - w * 64;
+            if (valid < 64) x &= (1ull << valid) - 1ull;
+            c += (uint32_t)__popcll(x);
+        }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    if (lane != 0) return;
-    const int64_t n1 = c, n0 = n - n1;
-    freq[site] = (double)n1 / (double)n;
-    int64_t b = ((int64_t)nbins * n1) / n;
-    if (b > nbins - 1) b = nbins - 1;
-    bin[site] = (int32_t)b;
-    const double maf = (double)(n0 < n1 ? n0 : n1) / (double)n;
-    int8_t st = ST_OK;
-    if (maf < maf_cutoff) st = ST_MAF;
-    else if (n0 < 2 || n1 < 2) st = ST_UNDEF;
-    status[site] = st;
-    walk_flag[site] = st == ST_OK ? 1 : 0;
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+        if (lane == 0) {
+            const int64_t n1 = c, n0 = n - n1;
+            freq[site] = (double)n1 / (double)n;
+            int64_t b = ((int64_t)nbins * n1) / n;
+            if (b > nbins - 1) b = nbins - 1;
+            bin[site] = (int32_t)b;
+            const double maf = (double)(n0 < n1 ? n0 : n1) / (double)n;
+            int8_t st = ST_OK;
+            if (maf < maf_cutoff) st = ST_MAF;
+            else if (n0 < 2 || n1 < 2) st = ST_UNDEF;
+            status[site] = st;
+            walk_flag[site] = st == ST_OK ? 1 : 0;
+        }
+    }
 }
 
 // iHH = downstream sum + upstream sum (Eq. 4 / Eq. 7); the locus status is the
@@ -330,10 +337,18 @@ __global__ void ehh_finish_kernel(int64_t n, int64_t cap, const uint64_t *__rest
 
 }  // namespace
 
+// Grids of the wave-per-item kernels are capped (they loop over their items):
+// one launch may not exceed 2^32 work items in x.
+constexpr int64_t kMaxBlocks = 1 << 20;
+
+static int64_t wave_blocks(int64_t items) {
+    const int64_t b = (items + kBlock / 64 - 1) / (kBlock / 64);
+    return b < kMaxBlocks ? (b > 0 ? b : 1) : kMaxBlocks;
+}
+
 hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps,
                        uint64_t *bits, hipStream_t s) {
-    const int64_t items = M * wps;
-    const int64_t blocks = (items + kBlock / 64 - 1) / (kBlock / 64);
+    const int64_t blocks = wave_blocks(M * wps);
     hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, alleles, n, M,
                        wps, bits);
     return hipGetLastError();
@@ -349,8 +364,7 @@ hipError_t launch_segments(int64_t M, const int64_t *pos, const double *gpos, in
 
 hipError_t launch_transpose(const uint64_t *bits, int64_t wps, int64_t n, int64_t M, int64_t mwp,
                             uint64_t *hbits, hipStream_t s) {
-    const int64_t items = mwp * ((n + 63) / 64);
-    const int64_t blocks = (items + kBlock / 64 - 1) / (kBlock / 64);
+    const int64_t blocks = wave_blocks(mwp * ((n + 63) / 64));
     hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, bits, wps, n, M,
                        mwp, hbits);
     return hipGetLastError();
@@ -359,7 +373,7 @@ hipError_t launch_transpose(const uint64_t *bits, int64_t wps, int64_t n, int64_
 hipError_t launch_site_stats(const uint64_t *bits, int64_t wps, int64_t n, int64_t M,
                              double maf_cutoff, int32_t nbins, double *freq, int32_t *bin,
                              uint8_t *walk_flag, int8_t *status, hipStream_t s) {
-    const int64_t blocks = (M + kBlock / 64 - 1) / (kBlock / 64);
+    const int64_t blocks = wave_blocks(M);
     hipLaunchKernelGGL(site_stats_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, bits, wps,
                        n, M, maf_cutoff, nbins, freq, bin, walk_flag, status);
     return hipGetLastError();

@@ -1,0 +1,780 @@
+// EHH walks of a batch of regions in one persistent launch: class ids per
+// haplotype, a pairwise tail for long walks, and a device work counter.
+//
+// What it computes is the partition refinement of ss_walk.hip (Sec. 1.1,
+// Eqs. 1-3; Sec. 1.2, Eq. 4 and the rules below it; Sec. 1.3, Eq. 7 for the
+// pooled XPEHH walk) with the same FP64 arithmetic in the same order.  Work
+// items are (region, site, direction); both core alleles of an iHS site share
+// one partition (Eq. 2), as in the plain kernel.
+//
+// Per item one workgroup of T threads:
+//   * slot r of wave w holds the 64 haplotypes of word w + r * (T / 64) of the
+//     marker rows; lane l's allele is bit l of the row word, its class id a
+//     register.  Per marker the members with allele 1 count into their
+//     class's LDS counter -- one atomic per word when all live lanes of the
+//     word share a class (a large class of identical haplotypes costs one
+//     atomic per 64 members) -- then one pass over the classes makes the
+//     children, drops those with < 2 members (and the classes of a core whose
+//     walk has stopped), gives the survivors dense ids, and sums C(., 2);
+//   * once the identical pairs left (the iHS cores' pairs, or the pooled
+//     pairs of XPEHH) number at most the pair capacity, the live classes are
+//     expanded into the list of those pairs and each pass covers 64 markers:
+//     XOR of the pair's 64-marker keys from the haplotype-major copy, lowest
+//     set bit = the marker where the pair splits, per-type 64-bin histograms
+//     give S at each marker of the pass;
+//   * the grid is persistent: each workgroup takes the next `chunk` items from
+//     a global counter until the batch is done, so walks of very different
+//     lengths and regions of different sizes balance across the GPU.
+#include "ss_internal.hpp"
+
+namespace ss {
+
+namespace {
+
+constexpr int32_t DEAD = -1;
+constexpr int kBig = 1 << 30;
+
+__device__ __forceinline__ uint32_t choose2(uint32_t x) { return (x * (x - 1u)) >> 1; }
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return __ockl_wfred_add_u32(v); }
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int i) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, i);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), i);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int i) {
+    return __builtin_bit_cast(double, readlane64(__builtin_bit_cast(uint64_t, v), i));
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint32_t wave_prefix(uint32_t v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+__host__ __device__ inline uint64_t low_bits(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
+
+__device__ __forceinline__ uint64_t key_of(const uint64_t *hb, int64_t mwp, int h, int64_t k0,
+                                           int dir) {
+    const uint64_t *row = hb + (size_t)h * (size_t)mwp;
+    const int64_t b = dir > 0 ? k0 + 64 : k0 + 1;   // padded index of the lowest marker
+    const int64_t wi = b >> 6;
+    const int sh = (int)(b & 63);
+    const uint64_t lo = wi < mwp ? row[wi] : 0ull;
+    const uint64_t hi = wi + 1 < mwp ? row[wi + 1] : 0ull;
+    const uint64_t x = sh ? ((lo >> sh) | (hi << (64 - sh))) : lo;
+    return dir > 0 ? x : __builtin_bitreverse64(x);
+}
+
+// Exclusive workgroup sum (u64); wtot holds one total per wave.
+__device__ __forceinline__ uint64_t block_excl_sum(uint64_t v, uint64_t *wtot, uint64_t &total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t a = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += a;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    uint64_t off = 0, all = 0;
+    const int nw = (int)(blockDim.x >> 6);
+    for (int w = 0; w < nw; ++w) {
+        const uint64_t s = wtot[w];
+        all += s;
+        if (w < wave) off += s;
+    }
+    total = all;
+    return off + inc - v;
+}
+
+// LDS layout (byte offsets).  The class table lives until the pair list is
+// built; keys, the second pair buffer and the histograms then reuse it.
+struct BLay {
+    uint32_t cnt1, szv0, szv1, map, sacc, knext, init, wtot, mem, pairs0;
+    uint32_t keys, pairs1, hist, pcnt, total;
+    int kmax;
+};
+
+__host__ __device__ inline uint32_t al16(uint32_t x) { return (x + 15u) & ~15u; }
+
+__host__ __device__ inline BLay batch_layout(int lmax, int pcap, int kcap) {
+    BLay l;
+    l.kmax = lmax / 2 + 2;
+    const uint32_t K = (uint32_t)l.kmax;
+    uint32_t o = 0;
+    l.cnt1 = o;  o += 4u * K;
+    l.szv0 = o;  o += 4u * K;
+    l.szv1 = o;  o += 4u * K;
+    l.map = o;   o += 8u * K;
+    l.sacc = o;  o += 32u;
+    l.knext = o; o += 8u;
+    l.init = o;  o += 8u;
+    o = al16(o);
+    const uint32_t table_end = o;
+    // reuses the class table once the pair list exists
+    uint32_t v = 0;
+    l.keys = v;   v = al16(v + 8u * (uint32_t)kcap);
+    l.pairs1 = v; v = al16(v + 4u * (uint32_t)pcap);
+    l.hist = v;   v = al16(v + 4u * 3u * 64u);
+    l.pcnt = v;   v = al16(v + 16u);
+    o = table_end > v ? table_end : v;
+    l.wtot = o;   o = al16(o + 8u * 16u);
+    l.mem = o;    o = al16(o + 2u * (uint32_t)kcap);
+    l.pairs0 = o; o = al16(o + 4u * (uint32_t)pcap);
+    l.total = o;
+    return l;
+}
+
+template <int MODE, int R>
+__device__ void ids_walk(const Region &G, int64_t j, int d, char *base, const BLay &Ly, int pcap,
+                         int kcap) {
+    const int T = (int)blockDim.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wpg = T >> 6;
+    const int dir = d == 0 ? 1 : -1;
+    const int nA = G.nA, nB = MODE == MODE_POOLED ? G.nB : 0;
+    const int WA = (nA + 63) >> 6, WB = MODE == MODE_POOLED ? (nB + 63) >> 6 : 0;
+    const int kmax = Ly.kmax;
+
+    uint32_t *cnt1 = (uint32_t *)(base + Ly.cnt1);
+    uint32_t *szv0 = (uint32_t *)(base + Ly.szv0);
+    uint32_t *szv1 = (uint32_t *)(base + Ly.szv1);
+    int32_t *map = (int32_t *)(base + Ly.map);
+    uint32_t *sacc = (uint32_t *)(base + Ly.sacc);
+    int32_t *knext = (int32_t *)(base + Ly.knext);
+    uint32_t *init = (uint32_t *)(base + Ly.init);
+
+    for (int i = tid; i < kmax; i += T) cnt1[i] = 0u;
+    if (tid < 8) sacc[tid] = 0u;
+    if (tid < 2) {
+        knext[tid] = 0;
+        init[tid] = 0u;
+    }
+
+    // slot r: 64-haplotype word wave + r * wpg of the pooled word space
+    const uint64_t *src[R];
+    int64_t stride[R];
+    uint32_t incu[R];   // per-slot increment of the class counters (A: 1, B: 1 << 16)
+    int32_t cls[R];
+    bool word[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int wq = wave + r * wpg;
+        bool valid;
+        if (wq < WA) {
+            src[r] = G.bitsA + wq;
+            stride[r] = G.wpsA;
+            valid = wq * 64 + lane < nA;
+            incu[r] = 1u;
+            word[r] = true;
+        } else if (MODE == MODE_POOLED && wq < WA + WB) {
+            src[r] = G.bitsB + (wq - WA);
+            stride[r] = G.wpsB;
+            valid = (wq - WA) * 64 + lane < nB;
+            incu[r] = 0x10000u;
+            word[r] = true;
+        } else {
+            src[r] = G.bitsA;
+            stride[r] = 0;
+            valid = false;
+            incu[r] = 0u;
+            word[r] = false;
+        }
+        cls[r] = valid ? 0 : DEAD;
+    }
+    __syncthreads();
+
+    // classes at x0: id = allele
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (word[r]) {
+            const uint64_t w = src[r][j * stride[r]];
+            const int32_t bit = (int32_t)((w >> lane) & 1ull);
+            if (cls[r] != DEAD) {
+                cls[r] = bit;
+                atomicAdd(&init[bit], incu[r]);
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t i0 = init[0], i1 = init[1];
+
+    bool act0, act1;
+    double ihh0 = 0.0, ihh1 = 0.0, ep0, ep1, P0, P1, PP = 1.0;
+    int32_t steps0 = 0, steps1 = 0;
+    uint32_t sa0, sa1, sa2 = 0;   // S after the last marker (iHS: cores 0, 1; XPEHH: A, B, pooled)
+    if (MODE == MODE_CORE) {
+        const uint32_t n0 = i0 & 0xFFFFu, n1 = i1 & 0xFFFFu;
+        P0 = (double)choose2(n0);
+        P1 = (double)choose2(n1);
+        act0 = n0 >= 2u;
+        act1 = n1 >= 2u;
+        ep0 = 1.0;
+        ep1 = 1.0;
+        sa0 = choose2(n0);
+        sa1 = choose2(n1);
+        if (tid == 0) {
+            szv0[0] = n0;
+            szv0[1] = n1 | 0x80000000u;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (cls[r] == 0 && n0 < 2u) cls[r] = DEAD;
+            if (cls[r] == 1 && n1 < 2u) cls[r] = DEAD;
+        }
+    } else {
+        const uint32_t a0 = i0 & 0xFFFFu, b0 = i0 >> 16, a1 = i1 & 0xFFFFu, b1 = i1 >> 16;
+        P0 = (double)choose2((uint32_t)nA);
+        P1 = (double)choose2((uint32_t)nB);
+        PP = (double)choose2((uint32_t)(nA + nB));
+        // x0 is part of the haplotype: each population's curve starts at its
+        // whole-sample EHH at x0
+        ep0 = (double)(choose2(a0) + choose2(a1)) / P0;
+        ep1 = (double)(choose2(b0) + choose2(b1)) / P1;
+        act0 = true;
+        act1 = false;
+        sa0 = choose2(a0) + choose2(a1);
+        sa1 = choose2(b0) + choose2(b1);
+        sa2 = choose2(a0 + b0) + choose2(a1 + b1);
+        if (tid == 0) {
+            szv0[0] = i0;
+            szv0[1] = i1;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (cls[r] == 0 && a0 + b0 < 2u) cls[r] = DEAD;
+            if (cls[r] == 1 && a1 + b1 < 2u) cls[r] = DEAD;
+        }
+    }
+    __syncthreads();
+
+    const bool can_pair = pcap > 0 && G.hbitsA != nullptr &&
+                          (MODE == MODE_CORE || G.hbitsB != nullptr);
+    int32_t K = 2;
+    int32_t status = ST_OK;
+    int step = 0;
+    bool pmode = false;
+    while (act0 || act1) {
+        // stage the next 64 markers: lane i holds the row words and the
+        // segment of step (step + 1 + i)
+        const int64_t kb = j + (int64_t)dir * (int64_t)(step + 1 + lane);
+        const bool inr = kb >= 0 && kb < G.M;
+        uint64_t rowv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) rowv[r] = (word[r] && inr) ? src[r][kb * stride[r]] : 0ull;
+        int32_t stl = ST_OK;
+        double gl = 0.0;
+        if (!inr) {
+            stl = ST_EDGE;
+        } else {
+            const double sv = G.seg[dir > 0 ? kb : kb + 1];
+            if (sv < 0.0) stl = ST_GAP;
+            else gl = sv;
+        }
+        const uint64_t abort_mask = __ballot(stl != ST_OK);
+        const int nb = abort_mask ? (int)__builtin_ctzll(abort_mask) : 64;
+        const int32_t abort_st = abort_mask ? (int32_t)__builtin_amdgcn_readlane(stl, nb) : ST_OK;
+
+        for (int i = 0; i < 64 && (act0 || act1); ++i) {
+            if (i == nb) {
+                status = abort_st;
+                goto done;
+            }
+            const double g = readlane_f64(gl, i);
+            const int par = step & 1;
+            uint32_t *szc = par ? szv1 : szv0;
+            uint32_t *szn = par ? szv0 : szv1;
+            uint32_t *sa = sacc + 4 * par;
+            int32_t *kn = knext + par;
+
+            // (1) ones per class; one atomic per word when its live lanes share a class
+            int32_t bit[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                bit[r] = 0;
+                if (word[r]) {
+                    const uint64_t w = readlane64(rowv[r], i);
+                    bit[r] = (int32_t)((w >> lane) & 1ull);
+                    const bool live = cls[r] != DEAD;
+                    const uint64_t lm = __ballot(live);
+                    if (lm) {
+                        const int first = (int)__builtin_ctzll(lm);
+                        const int32_t c0 = __builtin_amdgcn_readlane(cls[r], first);
+                        const uint64_t other = __ballot(live && cls[r] != c0);
+                        if (!other) {
+                            const uint32_t ones = (uint32_t)__popcll(__ballot(live && bit[r]));
+                            if (lane == first && ones) atomicAdd(&cnt1[c0], ones * incu[r]);
+                        } else if (live && bit[r]) {
+                            atomicAdd(&cnt1[cls[r]], incu[r]);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+
+            // (2) split every class, keep children with >= 2 members
+            for (int c0 = 0; c0 < K; c0 += T) {
+                const int c = c0 + tid;
+                const bool in = c < K;
+                uint32_t one = 0u, sz = 0u;
+                if (in) {
+                    one = cnt1[c];
+                    cnt1[c] = 0u;
+                    sz = szc[c];
+                }
+                bool keepz = false, keepo = false;
+                uint32_t wz = 0u, wo = 0u;
+                uint32_t s0 = 0u, s1 = 0u, s2 = 0u, s3 = 0u;   // s3: members kept
+                if (in) {
+                    if (MODE == MODE_CORE) {
+                        const uint32_t core = sz >> 31;
+                        const uint32_t n = sz & 0xFFFFu;
+                        const uint32_t o = one, z = n - one;
+                        const bool live = core ? act1 : act0;
+                        const uint32_t sc = choose2(o) + choose2(z);
+                        if (core) s1 = sc;
+                        else s0 = sc;
+                        keepz = live && z >= 2u;
+                        keepo = live && o >= 2u;
+                        s3 = (keepz ? z : 0u) + (keepo ? o : 0u);
+                        wz = z | (core << 31);
+                        wo = o | (core << 31);
+                    } else {
+                        const uint32_t nAc = sz & 0xFFFFu, nBc = sz >> 16;
+                        const uint32_t oA = one & 0xFFFFu, oB = one >> 16;
+                        const uint32_t zA = nAc - oA, zB = nBc - oB;
+                        s0 = choose2(oA) + choose2(zA);
+                        s1 = choose2(oB) + choose2(zB);
+                        s2 = choose2(oA + oB) + choose2(zA + zB);
+                        keepz = zA + zB >= 2u;
+                        keepo = oA + oB >= 2u;
+                        s3 = (keepz ? zA + zB : 0u) + (keepo ? oA + oB : 0u);
+                        wz = zA | (zB << 16);
+                        wo = oA | (oB << 16);
+                    }
+                }
+                const uint64_t bz = __ballot(keepz);
+                const uint64_t bo = __ballot(keepo);
+                const int nz = __popcll(bz), no = __popcll(bo);
+                int basei = 0;
+                if (lane == 0 && nz + no > 0) basei = atomicAdd(kn, nz + no);
+                basei = __shfl(basei, 0, 64);
+                const int idz = basei + (int)lanes_below(bz);
+                const int ido = basei + nz + (int)lanes_below(bo);
+                if (in) {
+                    map[2 * c] = keepz ? idz : DEAD;
+                    map[2 * c + 1] = keepo ? ido : DEAD;
+                }
+                if (keepz) szn[idz] = wz;
+                if (keepo) szn[ido] = wo;
+                s0 = wave_sum(s0);
+                s1 = wave_sum(s1);
+                if (MODE == MODE_POOLED) s2 = wave_sum(s2);
+                if (can_pair) s3 = wave_sum(s3);
+                if (lane == 0) {
+                    if (s0) atomicAdd(&sa[0], s0);
+                    if (s1) atomicAdd(&sa[1], s1);
+                    if (MODE == MODE_POOLED && s2) atomicAdd(&sa[2], s2);
+                    if (s3) atomicAdd(&sa[3], s3);
+                }
+            }
+            __syncthreads();
+
+            // (3) new class ids
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (cls[r] != DEAD) cls[r] = map[2 * cls[r] + bit[r]];
+            K = kn[0];
+            const uint32_t S0 = sa[0], S1 = sa[1], S2 = sa[2], members = sa[3];
+            if (tid == 0) {
+                uint32_t *other = sacc + 4 * (par ^ 1);
+                other[0] = other[1] = other[2] = other[3] = 0u;
+                knext[par ^ 1] = 0;
+            }
+            step += 1;
+
+            if (MODE == MODE_CORE) {
+                if (act0) {
+                    steps0 += 1;
+                    const double e = (double)S0 / P0;
+                    if (e < G.cutoff) {
+                        act0 = false;
+                    } else {
+                        ihh0 += 0.5 * (ep0 + e) * g;
+                        ep0 = e;
+                    }
+                }
+                if (act1) {
+                    steps1 += 1;
+                    const double e = (double)S1 / P1;
+                    if (e < G.cutoff) {
+                        act1 = false;
+                    } else {
+                        ihh1 += 0.5 * (ep1 + e) * g;
+                        ep1 = e;
+                    }
+                }
+                sa0 = S0;
+                sa1 = S1;
+            } else {
+                steps0 += 1;
+                if ((double)S2 / PP < G.cutoff) {
+                    act0 = false;
+                } else {
+                    const double eA = (double)S0 / P0;
+                    const double eB = (double)S1 / P1;
+                    ihh0 += 0.5 * (ep0 + eA) * g;
+                    ihh1 += 0.5 * (ep1 + eB) * g;
+                    ep0 = eA;
+                    ep1 = eB;
+                }
+                sa0 = S0;
+                sa1 = S1;
+                sa2 = S2;
+            }
+            // pairwise tail once few identical pairs are left
+            if (can_pair && (act0 || act1)) {
+                const uint32_t left = MODE == MODE_CORE ? (act0 ? S0 : 0u) + (act1 ? S1 : 0u) : S2;
+                if (left <= (uint32_t)pcap && members <= (uint32_t)kcap) {
+                    pmode = true;
+                    goto pairs;
+                }
+            }
+        }
+    }
+    goto done;
+
+pairs : {
+    // ---- build the list of identical pairs from the live classes ----------------
+    // classes of a stopped core are still in the table; they are skipped
+    __syncthreads();
+    const int par = step & 1;
+    uint32_t *szc = par ? szv1 : szv0;     // sizes of the current classes
+    uint32_t *sbase = par ? szv0 : szv1;   // member offset of each class
+    uint64_t *wtot = (uint64_t *)(base + Ly.wtot);
+    uint16_t *mem = (uint16_t *)(base + Ly.mem);
+    uint32_t *pr0 = (uint32_t *)(base + Ly.pairs0);
+    auto csize = [&](int c, uint32_t &tag) -> uint32_t {
+        const uint32_t sz = szc[c];
+        if (MODE == MODE_CORE) {
+            const uint32_t core = sz >> 31;
+            tag = core;
+            const bool live = core ? act1 : act0;
+            return live ? (sz & 0xFFFFu) : 0u;
+        }
+        tag = 0u;
+        return (sz & 0xFFFFu) + (sz >> 16);
+    };
+    const int KT = (K + T - 1) / T;
+    uint64_t loc = 0;
+    for (int q = 0; q < KT; ++q) {
+        const int c = tid * KT + q;
+        if (c < K) {
+            uint32_t tg;
+            const uint64_t n = csize(c, tg);
+            if (n >= 2) loc += n | ((uint64_t)(n * (n - 1) / 2) << 32);
+        }
+    }
+    uint64_t tot;
+    uint64_t ex = block_excl_sum(loc, wtot, tot);
+    for (int q = 0; q < KT; ++q) {
+        const int c = tid * KT + q;
+        if (c < K) {
+            uint32_t tg;
+            const uint64_t n = csize(c, tg);
+            const uint32_t mo = (uint32_t)ex, po = (uint32_t)(ex >> 32);
+            sbase[c] = mo;
+            cnt1[c] = mo;              // scatter cursor
+            map[c] = (int32_t)po;      // pair offset
+            if (n >= 2) ex += n | ((uint64_t)(n * (n - 1) / 2) << 32);
+        }
+    }
+    const int L = (int)(uint32_t)tot;
+    const int npairs0 = (int)(tot >> 32);
+    __syncthreads();
+    // members into their class's range of the member list
+    int32_t mypos[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        mypos[r] = -1;
+        if (cls[r] != DEAD) {
+            uint32_t tg;
+            if (csize(cls[r], tg) >= 2u) {
+                const int wq = wave + r * wpg;
+                const int h = wq < WA ? wq * 64 + lane : (0x8000 | ((wq - WA) * 64 + lane));
+                const int p = (int)atomicAdd(&cnt1[cls[r]], 1u);
+                mem[p] = (uint16_t)h;
+                mypos[r] = p;
+            }
+        }
+    }
+    __syncthreads();
+    // member at rank p of its class writes its p pairs with the earlier members
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (mypos[r] >= 0) {
+            const int c = cls[r];
+            uint32_t tg;
+            (void)csize(c, tg);
+            const int s = (int)sbase[c];
+            const int p = mypos[r] - s;
+            const uint32_t y = (uint32_t)mypos[r];
+            uint32_t out = (uint32_t)map[c] + (uint32_t)(p * (p - 1) / 2);
+            const uint32_t ty = MODE == MODE_CORE ? (tg << 15) : (uint32_t)(mem[y] & 0x8000u);
+            for (int x = s; x < s + p; ++x) {
+                const uint32_t tx = MODE == MODE_CORE ? (tg << 15) : (uint32_t)(mem[x] & 0x8000u);
+                pr0[out++] = (uint32_t)x | tx | ((y | ty) << 16);
+            }
+        }
+    }
+
+    // ---- one pass over the pair list per 64 markers ----------------------------
+    int npairs = npairs0;
+    int pb = 0;
+    uint64_t *keys = (uint64_t *)(base + Ly.keys);
+    uint32_t *hist = (uint32_t *)(base + Ly.hist);
+    uint32_t *pcnt = (uint32_t *)(base + Ly.pcnt);
+    uint32_t *pr1 = (uint32_t *)(base + Ly.pairs1);
+    while (act0 || act1) {
+        uint32_t *pin = pb ? pr1 : pr0;
+        uint32_t *pout = pb ? pr0 : pr1;
+        __syncthreads();   // pair list complete; the last pass's counts read
+        const int64_t k0 = j + (int64_t)dir * (int64_t)(step + 1);
+        for (int x = tid; x < L; x += T) {
+            const int h = mem[x];
+            keys[x] = (h & 0x8000) ? key_of(G.hbitsB, G.mwp, h & 0x7FFF, k0, dir)
+                                   : key_of(G.hbitsA, G.mwp, h, k0, dir);
+        }
+        for (int x = tid; x < 3 * 64; x += T) hist[x] = 0u;
+        if (tid == 0) *pcnt = 0u;
+        const int64_t kb = k0 + (int64_t)dir * (int64_t)lane;
+        const bool inr = kb >= 0 && kb < G.M;
+        const double sv = inr ? G.seg[dir > 0 ? kb : kb + 1] : 0.0;
+        const int32_t stl = !inr ? ST_EDGE : (sv < 0.0 ? ST_GAP : ST_OK);
+        const double gl = stl == ST_OK ? sv : 0.0;
+        const uint64_t abort_mask = __ballot(stl != ST_OK);
+        const int nb = abort_mask ? (int)__builtin_ctzll(abort_mask) : 64;
+        const int32_t abort_st = abort_mask ? (int32_t)__builtin_amdgcn_readlane(stl, nb) : ST_OK;
+        __syncthreads();
+        for (int p0 = (tid & ~63); p0 < npairs; p0 += T) {
+            const int p = p0 + lane;
+            const bool in = p < npairs;
+            const uint32_t pr = in ? pin[p] : 0u;
+            const uint64_t x = keys[pr & 0x7FFFu] ^ keys[(pr >> 16) & 0x7FFFu];
+            const int Lx = x ? (int)__builtin_ctzll(x) : 64;
+            if (in && Lx < 64) {
+                if (MODE == MODE_CORE) {
+                    atomicAdd(&hist[((pr >> 15) & 1u) * 64 + Lx], 1u);
+                } else {
+                    atomicAdd(&hist[Lx], 1u);
+                    const uint32_t tb = ((pr >> 15) & 1u) + ((pr >> 31) & 1u);
+                    if (tb == 0u) atomicAdd(&hist[64 + Lx], 1u);
+                    else if (tb == 2u) atomicAdd(&hist[128 + Lx], 1u);
+                }
+            }
+            const bool surv = in && Lx == 64;
+            const uint64_t sm = __ballot(surv);
+            uint32_t wo = 0u;
+            if (lane == 0 && sm) wo = atomicAdd(pcnt, (uint32_t)__popcll(sm));
+            wo = (uint32_t)__shfl((int)wo, 0, 64);
+            if (surv) pout[wo + __popcll(sm & low_bits(lane))] = pr;
+        }
+        __syncthreads();
+        const uint64_t valid = low_bits(nb);
+        const int lim = nb < 64 ? nb : 64;
+        if (MODE == MODE_CORE) {
+            // each core stops at its own first sub-cutoff marker of the pass
+            const uint32_t si0 = sa0 - wave_prefix(hist[lane], lane);
+            const uint32_t si1 = sa1 - wave_prefix(hist[64 + lane], lane);
+            if (act0) {
+                const uint64_t sm = __ballot((double)si0 / P0 < G.cutoff) & valid;
+                const int nterm = sm ? (int)__builtin_ctzll(sm) : lim;
+                steps0 += sm ? nterm + 1 : lim;
+                if (nterm > 0) {
+                    const double e = (double)si0 / P0;
+                    double prev = __shfl_up(e, 1, 64);
+                    if (lane == 0) prev = ep0;
+                    const double term = 0.5 * (prev + e) * gl;
+                    for (int t = 0; t < nterm; ++t) ihh0 += readlane_f64(term, t);
+                    ep0 = readlane_f64(e, nterm - 1);
+                }
+                if (sm) act0 = false;
+            }
+            if (act1) {
+                const uint64_t sm = __ballot((double)si1 / P1 < G.cutoff) & valid;
+                const int nterm = sm ? (int)__builtin_ctzll(sm) : lim;
+                steps1 += sm ? nterm + 1 : lim;
+                if (nterm > 0) {
+                    const double e = (double)si1 / P1;
+                    double prev = __shfl_up(e, 1, 64);
+                    if (lane == 0) prev = ep1;
+                    const double term = 0.5 * (prev + e) * gl;
+                    for (int t = 0; t < nterm; ++t) ihh1 += readlane_f64(term, t);
+                    ep1 = readlane_f64(e, nterm - 1);
+                }
+                if (sm) act1 = false;
+            }
+            sa0 = (uint32_t)__builtin_amdgcn_readlane(si0, 63);
+            sa1 = (uint32_t)__builtin_amdgcn_readlane(si1, 63);
+        } else {
+            const uint32_t siP = sa2 - wave_prefix(hist[lane], lane);
+            const uint32_t siA = sa0 - wave_prefix(hist[64 + lane], lane);
+            const uint32_t siB = sa1 - wave_prefix(hist[128 + lane], lane);
+            const uint64_t sm = __ballot((double)siP / PP < G.cutoff) & valid;
+            const int nterm = sm ? (int)__builtin_ctzll(sm) : lim;
+            steps0 += sm ? nterm + 1 : lim;
+            if (nterm > 0) {
+                const double eA = (double)siA / P0;
+                const double eB = (double)siB / P1;
+                double pA = __shfl_up(eA, 1, 64);
+                double pBv = __shfl_up(eB, 1, 64);
+                if (lane == 0) {
+                    pA = ep0;
+                    pBv = ep1;
+                }
+                const double tA = 0.5 * (pA + eA) * gl;
+                const double tB = 0.5 * (pBv + eB) * gl;
+                for (int t = 0; t < nterm; ++t) {
+                    ihh0 += readlane_f64(tA, t);
+                    ihh1 += readlane_f64(tB, t);
+                }
+                ep0 = readlane_f64(eA, nterm - 1);
+                ep1 = readlane_f64(eB, nterm - 1);
+            }
+            if (sm) act0 = false;
+            sa2 = (uint32_t)__builtin_amdgcn_readlane(siP, 63);
+            sa0 = (uint32_t)__builtin_amdgcn_readlane(siA, 63);
+            sa1 = (uint32_t)__builtin_amdgcn_readlane(siB, 63);
+        }
+        if ((act0 || act1) && nb < 64) {
+            status = abort_st;
+            break;
+        }
+        step += 64;
+        npairs = (int)*pcnt;
+        pb ^= 1;
+    }
+}
+done:
+    (void)pmode;
+    if (tid == 0) {
+        const size_t o = (size_t)j * 2 + d;
+        G.ihh[o * 2 + 0] = ihh0;
+        G.ihh[o * 2 + 1] = ihh1;
+        G.dstatus[o * 2 + 0] = status;
+        G.dstatus[o * 2 + 1] = status;
+        G.steps[o * 2 + 0] = steps0;
+        G.steps[o * 2 + 1] = MODE == MODE_CORE ? steps1 : 0;
+    }
+}
+
+// Persistent grid over the batch's items (region, site, direction).
+template <int R>
+__global__ void __launch_bounds__(1024) ids_batch_kernel(const Region *__restrict__ regs,
+                                                         int32_t nreg, int64_t total,
+                                                         unsigned long long *counter, int chunk,
+                                                         int lmax, int pcap, int kcap) {
+    extern __shared__ uint64_t lds_ids[];
+    __shared__ unsigned long long grab;
+    char *base = (char *)lds_ids;
+    const BLay Ly = batch_layout(lmax, pcap, kcap);
+    for (;;) {
+        __syncthreads();   // everyone has read the previous grab
+        if (threadIdx.x == 0) grab = atomicAdd(counter, (unsigned long long)chunk);
+        __syncthreads();
+        const int64_t b0 = (int64_t)grab;
+        if (b0 >= total) break;
+        const int64_t b1 = b0 + chunk < total ? b0 + chunk : total;
+        for (int64_t it = b0; it < b1; ++it) {
+            int lo = 0, hi = nreg - 1;   // last region with item0 <= it
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (regs[mid].item0 <= it) lo = mid;
+                else hi = mid - 1;
+            }
+            const Region G = regs[lo];
+            const int64_t loc = it - G.item0;
+            const int64_t j = loc >> 1;
+            const int d = (int)(loc & 1);
+            if (j >= G.M) continue;
+            if (G.walk_flag && !G.walk_flag[j]) continue;
+            if (G.mode == MODE_CORE) ids_walk<MODE_CORE, R>(G, j, d, base, Ly, pcap, kcap);
+            else ids_walk<MODE_POOLED, R>(G, j, d, base, Ly, pcap, kcap);
+            __syncthreads();
+        }
+    }
+}
+
+template <int R>
+hipError_t launch_r(const Region *regs, int32_t nreg, int64_t total, unsigned long long *counter,
+                    const WideCfg &c, hipStream_t s) {
+    hipLaunchKernelGGL((ids_batch_kernel<R>), dim3((unsigned)c.blocks), dim3((unsigned)c.threads),
+                       c.lds, s, regs, nreg, total, counter, c.chunk, c.lmax, c.pair_cap, c.key_cap);
+    return hipGetLastError();
+}
+
+template <int R>
+int occupancy_r(int threads, size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ids_batch_kernel<R>, threads, lds) !=
+        hipSuccess)
+        return 0;
+    return nb;
+}
+
+}  // namespace
+
+int ids_slots(int threads, int wmax) {
+    const int waves = threads / 64;
+    const int need = (wmax + waves - 1) / waves;
+    int r = 1;
+    while (r < need) r *= 2;
+    return r <= 16 ? r : 0;   // 32 slots would spill registers
+}
+
+size_t ids_lds_bytes(int threads, int lmax, int wmax, int pair_cap, int key_cap) {
+    if (threads != 256 && threads != 512 && threads != 1024) return 0;
+    if (lmax < 2 || lmax > 32767 || ids_slots(threads, wmax) == 0) return 0;
+    if (pair_cap < 0 || key_cap < 0 || key_cap > 32767) return 0;
+    return batch_layout(lmax, pair_cap, key_cap).total;
+}
+
+int ids_blocks_per_cu(const WideCfg &c) {
+    switch (ids_slots(c.threads, c.wmax)) {
+        case 1: return occupancy_r<1>(c.threads, c.lds);
+        case 2: return occupancy_r<2>(c.threads, c.lds);
+        case 4: return occupancy_r<4>(c.threads, c.lds);
+        case 8: return occupancy_r<8>(c.threads, c.lds);
+        case 16: return occupancy_r<16>(c.threads, c.lds);
+        default: return 0;
+    }
+}
+
+hipError_t launch_ids_batch(const Region *regs, int32_t nreg, int64_t total_items,
+                            unsigned long long *counter, const WideCfg &c, hipStream_t s) {
+    if (nreg <= 0 || total_items <= 0) return hipSuccess;
+    if (c.blocks <= 0 || c.chunk <= 0) return hipErrorInvalidValue;
+    switch (ids_slots(c.threads, c.wmax)) {
+        case 1: return launch_r<1>(regs, nreg, total_items, counter, c, s);
+        case 2: return launch_r<2>(regs, nreg, total_items, counter, c, s);
+        case 4: return launch_r<4>(regs, nreg, total_items, counter, c, s);
+        case 8: return launch_r<8>(regs, nreg, total_items, counter, c, s);
+        case 16: return launch_r<16>(regs, nreg, total_items, counter, c, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ss

@@ -1,0 +1,224 @@
+"""Batched scans through ss_scan_batch: the persistent walk over many regions
+against the CPU oracle and against single-region calls, for every launch
+configuration, under graph replay, after autotuning, and on the full
+5,000 x 10^6 workload (sampled loci)."""
+import sys
+
+import numpy as np
+import pytest
+
+import hapgen
+import oracle
+from tests.conftest import gpu_available
+from tests.test_gpu_parity import check_ihs, check_xpehh, assert_log, assert_rel
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an MI355X")]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ss():
+    import paper_1403_6854_amd as ss
+    ss.lib()
+    yield ss
+    ss.set_batch_config(ss.BatchConfig())
+    ss.set_walk_kernel(0)
+
+
+def _hm(ss, alleles, pos, gpos):
+    import torch
+    return ss.hapmat(torch.from_numpy(np.ascontiguousarray(alleles)).cuda(),
+                     torch.from_numpy(np.ascontiguousarray(pos, dtype=np.int64)).cuda(),
+                     torch.from_numpy(np.ascontiguousarray(gpos, dtype=np.float64)).cuda())
+
+
+def _np(out):
+    import torch
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+# (kind, n_a, n_b, n_sites, seed): iHS regions below and above 512 haplotypes,
+# XPEHH regions pooled below and above 512
+REGIONS = [("ihs", 120, 0, 900, 1), ("ihs", 700, 0, 1200, 2), ("xpehh", 200, 180, 800, 3),
+           ("ihs", 1500, 0, 600, 4), ("xpehh", 800, 600, 700, 5), ("ihs", 333, 0, 1000, 6)]
+
+
+def _data(kind, na, nb, m, seed):
+    a = hapgen.random_haplotypes(na, m, seed, n_founders=max(2, na // 25), switch_p=0.004)
+    if kind == "ihs":
+        return a, None
+    b = hapgen.random_haplotypes(nb, m, seed + 500, n_founders=max(2, nb // 25), switch_p=0.006)
+    return a, b
+
+
+@pytest.fixture(scope="module")
+def regions(ss):
+    out = []
+    for kind, na, nb, m, seed in REGIONS:
+        a, b = _data(kind, na, nb, m, seed)
+        ha = _hm(ss, a.alleles, a.pos_bp, a.gpos_cm)
+        hb = _hm(ss, b.alleles, a.pos_bp, a.gpos_cm) if b is not None else None
+        if b is None:
+            ref = oracle.ihs(a.alleles, a.pos_bp, a.gpos_cm)
+        else:
+            ref = oracle.xpehh(a.alleles, b.alleles, a.pos_bp, a.gpos_cm)
+        out.append((kind, ha, hb, ref))
+    return out
+
+
+def _run_batch(ss, regions, stream=None):
+    reqs = []
+    for kind, ha, hb, _ in regions:
+        r = ss.ScanRequest(ha, hb)
+        ss.alloc_outputs(r, steps=True)
+        reqs.append(r)
+    ss.scan_batch(reqs, stream=stream)
+    return reqs, [_np(r.out) for r in reqs]
+
+
+def _check_all(got, regions, what):
+    for (kind, _, _, ref), g in zip(regions, got):
+        if kind == "ihs":
+            check_ihs(g, ref, what)
+        else:
+            check_xpehh(g, ref, what)
+
+
+@pytest.mark.parametrize("small_kernel", [1, 0])
+def test_batch_matches_oracle_and_single_calls(ss, regions, small_kernel):
+    say("ss_scan_batch %d regions small_kernel=%d" % (len(regions), small_kernel))
+    ss.set_batch_config(ss.BatchConfig(small_kernel=small_kernel))
+    try:
+        _, got = _run_batch(ss, regions)
+    finally:
+        ss.set_batch_config(ss.BatchConfig())
+    _check_all(got, regions, "batch")
+    # bit-identical to the single-region entry points
+    for (kind, ha, hb, _), g in zip(regions, got):
+        one = _np(ss.ihs(ha, steps=True) if kind == "ihs" else ss.xpehh(ha, hb, steps=True))
+        for k in one:
+            np.testing.assert_array_equal(g[k], one[k], err_msg=kind + " " + k)
+
+
+CONFIGS = [dict(threads=256), dict(threads=1024), dict(pair_cap=0), dict(pair_cap=1024),
+           dict(pair_cap=8192), dict(pair_cap=16384), dict(chunk=7), dict(order=1),
+           dict(blocks_per_cu=1), dict(threads=1024, pair_cap=4096, chunk=3, order=1),
+           dict(kernel=1, threads=128), dict(kernel=1, threads=256), dict(kernel=1, threads=512),
+           dict(kernel=1, threads=256, pair_cap=0), dict(kernel=1, threads=128, pair_cap=8192,
+                                                            chunk=3, order=1)]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS, ids=[",".join("%s=%s" % kv for kv in c.items()) for c in CONFIGS])
+def test_launch_configurations_give_identical_results(ss, regions, cfg):
+    say("ss_scan_batch config %s" % cfg)
+    ss.set_batch_config(ss.BatchConfig(small_kernel=0))
+    try:
+        _, base = _run_batch(ss, regions)
+        ss.set_batch_config(ss.BatchConfig(small_kernel=0, **cfg))
+        _, got = _run_batch(ss, regions)
+    finally:
+        ss.set_batch_config(ss.BatchConfig())
+    for b, g in zip(base, got):
+        for k in b:
+            np.testing.assert_array_equal(g[k], b[k], err_msg=k)
+
+
+def test_graph_replays_match_eager(ss, regions):
+    import torch
+    say("ss_scan_batch graph replay")
+    reqs, eager = _run_batch(ss, regions)
+    stream = torch.cuda.Stream()
+    ss.set_graph(True)
+    try:
+        for rep in range(4):
+            for r in reqs:            # eager work between replays
+                for v in r.out.values():
+                    v.fill_(-1 if v.dtype != torch.float64 else float("nan"))
+            torch.cuda.synchronize()
+            ss.scan_batch(reqs, stream=stream)
+            stream.synchronize()
+            got = [_np(r.out) for r in reqs]
+            for e, g in zip(eager, got):
+                for k in e:
+                    np.testing.assert_array_equal(g[k], e[k], err_msg="replay %d %s" % (rep, k))
+    finally:
+        ss.set_graph(False)
+        ss.graph_clear()
+
+
+def test_autotune_then_parity(ss, regions):
+    say("ss_autotune_batch")
+    reqs = []
+    for kind, ha, hb, _ in regions:
+        r = ss.ScanRequest(ha, hb)
+        ss.alloc_outputs(r, steps=True)
+        reqs.append(r)
+    ss.set_batch_config(ss.BatchConfig(small_kernel=0))
+    try:
+        cfg, ms, ws = ss.autotune_batch(reqs, sample_items=0)
+        assert ms > 0.0
+        assert cfg.kernel in (0, 1) and cfg.small_kernel == 0
+        assert cfg.threads in ((256, 512, 1024) if cfg.kernel == 0 else (128, 256, 512))
+        assert ss.get_batch_config() == cfg
+        ss.scan_batch(reqs, ws=ws)
+        got = [_np(r.out) for r in reqs]
+    finally:
+        ss.set_batch_config(ss.BatchConfig())
+    _check_all(got, regions, "tuned")
+
+
+def _standardize_numpy(u, status, bins, nbins):
+    z = np.full_like(u, np.nan)
+    for b in range(nbins):
+        m = (bins == b) & np.isin(status, (0, 5))
+        if m.sum() >= 2:
+            v = u[m]
+            sd = v.std(ddof=1)
+            if sd > 0:
+                z[m] = (v - v.mean()) / sd
+    return z
+
+
+def test_large_batch_full_size_sampled_parity(ss):
+    """5,000 haplotypes x 10^6 sites in one persistent launch; the oracle
+    checks every 2,000th scored site and every sweep site."""
+    import torch
+    say("large batch: generating 5000 x 1e6 on the device")
+    alleles, pos, gpos, sweeps = hapgen.large_batch_input(None, device="cuda")
+    h = ss.hapmat(alleles, torch.from_numpy(pos).cuda(), torch.from_numpy(gpos).cuda())
+    req = ss.ScanRequest(h)
+    ss.alloc_outputs(req, steps=True)
+    say("large batch: scanning")
+    ss.scan_batch([req])
+    got = _np(req.out)
+    say("large batch: oracle on sampled loci")
+    host = alleles.cpu().numpy()
+    del alleles
+    scored = np.flatnonzero(got["status"] != 1)
+    sample = np.unique(np.concatenate([scored[::2000], np.asarray(sweeps)]))
+    ref = oracle.ihs(host, pos, gpos, loci=sample)
+    g = {k: v[sample] for k, v in got.items()}
+    r = {k: v[sample] for k, v in ref.items()}
+    ok_g = np.isin(g["status"], (0, 5))
+    ok_r = np.isin(r["status"], (0, 5))
+    np.testing.assert_array_equal(ok_g, ok_r)
+    np.testing.assert_array_equal(g["status"][~ok_g], r["status"][~ok_r])
+    np.testing.assert_array_equal(g["steps"], r["steps"].astype(np.int32))
+    np.testing.assert_array_equal(g["freq"], r["freq"])
+    every = np.ones(len(sample), dtype=bool)
+    assert_rel(g["ihh1"], r["ihh1"], every, "ihh1")
+    assert_rel(g["ihh0"], r["ihh0"], every, "ihh0")
+    assert_log(g["unstd"], r["unstd"], every, "unstd")
+    # standardization over all 10^6 sites, checked against numpy on the
+    # device's own unstandardized scores
+    n1 = np.rint(got["freq"] * 5000).astype(np.int64)
+    bins = np.minimum((40 * n1) // 5000, 39)
+    z = _standardize_numpy(got["unstd"], got["status"], bins, 40)
+    assert_log(got["std"], z, np.isin(got["status"], (0, 5)), "std")
+    assert (got["status"] == 0).sum() > 100000

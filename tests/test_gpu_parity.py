@@ -33,12 +33,23 @@ def ss():
     return ss
 
 
-@pytest.fixture(params=[1, 2], ids=["lds_ids", "reg_masks"])
+@pytest.fixture(params=[1, 2, "batch_ids", "batch_lists"],
+                ids=["lds_ids", "reg_masks", "batch_ids", "batch_lists"])
 def walk(request, ss):
-    """Run a scan test with each EHH-walk kernel (results must not depend on it)."""
-    ss.set_walk_kernel(request.param)
+    """Run a scan test with each EHH-walk kernel (results must not depend on
+    it): the plain class-id kernel, the bitmask kernel, and both kernels of the
+    persistent batch walk."""
+    if request.param == "batch_ids":
+        ss.set_batch_config(ss.BatchConfig(kernel=0, threads=512))
+        ss.set_walk_kernel(3)
+    elif request.param == "batch_lists":
+        ss.set_batch_config(ss.BatchConfig(kernel=1, threads=256))
+        ss.set_walk_kernel(3)
+    else:
+        ss.set_walk_kernel(request.param)
     yield request.param
     ss.set_walk_kernel(0)
+    ss.set_batch_config(ss.BatchConfig())
 
 
 def _dev(d):
@@ -161,7 +172,7 @@ def test_ehh_capacity_status(ss):
 # ---------------------------------------------------------------------------
 def test_ihs_tiny_config(ss, walk):
     d = hapgen.config_input(0)
-    say("ss_ihs 200 x 2000 walk=%d" % walk)
+    say("ss_ihs 200 x 2000 walk=%s" % walk)
     h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
     got = _np(ss.ihs(h, steps=True))
     ref = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm)
@@ -170,7 +181,7 @@ def test_ihs_tiny_config(ss, walk):
 
 def test_ihs_chr22_shaped_config(ss, walk):
     d = hapgen.config_input(1)
-    say("ss_ihs 204 x 22147 walk=%d" % walk)
+    say("ss_ihs 204 x 22147 walk=%s" % walk)
     h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
     got = _np(ss.ihs(h, steps=True))
     ref = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm)
@@ -211,7 +222,7 @@ def test_ihs_edge_cases(ss, walk, case):
         params = oracle.Params(ehh_cutoff=0.001)
     if case == "narrow_bins":
         params = oracle.Params(bin_width=0.01)
-    say("ss_ihs edge case %s walk=%d" % (case, walk))
+    say("ss_ihs edge case %s walk=%s" % (case, walk))
     h = _hm(ss, d.alleles, pos, gpos)
     got = _np(ss.ihs(h, ss.Params(**vars(params)), steps=True))
     ref = oracle.ihs(d.alleles, pos, gpos, params)
@@ -221,7 +232,7 @@ def test_ihs_edge_cases(ss, walk, case):
 @pytest.mark.parametrize("n", [3, 63, 64, 65, 128, 129, 256, 257, 400, 511, 512, 513])
 def test_ihs_ragged_haplotype_counts(ss, walk, n):
     d = hapgen.random_haplotypes(n, 700, 40 + n, n_founders=max(2, n // 12), switch_p=0.01)
-    say("ss_ihs %d x 700 walk=%d" % (n, walk))
+    say("ss_ihs %d x 700 walk=%s" % (n, walk))
     h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
     params = oracle.Params(maf_cutoff=0.0)
     got = _np(ss.ihs(h, ss.Params(**vars(params)), steps=True))
@@ -289,7 +300,7 @@ def _many_classes(seed):
 
 def test_ihs_more_classes_than_a_wave_row(ss, walk):
     H, pos, gpos, core = _many_classes(3)
-    say("ss_ihs many classes walk=%d" % walk)
+    say("ss_ihs many classes walk=%s" % walk)
     h = _hm(ss, H, pos, gpos)
     params = oracle.Params(maf_cutoff=0.0)
     got = _np(ss.ihs(h, ss.Params(**vars(params)), steps=True))
@@ -324,7 +335,7 @@ def test_ihs_large_haplotype_count(ss, walk):
 # ---------------------------------------------------------------------------
 def test_xpehh_chr22_shaped_config(ss, walk):
     a, b = hapgen.config_input(2)
-    say("ss_xpehh 204+210 x 22147 walk=%d" % walk)
+    say("ss_xpehh 204+210 x 22147 walk=%s" % walk)
     ha = _hm(ss, a.alleles, a.pos_bp, a.gpos_cm)
     hb = _hm(ss, b.alleles, b.pos_bp, b.gpos_cm)
     got = _np(ss.xpehh(ha, hb, steps=True))
@@ -337,7 +348,7 @@ def test_xpehh_ragged_populations(ss, walk, na, nb):
     M = 600 if na + nb < 2000 else 200
     a = hapgen.random_haplotypes(na, M, na, n_founders=max(2, na // 20), switch_p=0.01)
     b = hapgen.random_haplotypes(nb, M, 1000 + nb, n_founders=max(2, nb // 20), switch_p=0.02)
-    say("ss_xpehh %d+%d x %d walk=%d" % (na, nb, M, walk))
+    say("ss_xpehh %d+%d x %d walk=%s" % (na, nb, M, walk))
     ha = _hm(ss, a.alleles, a.pos_bp, a.gpos_cm)
     hb = _hm(ss, b.alleles, a.pos_bp, a.gpos_cm)
     got = _np(ss.xpehh(ha, hb, steps=True))

@@ -40,3 +40,47 @@ def test_random_haplotypes():
     d = hapgen.random_haplotypes(10, 50, 3)
     assert d.alleles.shape == (50, 10)
     np.testing.assert_array_equal(d.pos_bp, np.arange(1, 51) * 1000)
+
+
+def test_sparse_copy_events_render_like_the_model():
+    # rendering the sparse draws equals copying founders segment by segment
+    rng = np.random.default_rng(3)
+    F, M, n = 7, 500, 40
+    fo = hapgen.draw_founders(rng, F, M)
+    ev = hapgen.draw_copy_events(rng, n, M, F, 0.02, 0.01)
+    got = hapgen.render_alleles(fo, ev, chunk=128).numpy()
+    ref = np.empty((M, n), np.uint8)
+    for h in range(n):
+        f = int(ev.start[h])
+        sw = dict(zip(ev.sw_site[ev.sw_hap == h].tolist(), ev.sw_step[ev.sw_hap == h].tolist()))
+        for s in range(M):
+            if s in sw:
+                f = (f + sw[s]) % F
+                assert sw[s] != 0
+            ref[s, h] = fo[f, s]
+        for s in ev.fl_site[ev.fl_hap == h]:
+            ref[s, h] ^= 1
+    np.testing.assert_array_equal(got, ref)
+    assert ev.sw_site.min() >= 1 and ev.sw_site.max() < M
+
+
+def test_sparse_copy_event_rates():
+    rng = np.random.default_rng(11)
+    n, M = 400, 20000
+    ev = hapgen.draw_copy_events(rng, n, M, 50, 0.003, 0.001)
+    exp_sw, exp_fl = n * (M - 1) * 0.003, n * M * 0.001
+    assert abs(len(ev.sw_site) - exp_sw) < 5 * np.sqrt(exp_sw)
+    assert abs(len(ev.fl_site) - exp_fl) < 5 * np.sqrt(exp_fl)
+    for h in (0, 17, 399):
+        s = ev.sw_site[ev.sw_hap == h]
+        assert np.all(np.diff(s) > 0)
+
+
+def test_large_batch_input_scaled():
+    a, pos, gpos, sites = hapgen.large_batch_input(10000)
+    assert tuple(a.shape) == (10000, 5000)
+    assert np.all(np.diff(pos) > 0) and len(sites) == 2
+    for s in sites:
+        assert 0.5 * 5000 - 2 <= int(a[s].sum()) <= 0.95 * 5000 + 2
+    b, pos2, _, _ = hapgen.large_batch_input(10000)
+    assert np.array_equal(pos, pos2) and bool((a == b).all())
