@@ -11,11 +11,24 @@ with trapezoid iHH, the log-ratios and the frequency-bin standardization
 (ss_pack + ss_ihs).  The XPEHH scan of the same sites against 210 haplotypes
 is timed the same way and reported beside it.
 
+Two more workloads are reported in the same line:
+  * "batched": 5,000 haplotypes x 10^6 SNPs over 250 Mb (200 founders,
+    switch probability 0.001, 20 planted sweeps), every qualifying core locus
+    in one persistent launch captured in a HIP graph with an autotuned
+    configuration, against the plain per-locus class-id kernel on the same
+    GPU;
+  * "served": 4,096 region-scan requests (Poisson arrivals at 200/s, iHS with
+    probability 0.6 else XPEHH, 100-5,000 haplotypes per population and
+    1,000-200,000 SNPs, both log-uniform) through the continuous-batching
+    server, against the same requests scanned back to back one at a time;
+    p50 / p99 latency and throughput for both.
+
 Prints ONE JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -76,6 +89,159 @@ def time_scan(fn, warmup: int, steps: int, ss, torch):
     return (t1 - t0), walk_ms / max(1, launches), launches
 
 
+def bench_batched(ss, torch, dev, reps: int = 3):
+    """5,000 x 10^6 iHS: one persistent launch in a graph vs the plain kernel."""
+    import hapgen
+    log("batched: generating 5000 x 1e6 on the device")
+    alleles, pos, gpos, sweeps = hapgen.large_batch_input(None, device=dev)
+    h = ss.hapmat(alleles, torch.from_numpy(pos).to(dev), torch.from_numpy(gpos).to(dev))
+    n, M = int(alleles.shape[1]), int(alleles.shape[0])
+    del alleles
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    stream = torch.cuda.Stream()
+    req = ss.ScanRequest(h)
+    ss.alloc_outputs(req)
+    log("batched: autotuning the persistent walk")
+    t0 = time.perf_counter()
+    cfg, tune_ms, ws = ss.autotune_batch([req], stream=stream, sample_items=200_000)
+    tune_s = time.perf_counter() - t0
+    # walk kernel alone (eager, timed with events on the stream)
+    ss.scan_batch([req], stream=stream, ws=ws, validate=False)
+    stream.synchronize()
+    ss.timing_read(reset=True)
+    ss.timing_enable(True)
+    ss.scan_batch([req], stream=stream, ws=ws, validate=False)
+    stream.synchronize()
+    ss.timing_enable(False)
+    walk_ms, _ = ss.timing_read(reset=True)
+    # whole scan as a graph replay
+    ss.set_graph(True)
+    ss.scan_batch([req], stream=stream, ws=ws, validate=False)    # capture + first replay
+    stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ss.scan_batch([req], stream=stream, ws=ws, validate=False)
+    stream.synchronize()
+    graph_s = (time.perf_counter() - t0) / reps
+    ss.set_graph(False)
+    ss.graph_clear()
+    status = req.out["status"]
+    loci = int((status != 1).sum().item())
+    # the plain per-locus kernel (one workgroup per site and direction)
+    log("batched: plain per-locus kernel on the same input")
+    ss.set_walk_kernel(1)
+    plain = ss.ihs(h, validate=False)
+    torch.cuda.synchronize()
+    ss.timing_read(reset=True)
+    ss.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plain = ss.ihs(h, validate=False)
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / reps
+    ss.timing_enable(False)
+    plain_walk_ms, launches = ss.timing_read(reset=True)
+    ss.set_walk_kernel(0)
+    same = bool(torch.equal(plain["status"], status)) and bool(
+        torch.equal(plain["unstd"].nan_to_num(-7.0), req.out["unstd"].nan_to_num(-7.0)))
+    res = {"workload": "ihs_batched_5000x1e6", "n_haps": n, "n_sites": M, "core_loci": loci,
+           "sweeps": len(sweeps), "value": round(loci / graph_s, 1), "unit": "core loci/s",
+           "scan_ms": round(graph_s * 1e3, 3), "walk_kernel_ms": round(walk_ms, 3),
+           "graph": True, "config": dataclasses.asdict(cfg), "autotune_s": round(tune_s, 2),
+           "autotune_sample_ms": round(tune_ms, 3),
+           "plain_kernel": {"value": round(loci / plain_s, 1), "scan_ms": round(plain_s * 1e3, 3),
+                            "walk_kernel_ms": round(plain_walk_ms / max(1, launches), 3)},
+           "speedup_vs_plain": round(plain_s / graph_s, 3), "identical_results": same}
+    del req, plain, h, ws
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_served(ss, torch, dev, args):
+    """The served request stream: continuous batching vs back to back."""
+    import hapgen
+    from paper_1403_6854_amd import serve
+    specs = hapgen.request_stream(args.serve_requests)
+
+    def make(spec):
+        def f():
+            a, b, pos, gpos = hapgen.device_region(spec, dev)
+            ha = ss.hapmat(a, pos, gpos)
+            hb = ss.hapmat(b, pos, gpos) if b is not None else None
+            return ha, hb
+        return f
+
+    def reqs_of(sp):
+        return [serve.ServeRequest(s.rid, s.arrival_s, s.kind,
+                                   serve.request_bytes(s.kind, s.n_a, s.n_b, s.n_sites),
+                                   make(s), s.n_sites) for s in sp]
+
+    def loci_of(done, sp):
+        kinds = {s.rid: s for s in sp}
+        tot = 0
+        for c in done:
+            st = c.out["status"]
+            tot += int((st != 1).sum().item()) if kinds[c.rid].kind == "ihs" else int(st.numel())
+        return tot
+
+    budget = int(args.serve_budget_gb * (1 << 30))
+    # warm-up (library, generator and allocator first-use costs stay out of
+    # the measured runs) and autotuning of the persistent walk on a batch of
+    # the mix (requests drawn like the stream's, with other seeds)
+    ss.set_batch_config(ss.BatchConfig())
+    tune_specs = [dataclasses.replace(s, rid=100000 + i, seed=s.seed + (1 << 24), arrival_s=0.0)
+                  for i, s in enumerate(hapgen.request_stream(48))]
+    tune = []
+    for r in reqs_of(tune_specs):
+        a, b = r.make()
+        q = ss.ScanRequest(a, b)
+        ss.alloc_outputs(q)
+        tune.append(q)
+    cfg, _, _ = ss.autotune_batch(tune)
+    del tune
+    warm = [dataclasses.replace(s, arrival_s=0.0) for s in specs[:12]]
+    serve.Server(serve.TorchBackend(args.serve_streams), budget).run(reqs_of(warm))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log("served: %d requests, continuous batching" % len(specs))
+    srv = serve.Server(serve.TorchBackend(args.serve_streams), budget, max_batch=64)
+    done = srv.run(reqs_of(specs))
+    torch.cuda.synchronize()
+    s1 = serve.summarize(done)
+    s1["core_loci_per_s"] = round(loci_of(done, specs) / s1["makespan_s"], 1)
+    s1.update({"batches": srv.batches, "mean_batch": round(float(np.mean(srv.batch_sizes)), 2),
+               "peak_admitted_GB": round(srv.peak_bytes / 2**30, 2),
+               "streams": args.serve_streams, "budget_GB": args.serve_budget_gb,
+               "config": dataclasses.asdict(cfg)})
+    del done
+    torch.cuda.empty_cache()
+
+    log("served: %d requests back to back (plain scans)" % len(specs))
+    stream = torch.cuda.Stream()
+    ss.set_walk_kernel(2)    # bitmask kernel when it applies, else the plain class-id kernel
+
+    def run_one(r):
+        with torch.cuda.stream(stream):
+            ha, hb = r.make()
+            out = ss.ihs(ha, validate=False) if hb is None else ss.xpehh(ha, hb, validate=False)
+        stream.synchronize()
+        return {"status": out["status"]}
+
+    seq = serve.run_back_to_back(reqs_of(specs), run_one)
+    ss.set_walk_kernel(0)
+    s2 = serve.summarize(seq)
+    s2["core_loci_per_s"] = round(loci_of(seq, specs) / s2["makespan_s"], 1)
+    del seq
+    torch.cuda.empty_cache()
+    return {"workload": "served_mixed_4096", "requests": len(specs),
+            "arrivals_per_s": hapgen.SERVE["rate_per_s"],
+            "continuous_batching": s1, "back_to_back": s2,
+            "throughput_ratio": round(s1["requests_per_s"] / s2["requests_per_s"], 3),
+            "p99_ratio": round(s2["p99_ms"] / s1["p99_ms"], 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +249,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--serve-budget-gb", type=float, default=48.0)
+    ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -184,6 +355,9 @@ def main():
                "sample": "%d full iHS scans of the 204 x 22,147 workload (%d core loci each), "
                          "%.2f s per scan" % (args.cpu_reps, core_loci, t_cpu)}
 
+    batched = None if args.no_batched else bench_batched(ss, torch, dev)
+    served = None if args.no_served else bench_served(ss, torch, dev, args)
+
     line = {
         "metric": "iHS core loci/sec on 1 MI355X (XPEHH beside it)",
         "value": round(value, 1),
@@ -205,6 +379,8 @@ def main():
                   "unit": "core loci/s", "ms_per_step": round(elx / args.steps * 1e3, 5),
                   "walk_kernel_ms": round(walk_ms_x, 5), "work_cells": Wx,
                   "achieved_TOPs": round(Wx / (walk_ms_x * 1e-3) / 1e12, 4)},
+        "batched": batched,
+        "served": served,
         "context": {"paper_cpu_loci_per_s": {"ihs_ceu22_1thread": 62.7, "ihs_ceu22_16threads": 671,
                                              "xpehh_ceuyri22_1thread": 38.3,
                                              "xpehh_ceuyri22_16threads": 426},

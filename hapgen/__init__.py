@@ -348,3 +348,92 @@ def poisson_arrivals(n: int, rate_per_s: float, seed: int = 7) -> np.ndarray:
 
 def log_uniform_int(rng: np.random.Generator, lo: int, hi: int) -> int:
     return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+
+
+# ---------------------------------------------------------------------------
+# Served region-scan requests: many regions of random sizes, generated on the
+# device from per-request seeds (torch's counter-based generator), so that a
+# request stream of ~10^11 alleles does not wait on the host.
+# ---------------------------------------------------------------------------
+SERVE = dict(n_requests=4096, rate_per_s=200.0, p_ihs=0.6, n_range=(100, 5000),
+             sites_range=(1000, 200_000), bp_per_site=1580, n_founders=40, switch_p=0.003,
+             flip_p=0.001, share_p=0.8, arrival_seed=7, seed_base=1 << 20)
+
+
+@dataclasses.dataclass
+class RequestSpec:
+    rid: int
+    kind: str          # "ihs" or "xpehh"
+    arrival_s: float
+    n_a: int
+    n_b: int           # 0 for iHS
+    n_sites: int
+    seed: int
+
+
+def request_stream(n_requests: Optional[int] = None, rate_per_s: Optional[float] = None):
+    """The served workload: Poisson arrivals, iHS with probability p_ihs else
+    XPEHH, haplotype counts per population and site counts log-uniform."""
+    c = SERVE
+    n = c["n_requests"] if n_requests is None else int(n_requests)
+    rate = c["rate_per_s"] if rate_per_s is None else float(rate_per_s)
+    arr = poisson_arrivals(n, rate, seed=c["arrival_seed"])
+    rng = np.random.default_rng(c["arrival_seed"] + 1)
+    out = []
+    for r in range(n):
+        kind = "ihs" if rng.random() < c["p_ihs"] else "xpehh"
+        na = log_uniform_int(rng, *c["n_range"])
+        nb = log_uniform_int(rng, *c["n_range"]) if kind == "xpehh" else 0
+        m = log_uniform_int(rng, *c["sites_range"])
+        out.append(RequestSpec(r, kind, float(arr[r]), na, nb, m, c["seed_base"] + r))
+    return out
+
+
+def _device_copy(gen, founders, n_haps: int, switch_p: float, flip_p: float, chunk: int = 16384):
+    """Founder copying on the device (dense draws from ``gen``), drawn
+    haplotype-major so that the founder path is a scan along the contiguous
+    axis; returned site-major."""
+    import torch
+    F, M = founders.shape
+    dev = founders.device
+    out = torch.empty((M, n_haps), dtype=torch.uint8, device=dev)
+    cur = torch.randint(0, F, (n_haps,), generator=gen, device=dev)
+    for s0 in range(0, M, chunk):
+        s1 = min(M, s0 + chunk)
+        sw = torch.rand((n_haps, s1 - s0), generator=gen, device=dev) < switch_p
+        if s0 == 0:
+            sw[:, 0] = False
+        step = torch.randint(1, max(2, F), (n_haps, s1 - s0), generator=gen, device=dev)
+        step = step * sw if F >= 2 else torch.zeros_like(step)
+        path = torch.remainder(cur[:, None] + torch.cumsum(step, dim=1), F)
+        cur = path[:, -1].clone()
+        col = torch.arange(s0, s1, device=dev)[None, :]
+        block = founders[path, col]
+        flips = torch.rand((n_haps, s1 - s0), generator=gen, device=dev) < flip_p
+        out[s0:s1] = (block ^ flips.to(torch.uint8)).t()
+    return out
+
+
+def device_region(spec: RequestSpec, device="cuda"):
+    """Inputs of one served request, generated on ``device``: (alleles_a,
+    alleles_b or None, pos_bp, gpos_cm) as torch tensors; positions are drawn
+    on the host from the same seed."""
+    import torch
+    c = SERVE
+    rng = np.random.default_rng(spec.seed)
+    pos, gpos = draw_positions(rng, spec.n_sites, max(spec.n_sites, spec.n_sites * c["bp_per_site"]))
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(spec.seed))
+    F, M = c["n_founders"], spec.n_sites
+    # Beta(1/2, 1/2) is the arcsine law: sin^2(pi U / 2)
+    p = torch.sin(0.5 * math.pi * torch.rand(M, generator=gen, device=device, dtype=torch.float64)) ** 2
+    fa = (torch.rand((F, M), generator=gen, device=device, dtype=torch.float64) < p[None, :]).to(torch.uint8)
+    a = _device_copy(gen, fa, spec.n_a, c["switch_p"], c["flip_p"])
+    b = None
+    if spec.kind == "xpehh":
+        p2 = torch.sin(0.5 * math.pi * torch.rand(M, generator=gen, device=device, dtype=torch.float64)) ** 2
+        fresh = (torch.rand((F, M), generator=gen, device=device, dtype=torch.float64) < p2[None, :]).to(torch.uint8)
+        keep = torch.rand((F, M), generator=gen, device=device, dtype=torch.float64) < c["share_p"]
+        fb = torch.where(keep, fa, fresh)
+        b = _device_copy(gen, fb, spec.n_b, c["switch_p"], c["flip_p"])
+    return (a, b, torch.from_numpy(pos).to(device), torch.from_numpy(gpos).to(device))

@@ -226,9 +226,13 @@ int ss_scan_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_params *
 
 /* Launch configuration of the persistent walk (process-wide). */
 typedef struct ss_batch_config {
-    int32_t threads;        /* workgroup size: 256, 512 or 1024 (kernel 0);
-                               128, 256 or 512 (kernel 1)                               */
-    int32_t pair_cap;       /* pairs, and haplotypes, the pairwise phase holds: 0..16384 */
+    int32_t threads;        /* workgroup size.  Kernel 0: a multiple of 64 in [64, 1024],
+                               a minimum -- each region takes the smallest size that
+                               holds its rows (16 64-haplotype words per wave), and
+                               regions of one size share one launch; kernel 1: 128, 256
+                               or 512                                                   */
+    int32_t pair_cap;       /* pairs, and haplotypes, the pairwise phase holds: 0..16384
+                               (kernel 0: launches of 256 threads or more)              */
     int32_t chunk;          /* work items taken per grab of the counter, >= 1            */
     int32_t blocks_per_cu;  /* persistent workgroups per CU; 0 = as many as fit          */
     int32_t order;          /* 0: regions in the order given; 1: most haplotypes first   */
@@ -237,6 +241,9 @@ typedef struct ss_batch_config {
     int32_t kernel;         /* 0: class ids per haplotype with a pairwise tail, one item
                                per (site, direction) [default]; 1: per-core walks over
                                sorted member lists, one item per (site, direction, core) */
+    int32_t small_pair_cap; /* kernel 0: pair capacity of the launches of 64 or 128
+                               threads (regions of up to 2048 haplotypes in the walk),
+                               whose occupancy the pair buffers would halve; 0..16384    */
 } ss_batch_config;
 
 int ss_get_batch_config(ss_batch_config *c);

@@ -176,17 +176,19 @@ hipEvent_t take_event() {
 
 int g_walk_kind = ss::WALK_AUTO;
 int g_mask_lpc = 0;   // lanes per class of the bitmask walk; 0 = default
-ss_batch_config g_bcfg = {512, 2048, 1, 0, 0, 1, 0};
+ss_batch_config g_bcfg = {64, 2048, 1, 0, 0, 1, 0, 0};
 bool g_graph_on = false;
 bool g_capturing = false;   // timing events are not recorded into graphs
 
 int check_batch_config(const ss_batch_config &c) {
     if (c.kernel != 0 && c.kernel != 1) return fail(SS_EARG, "kernel must be 0 or 1");
-    if (c.kernel == 0 && c.threads != 256 && c.threads != 512 && c.threads != 1024)
-        return fail(SS_EARG, "threads must be 256, 512 or 1024 for kernel 0");
+    if (c.kernel == 0 && (c.threads < 64 || c.threads > 1024 || c.threads % 64))
+        return fail(SS_EARG, "threads must be a multiple of 64 in [64, 1024] for kernel 0");
     if (c.kernel == 1 && c.threads != 128 && c.threads != 256 && c.threads != 512)
         return fail(SS_EARG, "threads must be 128, 256 or 512 for kernel 1");
     if (c.pair_cap < 0 || c.pair_cap > 16384) return fail(SS_EARG, "pair_cap must be in [0, 16384]");
+    if (c.small_pair_cap < 0 || c.small_pair_cap > 16384)
+        return fail(SS_EARG, "small_pair_cap must be in [0, 16384]");
     if (c.chunk < 1 || c.chunk > 4096) return fail(SS_EARG, "chunk must be in [1, 4096]");
     if (c.blocks_per_cu < 0 || c.blocks_per_cu > 64) return fail(SS_EARG, "blocks_per_cu must be in [0, 64]");
     if (c.order != 0 && c.order != 1) return fail(SS_EARG, "order must be 0 or 1");
@@ -204,9 +206,14 @@ bool make_wide_cfg(const ss_batch_config &bc, int lmax, int wmax, ss::WideCfg &c
     c.lmax = lmax;
     c.wmax = wmax;
     if (bc.kernel == 0) {
+        // the configured size is a minimum: wider rows take larger workgroups
+        const int need = ss::ids_threads_for(wmax);
+        if (need == 0) return false;
+        c.threads = std::max(bc.threads, need);
+        if (c.threads <= 128) c.pair_cap = bc.small_pair_cap;
         // the member list of the pairwise tail holds as many haplotypes as
         // there are pairs; walks with more members wait in the per-marker phase
-        c.key_cap = std::min(bc.pair_cap, 32767);
+        c.key_cap = std::min(c.pair_cap, 32767);
         c.lds = ss::ids_lds_bytes(c.threads, lmax, wmax, c.pair_cap, c.key_cap);
     } else {
         // a pair list of P pairs holds at most ~P / 4 haplotypes in classes of
@@ -449,12 +456,24 @@ int walk_scan(Scan &sc, hipStream_t s) {
 }
 
 // ---- batches -------------------------------------------------------------------
+// Regions of the persistent walk that share one launch: the class-id kernel
+// gives every region the smallest workgroup that holds its rows, so regions
+// are grouped by workgroup size; the list kernel takes them all in one group.
+struct Group {
+    int first = 0, count = 0;   // range of Batch::regions
+    int64_t total_items = 0;
+    int lmax = 0, wmax = 0, threads = 0;
+};
+
+constexpr int kMaxGroups = 16;
+
 struct Batch {
     std::vector<Scan> scans;
-    std::vector<int> wide;            // scans walked by the persistent kernel, in item order
-    std::vector<ss::Region> regions;  // their descriptors (item0 set)
+    std::vector<int> wide;            // scans walked by the persistent kernel
+    std::vector<ss::Region> regions;  // their descriptors, group by group (item0 per group)
+    std::vector<Group> groups;
     ss::Region *d_regions = nullptr;
-    unsigned long long *d_counter = nullptr;
+    unsigned long long *d_counter = nullptr;   // one per group
     int64_t total_items = 0;
     int lmax = 0, wmax = 0;
 };
@@ -495,26 +514,51 @@ BatchLayout batch_layout(const ss_scan_request *reqs, int32_t n, const ss_params
     return L;
 }
 
-// Item numbering of the persistent walk's regions for a region order.
-void number_items(Batch &B, int order, int kernel) {
-    std::vector<int> idx(B.wide.size());
-    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
-    if (order == 1) {
-        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
-            const Scan &a = B.scans[B.wide[x]], &b = B.scans[B.wide[y]];
-            return list_len(a.args.nA, a.args.nB, a.mode) > list_len(b.args.nA, b.args.nB, b.mode);
-        });
-    }
-    B.regions.clear();
-    int64_t item = 0;
-    for (int i : idx) {
+// Launch groups and item numbering of the persistent walk's regions for a
+// configuration (region order within a group: as given, or most haplotypes
+// first).
+void number_items(Batch &B, const ss_batch_config &bc) {
+    struct Key {
+        int threads, idx, len;
+    };
+    std::vector<Key> keys;
+    for (size_t i = 0; i < B.wide.size(); ++i) {
         const Scan &sc = B.scans[B.wide[i]];
+        const int len = list_len(sc.args.nA, sc.args.nB, sc.mode);
+        const int wrd = row_words(sc.args.nA, sc.args.nB, sc.mode);
+        const int t = bc.kernel == 0 ? std::max(bc.threads, ss::ids_threads_for(wrd)) : bc.threads;
+        keys.push_back({t, (int)i, len});
+    }
+    std::stable_sort(keys.begin(), keys.end(), [&](const Key &x, const Key &y) {
+        if (x.threads != y.threads) return x.threads > y.threads;
+        if (bc.order == 1) return x.len > y.len;
+        return false;
+    });
+    B.regions.clear();
+    B.groups.clear();
+    B.total_items = 0;
+    int64_t item = 0;
+    for (const Key &k : keys) {
+        if (B.groups.empty() || B.groups.back().threads != k.threads) {
+            Group g;
+            g.first = (int)B.regions.size();
+            g.threads = k.threads;
+            B.groups.push_back(g);
+            item = 0;
+        }
+        Group &g = B.groups.back();
+        const Scan &sc = B.scans[B.wide[k.idx]];
         ss::Region r = region_of(sc);
         r.item0 = item;
-        item += ss::region_items(sc.mode, sc.args.M, kernel);
+        const int64_t n_items = ss::region_items(sc.mode, sc.args.M, bc.kernel);
+        item += n_items;
+        g.count += 1;
+        g.total_items += n_items;
+        g.lmax = std::max(g.lmax, k.len);
+        g.wmax = std::max(g.wmax, row_words(sc.args.nA, sc.args.nB, sc.mode));
+        B.total_items += n_items;
         B.regions.push_back(r);
     }
-    B.total_items = item;
 }
 
 int build_batch(const ss_scan_request *reqs, int32_t n, const ss_params *p, void *d_ws,
@@ -551,23 +595,30 @@ int build_batch(const ss_scan_request *reqs, int32_t n, const ss_params *p, void
     }
     B.d_regions = (ss::Region *)((char *)d_ws + L.regions);
     B.d_counter = (unsigned long long *)((char *)d_ws + L.counter);
-    number_items(B, g_bcfg.order, g_bcfg.kernel);
+    number_items(B, g_bcfg);
+    if ((int)B.groups.size() > kMaxGroups) return fail(SS_EDEV, "too many launch groups");
     return SS_OK;
 }
 
-// The persistent walk over the batch's regions (the first item_limit items
-// if item_limit >= 0).
+// The persistent walks over the batch's regions, one launch per group (the
+// first item_limit items of each group if item_limit >= 0).
 int launch_batch_wide(Batch &B, const ss_batch_config &bc, int64_t item_limit, hipStream_t s) {
     if (B.wide.empty()) return SS_OK;
-    ss::WideCfg c;
-    if (!make_wide_cfg(bc, B.lmax, B.wmax, c))
-        return fail(SS_EDEV, "persistent walk configuration does not fit this device");
     SS_HIP(ss::launch_fill_regions(B.regions.data(), (int)B.regions.size(), B.d_regions, s));
-    SS_HIP(ss::launch_zero_u64(B.d_counter, 1, s));
-    const int64_t total = item_limit >= 0 ? std::min(item_limit, B.total_items) : B.total_items;
-    SS_HIP(c.kernel == 0
-               ? ss::launch_ids_batch(B.d_regions, (int32_t)B.regions.size(), total, B.d_counter, c, s)
-               : ss::launch_wide_walk(B.d_regions, (int32_t)B.regions.size(), total, B.d_counter, c, s));
+    SS_HIP(ss::launch_zero_u64(B.d_counter, kMaxGroups, s));
+    for (size_t gi = 0; gi < B.groups.size(); ++gi) {
+        const Group &g = B.groups[gi];
+        ss::WideCfg c;
+        ss_batch_config gb = bc;
+        gb.threads = g.threads;
+        if (!make_wide_cfg(gb, g.lmax, g.wmax, c))
+            return fail(SS_EDEV, "persistent walk configuration does not fit this device");
+        const int64_t total = item_limit >= 0 ? std::min(item_limit, g.total_items) : g.total_items;
+        ss::Region *regs = B.d_regions + g.first;
+        unsigned long long *ctr = B.d_counter + gi;
+        SS_HIP(c.kernel == 0 ? ss::launch_ids_batch(regs, g.count, total, ctr, c, s)
+                             : ss::launch_wide_walk(regs, g.count, total, ctr, c, s));
+    }
     return SS_OK;
 }
 
@@ -812,12 +863,16 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
         SS_HIP(hipEventCreate(&e0));
         SS_HIP(hipEventCreate(&e1));
         auto time_cfg = [&](const ss_batch_config &c, double &ms) -> int {
-            ss::WideCfg wc;
-            if (!make_wide_cfg(c, B.lmax, B.wmax, wc)) {
-                ms = 1e30;
-                return SS_OK;
+            number_items(B, c);
+            for (const Group &g : B.groups) {
+                ss::WideCfg wc;
+                ss_batch_config gb = c;
+                gb.threads = g.threads;
+                if ((int)B.groups.size() > kMaxGroups || !make_wide_cfg(gb, g.lmax, g.wmax, wc)) {
+                    ms = 1e30;
+                    return SS_OK;
+                }
             }
-            number_items(B, c.order, c.kernel);
             double bestv = 1e30;
             for (int rep = 0; rep < 2; ++rep) {
                 SS_HIP(hipEventRecord(e0, s));
@@ -835,7 +890,7 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
         SS_TRY(time_cfg(cur, cur_ms));
         // kernel and workgroup size together, then one setting at a time
         for (int k : {0, 1}) {
-            for (int t : {128, 256, 512, 1024}) {
+            for (int t : {64, 128, 256, 512, 1024}) {
                 ss_batch_config c = cur;
                 c.kernel = k;
                 c.threads = t;
@@ -853,6 +908,15 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
                 double ms;
                 SS_TRY(time_cfg(c, ms));
                 if (ms < cur_ms) { cur = c; cur_ms = ms; }
+            }
+            if (cur.kernel == 0) {
+                for (int pc : {0, 512, 1024, 2048}) {
+                    ss_batch_config c = cur;
+                    c.small_pair_cap = pc;
+                    double ms;
+                    SS_TRY(time_cfg(c, ms));
+                    if (ms < cur_ms) { cur = c; cur_ms = ms; }
+                }
             }
             for (int bpc : {0, 1, 2, 3, 4}) {
                 ss_batch_config c = cur;

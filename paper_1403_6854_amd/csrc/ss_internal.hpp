@@ -118,7 +118,7 @@ inline int64_t region_items(int mode, int64_t M, int kernel) {
 // Launch configuration of the persistent wide walk.
 struct WideCfg {
     int kernel;      // 0: class ids with a pairwise tail (ss_walk_batch.hip); 1: lists (ss_walk_wide.hip)
-    int threads;     // workgroup size: 256, 512 or 1024 (kernel 0); 128, 256 or 512 (kernel 1)
+    int threads;     // workgroup size: 64 .. 1024 (kernel 0); 128, 256 or 512 (kernel 1)
     int pair_cap;    // pairs held by the pairwise phase
     int key_cap;     // haplotypes whose 64-marker keys the pairwise phase holds
     int chunk;       // items taken per grab of the work counter
@@ -137,6 +137,8 @@ inline int wide_max_list(int threads) { return 64 * threads < 16384 ? 64 * threa
 // Class-id batch walk: slots per thread (0 if the row is too wide), LDS
 // bytes (0 if invalid), workgroups per CU, launch.
 int ids_slots(int threads, int wmax);
+// Smallest workgroup size (64 .. 1024) whose slots hold a row of wmax words.
+int ids_threads_for(int wmax);
 size_t ids_lds_bytes(int threads, int lmax, int wmax, int pair_cap, int key_cap);
 int ids_blocks_per_cu(const WideCfg &c);
 hipError_t launch_ids_batch(const Region *regs, int32_t nreg, int64_t total_items,

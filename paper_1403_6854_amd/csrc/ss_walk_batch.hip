@@ -309,17 +309,16 @@ __device__ void ids_walk(const Region &G, int64_t j, int d, char *base, const BL
                     const uint64_t w = readlane64(rowv[r], i);
                     bit[r] = (int32_t)((w >> lane) & 1ull);
                     const bool live = cls[r] != DEAD;
-                    const uint64_t lm = __ballot(live);
-                    if (lm) {
-                        const int first = (int)__builtin_ctzll(lm);
-                        const int32_t c0 = __builtin_amdgcn_readlane(cls[r], first);
-                        const uint64_t other = __ballot(live && cls[r] != c0);
-                        if (!other) {
-                            const uint32_t ones = (uint32_t)__popcll(__ballot(live && bit[r]));
-                            if (lane == first && ones) atomicAdd(&cnt1[c0], ones * incu[r]);
-                        } else if (live && bit[r]) {
-                            atomicAdd(&cnt1[cls[r]], incu[r]);
+                    // lane 0's class; when every live lane is in it, one atomic
+                    const int32_t c0 = __builtin_amdgcn_readfirstlane(cls[r]);
+                    const uint64_t other = __ballot(live && cls[r] != c0);
+                    if (!other) {
+                        if (c0 != DEAD) {
+                            const uint32_t ones = (uint32_t)__popcll(__ballot(live && bit[r] != 0));
+                            if (lane == 0 && ones) atomicAdd(&cnt1[c0], ones * incu[r]);
                         }
+                    } else if (live && bit[r]) {
+                        atomicAdd(&cnt1[cls[r]], incu[r]);
                     }
                 }
             }
@@ -691,6 +690,9 @@ __global__ void __launch_bounds__(1024) ids_batch_kernel(const Region *__restric
     __shared__ unsigned long long grab;
     char *base = (char *)lds_ids;
     const BLay Ly = batch_layout(lmax, pcap, kcap);
+    // the region of the last item (items of one region are consecutive)
+    Region G;
+    int64_t g_lo = 0, g_hi = -1;
     for (;;) {
         __syncthreads();   // everyone has read the previous grab
         if (threadIdx.x == 0) grab = atomicAdd(counter, (unsigned long long)chunk);
@@ -699,13 +701,17 @@ __global__ void __launch_bounds__(1024) ids_batch_kernel(const Region *__restric
         if (b0 >= total) break;
         const int64_t b1 = b0 + chunk < total ? b0 + chunk : total;
         for (int64_t it = b0; it < b1; ++it) {
-            int lo = 0, hi = nreg - 1;   // last region with item0 <= it
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (regs[mid].item0 <= it) lo = mid;
-                else hi = mid - 1;
+            if (it < g_lo || it >= g_hi) {
+                int lo = 0, hi = nreg - 1;   // last region with item0 <= it
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (regs[mid].item0 <= it) lo = mid;
+                    else hi = mid - 1;
+                }
+                G = regs[lo];
+                g_lo = G.item0;
+                g_hi = lo + 1 < nreg ? regs[lo + 1].item0 : INT64_MAX;
             }
-            const Region G = regs[lo];
             const int64_t loc = it - G.item0;
             const int64_t j = loc >> 1;
             const int d = (int)(loc & 1);
@@ -745,8 +751,13 @@ int ids_slots(int threads, int wmax) {
     return r <= 16 ? r : 0;   // 32 slots would spill registers
 }
 
+int ids_threads_for(int wmax) {
+    const int t = 64 * ((wmax + 15) / 16);   // 16 slots per thread at most
+    return t <= 1024 ? (t > 0 ? t : 64) : 0;
+}
+
 size_t ids_lds_bytes(int threads, int lmax, int wmax, int pair_cap, int key_cap) {
-    if (threads != 256 && threads != 512 && threads != 1024) return 0;
+    if (threads < 64 || threads > 1024 || threads % 64) return 0;
     if (lmax < 2 || lmax > 32767 || ids_slots(threads, wmax) == 0) return 0;
     if (pair_cap < 0 || key_cap < 0 || key_cap > 32767) return 0;
     return batch_layout(lmax, pair_cap, key_cap).total;

@@ -1,0 +1,227 @@
+"""Continuous-batching scan server over ss_scan_batch.
+
+Scan requests -- iHS over one region, or XPEHH over a pair of populations on
+one region -- arrive over time.  The server
+
+  * admits waiting requests first come, first served, while the device memory
+    they need (their haplotype matrices, kept resident until the request is
+    done, plus workspace and outputs) fits the budget;
+  * gathers every request admitted at one admission point into one batch: one
+    ss_scan_batch call, whose EHH walks for all regions share one persistent
+    launch, enqueued on a free stream;
+  * keeps one batch per stream of the backend on the device at once, so
+    requests that arrive while others run are admitted as soon as a stream
+    and memory free up, and their work overlaps on the GPU;
+  * retires a batch when its completion event has fired, releasing its memory.
+
+Latency of a request is completion time minus arrival time.  The per-request
+results are exactly those of the request run alone (every walk kernel gives the
+same answer, and standardization is per region).
+
+``run_back_to_back`` is the reference point: the same requests one at a time in
+arrival order, each a plain single-region scan waited for before the next.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class ServeRequest:
+    rid: int
+    arrival_s: float
+    kind: str                    # "ihs" or "xpehh"
+    nbytes: int                  # device memory held while admitted
+    make: Callable               # () -> (HapMat a, HapMat b or None), enqueued on the current stream
+    n_sites: int = 0
+
+
+@dataclasses.dataclass
+class Completion:
+    rid: int
+    arrival_s: float
+    admit_s: float
+    finish_s: float
+    batch: int
+    out: Optional[dict] = None
+
+    @property
+    def latency_s(self) -> float:
+        return self.finish_s - self.arrival_s
+
+
+def words(n: int) -> int:
+    return (int(n) + 63) // 64
+
+
+def request_bytes(kind: str, n_a: int, n_b: int, n_sites: int, steps: bool = False) -> int:
+    """Device memory of one request while it is admitted (an upper estimate):
+    0/1 alleles during packing, packed matrices, positions, haplotype-major
+    copies, per-site workspace and outputs."""
+    m = int(n_sites)
+    n_tot = n_a + (n_b if kind == "xpehh" else 0)
+    alleles = m * n_tot
+    bits = 8 * m * (words(n_a) + (words(n_b) if kind == "xpehh" else 0))
+    hapmajor = 8 * n_tot * (m // 64 + 3)
+    per_site = 16 + 1 + 4 + 32 + 16 + 16 + 8 + 8 + 8 + 8   # positions, flags, bins, walk records, segments, redo
+    outputs = m * (5 * 8 + 1 + (16 if steps else 0))
+    return alleles + bits + hapmajor + per_site * m + outputs + (1 << 16)
+
+
+class TorchBackend:
+    """Runs batches through ss_scan_batch on a pool of streams."""
+
+    def __init__(self, n_streams: int = 2, params=None, keep=("status",), steps: bool = False):
+        import torch
+        import paper_1403_6854_amd as ss
+        self.ss = ss
+        self.torch = torch
+        self.params = params
+        self.keep = keep
+        self.steps = steps
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.free = list(range(n_streams))
+
+    def slots(self) -> int:
+        return len(self.free)
+
+    def launch(self, reqs: List[ServeRequest]):
+        torch, ss = self.torch, self.ss
+        si = self.free.pop()
+        s = self.streams[si]
+        with torch.cuda.stream(s):
+            srs = []
+            for r in reqs:
+                a, b = r.make()
+                sr = ss.ScanRequest(a, b)
+                ss.alloc_outputs(sr, steps=self.steps)
+                srs.append(sr)
+            ss.scan_batch(srs, self.params, stream=s, validate=False)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return (si, ev, srs)
+
+    def done(self, handle) -> bool:
+        return handle[1].query()
+
+    def retire(self, handle) -> List[dict]:
+        si, ev, srs = handle
+        self.free.append(si)
+        outs = []
+        for sr in srs:
+            outs.append({k: v for k, v in sr.out.items() if self.keep is None or k in self.keep})
+        return outs
+
+
+class Server:
+    """Admission by memory budget, continuous batching, completion polling.
+
+    ``backend`` provides slots() (free streams), launch(list) -> handle,
+    done(handle) -> bool and retire(handle) -> per-request outputs; ``clock``
+    and ``sleep`` are injectable so the policy can be exercised off the GPU.
+    """
+
+    def __init__(self, backend, budget_bytes: int, max_batch: int = 64,
+                 clock: Callable[[], float] = time.perf_counter,
+                 sleep: Callable[[float], None] = time.sleep, poll_s: float = 1e-4):
+        if budget_bytes <= 0 or max_batch < 1:
+            raise ValueError("budget_bytes and max_batch must be positive")
+        self.backend = backend
+        self.budget = int(budget_bytes)
+        self.max_batch = int(max_batch)
+        self.clock = clock
+        self.sleep = sleep
+        self.poll_s = poll_s
+        self.peak_bytes = 0
+        self.batches = 0
+        self.batch_sizes: List[int] = []
+
+    def run(self, requests: List[ServeRequest]) -> List[Completion]:
+        reqs = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
+        t0 = self.clock()
+        nxt = 0
+        pending = collections.deque()
+        inflight = []          # (handle, [(req, admit_s)], bytes, batch id)
+        used = 0
+        done: List[Completion] = []
+        while nxt < len(reqs) or pending or inflight:
+            now = self.clock() - t0
+            while nxt < len(reqs) and reqs[nxt].arrival_s <= now:
+                pending.append(reqs[nxt])
+                nxt += 1
+            progressed = False
+            for item in list(inflight):
+                handle, members, nbytes, bid = item
+                if self.backend.done(handle):
+                    fin = self.clock() - t0
+                    outs = self.backend.retire(handle)
+                    for (r, adm), o in zip(members, outs):
+                        done.append(Completion(r.rid, r.arrival_s, adm, fin, bid, o))
+                    used -= nbytes
+                    inflight.remove(item)
+                    progressed = True
+            if pending and self.backend.slots() > 0:
+                batch, nbytes = [], 0
+                while pending and len(batch) < self.max_batch:
+                    r = pending[0]
+                    if used + nbytes + r.nbytes > self.budget:
+                        # a request larger than the whole budget runs alone
+                        if not (r.nbytes > self.budget and not batch and not inflight):
+                            break
+                    batch.append(pending.popleft())
+                    nbytes += r.nbytes
+                if batch:
+                    adm = self.clock() - t0
+                    handle = self.backend.launch(batch)
+                    used += nbytes
+                    self.peak_bytes = max(self.peak_bytes, used)
+                    inflight.append((handle, [(r, adm) for r in batch], nbytes, self.batches))
+                    self.batch_sizes.append(len(batch))
+                    self.batches += 1
+                    progressed = True
+            if not progressed:
+                if not inflight and not pending and nxt < len(reqs):
+                    wait = reqs[nxt].arrival_s - (self.clock() - t0)
+                    if wait > 0:
+                        self.sleep(min(wait, 0.01))
+                else:
+                    self.sleep(self.poll_s)
+        return done
+
+
+def run_back_to_back(requests: List[ServeRequest], run_one: Callable,
+                     clock: Callable[[], float] = time.perf_counter,
+                     sleep: Callable[[float], None] = time.sleep) -> List[Completion]:
+    """Each request in arrival order, alone: ``run_one(request)`` runs the
+    scan and returns when its results are complete."""
+    reqs = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
+    t0 = clock()
+    out = []
+    for i, r in enumerate(reqs):
+        while clock() - t0 < r.arrival_s:
+            sleep(min(0.01, r.arrival_s - (clock() - t0)))
+        adm = clock() - t0
+        o = run_one(r)
+        out.append(Completion(r.rid, r.arrival_s, adm, clock() - t0, i, o))
+    return out
+
+
+def summarize(done: List[Completion]) -> dict:
+    lat = np.array([c.latency_s for c in done])
+    if lat.size == 0:
+        return {"requests": 0}
+    first = min(c.arrival_s for c in done)
+    last = max(c.finish_s for c in done)
+    return {
+        "requests": int(lat.size),
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "mean_ms": float(lat.mean() * 1e3),
+        "makespan_s": float(last - first),
+        "requests_per_s": float(lat.size / max(last - first, 1e-9)),
+    }

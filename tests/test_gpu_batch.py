@@ -106,9 +106,10 @@ def test_batch_matches_oracle_and_single_calls(ss, regions, small_kernel):
             np.testing.assert_array_equal(g[k], one[k], err_msg=kind + " " + k)
 
 
-CONFIGS = [dict(threads=256), dict(threads=1024), dict(pair_cap=0), dict(pair_cap=1024),
+CONFIGS = [dict(threads=64), dict(threads=256), dict(threads=1024), dict(pair_cap=0), dict(pair_cap=1024),
            dict(pair_cap=8192), dict(pair_cap=16384), dict(chunk=7), dict(order=1),
            dict(blocks_per_cu=1), dict(threads=1024, pair_cap=4096, chunk=3, order=1),
+           dict(small_pair_cap=1024), dict(threads=128, small_pair_cap=4096, pair_cap=0),
            dict(kernel=1, threads=128), dict(kernel=1, threads=256), dict(kernel=1, threads=512),
            dict(kernel=1, threads=256, pair_cap=0), dict(kernel=1, threads=128, pair_cap=8192,
                                                             chunk=3, order=1)]
@@ -164,7 +165,7 @@ def test_autotune_then_parity(ss, regions):
         cfg, ms, ws = ss.autotune_batch(reqs, sample_items=0)
         assert ms > 0.0
         assert cfg.kernel in (0, 1) and cfg.small_kernel == 0
-        assert cfg.threads in ((256, 512, 1024) if cfg.kernel == 0 else (128, 256, 512))
+        assert cfg.threads in ((64, 128, 256, 512, 1024) if cfg.kernel == 0 else (128, 256, 512))
         assert ss.get_batch_config() == cfg
         ss.scan_batch(reqs, ws=ws)
         got = [_np(r.out) for r in reqs]

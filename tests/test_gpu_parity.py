@@ -40,7 +40,7 @@ def walk(request, ss):
     it): the plain class-id kernel, the bitmask kernel, and both kernels of the
     persistent batch walk."""
     if request.param == "batch_ids":
-        ss.set_batch_config(ss.BatchConfig(kernel=0, threads=512))
+        ss.set_batch_config(ss.BatchConfig(kernel=0))
         ss.set_walk_kernel(3)
     elif request.param == "batch_lists":
         ss.set_batch_config(ss.BatchConfig(kernel=1, threads=256))

@@ -1,0 +1,146 @@
+"""The serving policy of paper_1403_6854_amd.serve on a simulated device:
+admission by memory budget, first come first served, continuous batching,
+one completion per request, latency accounting."""
+import numpy as np
+import pytest
+
+from paper_1403_6854_amd import serve
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-6)
+
+
+class FakeBackend:
+    """Streams that finish a batch `cost(batch)` seconds after its launch."""
+
+    def __init__(self, clock, n_streams=2, cost=lambda b: 0.01 * len(b)):
+        self.clock = clock
+        self.free = list(range(n_streams))
+        self.cost = cost
+        self.active_bytes = 0
+        self.max_active = 0
+        self.launches = []
+
+    def slots(self):
+        return len(self.free)
+
+    def launch(self, reqs):
+        si = self.free.pop()
+        nb = sum(r.nbytes for r in reqs)
+        self.active_bytes += nb
+        self.max_active = max(self.max_active, self.active_bytes)
+        self.launches.append((self.clock(), [r.rid for r in reqs]))
+        return (si, self.clock() + self.cost(reqs), reqs, nb)
+
+    def done(self, h):
+        return self.clock() >= h[1]
+
+    def retire(self, h):
+        self.free.append(h[0])
+        self.active_bytes -= h[3]
+        return [{"rid": r.rid} for r in h[2]]
+
+
+def _reqs(n, rate=100.0, nbytes=10, seed=0):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    sizes = nbytes if np.isscalar(nbytes) else nbytes
+    out = []
+    for i in range(n):
+        b = int(sizes if np.isscalar(sizes) else sizes[i])
+        out.append(serve.ServeRequest(i, float(t[i]), "ihs", b, make=None))
+    return out
+
+
+def _run(reqs, budget=10**9, max_batch=64, n_streams=2, cost=lambda b: 0.01 * len(b)):
+    clk = FakeClock()
+    be = FakeBackend(clk, n_streams, cost)
+    srv = serve.Server(be, budget, max_batch=max_batch, clock=clk, sleep=clk.sleep, poll_s=1e-4)
+    done = srv.run(reqs)
+    return done, be, srv
+
+
+def test_every_request_completes_once_with_its_own_output():
+    reqs = _reqs(300)
+    done, be, srv = _run(reqs)
+    assert sorted(c.rid for c in done) == list(range(300))
+    for c in done:
+        assert c.out == {"rid": c.rid}
+        assert c.arrival_s <= c.admit_s <= c.finish_s
+    assert sum(srv.batch_sizes) == 300
+
+
+def test_budget_is_never_exceeded():
+    rng = np.random.default_rng(4)
+    sizes = rng.integers(1, 40, size=200)
+    reqs = _reqs(200, rate=1000.0, nbytes=sizes)
+    done, be, srv = _run(reqs, budget=100, cost=lambda b: 0.005 * len(b))
+    assert len(done) == 200
+    assert be.max_active <= 100
+    assert srv.peak_bytes <= 100
+
+
+def test_first_come_first_served():
+    reqs = _reqs(150, rate=500.0)
+    done, be, srv = _run(reqs, budget=35, max_batch=4)
+    order = [rid for _, rids in be.launches for rid in rids]
+    assert order == sorted(order)
+    adm = {c.rid: c.admit_s for c in done}
+    assert all(adm[i] <= adm[i + 1] for i in range(149))
+
+
+def test_requests_batch_up_under_load_and_not_when_idle():
+    slow = _reqs(200, rate=2000.0)
+    _, _, srv = _run(slow, cost=lambda b: 0.02 + 0.001 * len(b))
+    assert max(srv.batch_sizes) > 1
+    idle = _reqs(50, rate=1.0)
+    _, _, srv2 = _run(idle, cost=lambda b: 0.001)
+    assert max(srv2.batch_sizes) == 1
+
+
+def test_batches_overlap_on_several_streams():
+    reqs = _reqs(100, rate=2000.0)
+    _, be, _ = _run(reqs, n_streams=3, max_batch=2, cost=lambda b: 0.05)
+    starts = [t for t, _ in be.launches]
+    # with three streams, the second and third batch start before the first ends
+    assert starts[2] < starts[0] + 0.05
+
+
+def test_oversized_request_runs_alone():
+    reqs = _reqs(10, rate=1000.0, nbytes=[5, 5, 500, 5, 5, 5, 5, 5, 5, 5])
+    done, be, srv = _run(reqs, budget=50)
+    assert len(done) == 10
+    big = [rids for _, rids in be.launches if 2 in rids]
+    assert big == [[2]]
+
+
+def test_summary_and_back_to_back():
+    reqs = _reqs(40, rate=50.0)
+    clk = FakeClock()
+
+    def run_one(r):
+        clk.t += 0.03
+        return {"rid": r.rid}
+
+    seq = serve.run_back_to_back(reqs, run_one, clock=clk, sleep=clk.sleep)
+    assert [c.rid for c in seq] == list(range(40))
+    assert all(c.finish_s - c.admit_s == pytest.approx(0.03) for c in seq)
+    s = serve.summarize(seq)
+    assert s["requests"] == 40 and s["p99_ms"] >= s["p50_ms"] >= 30.0 - 1e-6
+
+
+def test_request_bytes_grow_with_the_region():
+    a = serve.request_bytes("ihs", 100, 0, 1000)
+    b = serve.request_bytes("ihs", 5000, 0, 1000)
+    c = serve.request_bytes("xpehh", 5000, 5000, 1000)
+    d = serve.request_bytes("xpehh", 5000, 5000, 200000)
+    assert a < b < c < d
+    assert d > 5000 * 2 * 200000   # the 0/1 matrices alone
