@@ -104,7 +104,7 @@ def bench_batched(ss, torch, dev, reps: int = 3):
     ss.alloc_outputs(req)
     log("batched: autotuning the persistent walk")
     t0 = time.perf_counter()
-    cfg, tune_ms, ws = ss.autotune_batch([req], stream=stream, sample_items=200_000)
+    cfg, tune_ms, ws = ss.autotune_batch([req], stream=stream, sample_items=400_000)
     tune_s = time.perf_counter() - t0
     # walk kernel alone (eager, timed with events on the stream)
     ss.scan_batch([req], stream=stream, ws=ws, validate=False)
@@ -199,7 +199,7 @@ def bench_served(ss, torch, dev, args):
         q = ss.ScanRequest(a, b)
         ss.alloc_outputs(q)
         tune.append(q)
-    cfg, _, _ = ss.autotune_batch(tune)
+    cfg, _, _ = ss.autotune_batch(tune, sample_items=0)
     del tune
     warm = [dataclasses.replace(s, arrival_s=0.0) for s in specs[:12]]
     serve.Server(serve.TorchBackend(args.serve_streams), budget).run(reqs_of(warm))

@@ -390,25 +390,33 @@ def request_stream(n_requests: Optional[int] = None, rate_per_s: Optional[float]
 
 
 def _device_copy(gen, founders, n_haps: int, switch_p: float, flip_p: float, chunk: int = 16384):
-    """Founder copying on the device (dense draws from ``gen``), drawn
-    haplotype-major so that the founder path is a scan along the contiguous
-    axis; returned site-major."""
+    """Founder copying on the device, drawn haplotype-major so that the
+    founder path is a scan along the contiguous axis; returned site-major.
+
+    One uniform u per (haplotype, site) decides the switch (u < switch_p) and,
+    rescaled to [0, 1), which other founder is taken next; a second uniform
+    decides the flip."""
     import torch
     F, M = founders.shape
     dev = founders.device
     out = torch.empty((M, n_haps), dtype=torch.uint8, device=dev)
-    cur = torch.randint(0, F, (n_haps,), generator=gen, device=dev)
+    cur = torch.randint(0, F, (n_haps,), generator=gen, device=dev).to(torch.int32)
     for s0 in range(0, M, chunk):
         s1 = min(M, s0 + chunk)
-        sw = torch.rand((n_haps, s1 - s0), generator=gen, device=dev) < switch_p
+        u = torch.rand((n_haps, s1 - s0), generator=gen, device=dev)
+        if F >= 2:
+            step = torch.where(u < switch_p,
+                               1 + torch.clamp((u * (1.0 / switch_p) * (F - 1)).to(torch.int32),
+                                               max=F - 2),
+                               torch.zeros((), dtype=torch.int32, device=dev))
+        else:
+            step = torch.zeros_like(u, dtype=torch.int32)
         if s0 == 0:
-            sw[:, 0] = False
-        step = torch.randint(1, max(2, F), (n_haps, s1 - s0), generator=gen, device=dev)
-        step = step * sw if F >= 2 else torch.zeros_like(step)
-        path = torch.remainder(cur[:, None] + torch.cumsum(step, dim=1), F)
+            step[:, 0] = 0
+        path = torch.remainder(cur[:, None] + torch.cumsum(step, dim=1, dtype=torch.int32), F)
         cur = path[:, -1].clone()
-        col = torch.arange(s0, s1, device=dev)[None, :]
-        block = founders[path, col]
+        col = torch.arange(s0, s1, device=dev, dtype=torch.int32)[None, :]
+        block = founders[path.long(), col.long()]
         flips = torch.rand((n_haps, s1 - s0), generator=gen, device=dev) < flip_p
         out[s0:s1] = (block ^ flips.to(torch.uint8)).t()
     return out
@@ -426,14 +434,14 @@ def device_region(spec: RequestSpec, device="cuda"):
     gen.manual_seed(int(spec.seed))
     F, M = c["n_founders"], spec.n_sites
     # Beta(1/2, 1/2) is the arcsine law: sin^2(pi U / 2)
-    p = torch.sin(0.5 * math.pi * torch.rand(M, generator=gen, device=device, dtype=torch.float64)) ** 2
-    fa = (torch.rand((F, M), generator=gen, device=device, dtype=torch.float64) < p[None, :]).to(torch.uint8)
+    p = torch.sin(0.5 * math.pi * torch.rand(M, generator=gen, device=device)) ** 2
+    fa = (torch.rand((F, M), generator=gen, device=device) < p[None, :]).to(torch.uint8)
     a = _device_copy(gen, fa, spec.n_a, c["switch_p"], c["flip_p"])
     b = None
     if spec.kind == "xpehh":
-        p2 = torch.sin(0.5 * math.pi * torch.rand(M, generator=gen, device=device, dtype=torch.float64)) ** 2
-        fresh = (torch.rand((F, M), generator=gen, device=device, dtype=torch.float64) < p2[None, :]).to(torch.uint8)
-        keep = torch.rand((F, M), generator=gen, device=device, dtype=torch.float64) < c["share_p"]
+        p2 = torch.sin(0.5 * math.pi * torch.rand(M, generator=gen, device=device)) ** 2
+        fresh = (torch.rand((F, M), generator=gen, device=device) < p2[None, :]).to(torch.uint8)
+        keep = torch.rand((F, M), generator=gen, device=device) < c["share_p"]
         fb = torch.where(keep, fa, fresh)
         b = _device_copy(gen, fb, spec.n_b, c["switch_p"], c["flip_p"])
     return (a, b, torch.from_numpy(pos).to(device), torch.from_numpy(gpos).to(device))

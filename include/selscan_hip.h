@@ -228,7 +228,7 @@ int ss_scan_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_params *
 typedef struct ss_batch_config {
     int32_t threads;        /* workgroup size.  Kernel 0: a multiple of 64 in [64, 1024],
                                a minimum -- each region takes the smallest size that
-                               holds its rows (16 64-haplotype words per wave), and
+                               holds its rows (`slots` 64-haplotype words per wave), and
                                regions of one size share one launch; kernel 1: 128, 256
                                or 512                                                   */
     int32_t pair_cap;       /* pairs, and haplotypes, the pairwise phase holds: 0..16384
@@ -244,6 +244,9 @@ typedef struct ss_batch_config {
     int32_t small_pair_cap; /* kernel 0: pair capacity of the launches of 64 or 128
                                threads (regions of up to 2048 haplotypes in the walk),
                                whose occupancy the pair buffers would halve; 0..16384    */
+    int32_t slots;          /* kernel 0: 64-haplotype words per wave (4, 8 or 16
+                               [default]): fewer words per wave spread a walk over more
+                               waves; rows wider than 16 waves of them take 16 per wave */
 } ss_batch_config;
 
 int ss_get_batch_config(ss_batch_config *c);
@@ -252,8 +255,9 @@ int ss_set_batch_config(const ss_batch_config *c);
 
 /*
  * ss_autotune_batch -- time candidate configurations of the persistent walk on
- * these requests (the walks of the first sample_items work items, or all if
- * sample_items <= 0), keep the fastest as the process-wide configuration and
+ * these requests (the walks of about sample_items work items per launch group,
+ * spread evenly over its sites, or all if sample_items <= 0), keep the fastest
+ * as the process-wide configuration and
  * return it with its time.  Blocks until the timings are done; the outputs of
  * the requests are left undefined (run ss_scan_batch afterwards).
  * Errors: as ss_scan_batch.

@@ -63,7 +63,8 @@ class _BatchConfig(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("pair_cap", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("small_kernel", ctypes.c_int32),
-                ("kernel", ctypes.c_int32), ("small_pair_cap", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("small_pair_cap", ctypes.c_int32),
+                ("slots", ctypes.c_int32)]
 
 
 _lib = None
@@ -424,26 +425,27 @@ def scan_batch(reqs, params: Optional[Params] = None, stream=None,
 class BatchConfig:
     """Launch configuration of the persistent walk (see ss_batch_config)."""
     threads: int = 64
-    pair_cap: int = 2048
+    pair_cap: int = 4096
     chunk: int = 1
     blocks_per_cu: int = 0
     order: int = 0
     small_kernel: int = 1
     kernel: int = 0
-    small_pair_cap: int = 0
+    small_pair_cap: int = 1024
+    slots: int = 16
 
 
 def get_batch_config() -> BatchConfig:
     c = _BatchConfig()
     _check(lib().ss_get_batch_config(ctypes.byref(c)))
     return BatchConfig(c.threads, c.pair_cap, c.chunk, c.blocks_per_cu, c.order, c.small_kernel,
-                       c.kernel, c.small_pair_cap)
+                       c.kernel, c.small_pair_cap, c.slots)
 
 
 def set_batch_config(cfg: BatchConfig):
     c = _BatchConfig(int(cfg.threads), int(cfg.pair_cap), int(cfg.chunk), int(cfg.blocks_per_cu),
                      int(cfg.order), int(cfg.small_kernel), int(cfg.kernel),
-                     int(cfg.small_pair_cap))
+                     int(cfg.small_pair_cap), int(cfg.slots))
     _check(lib().ss_set_batch_config(ctypes.byref(c)))
 
 
@@ -464,7 +466,7 @@ def autotune_batch(reqs, params: Optional[Params] = None, stream=None,
                                    ws.numel() - (base - ws.data_ptr()), _stream(stream),
                                    int(sample_items), ctypes.byref(best), ctypes.byref(ms)))
     cfg = BatchConfig(best.threads, best.pair_cap, best.chunk, best.blocks_per_cu, best.order,
-                      best.small_kernel, best.kernel, best.small_pair_cap)
+                      best.small_kernel, best.kernel, best.small_pair_cap, best.slots)
     return cfg, float(ms.value), ws
 
 

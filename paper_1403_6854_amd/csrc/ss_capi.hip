@@ -176,7 +176,7 @@ hipEvent_t take_event() {
 
 int g_walk_kind = ss::WALK_AUTO;
 int g_mask_lpc = 0;   // lanes per class of the bitmask walk; 0 = default
-ss_batch_config g_bcfg = {64, 2048, 1, 0, 0, 1, 0, 0};
+ss_batch_config g_bcfg = {64, 4096, 1, 0, 0, 1, 0, 1024, 16};
 bool g_graph_on = false;
 bool g_capturing = false;   // timing events are not recorded into graphs
 
@@ -189,6 +189,7 @@ int check_batch_config(const ss_batch_config &c) {
     if (c.pair_cap < 0 || c.pair_cap > 16384) return fail(SS_EARG, "pair_cap must be in [0, 16384]");
     if (c.small_pair_cap < 0 || c.small_pair_cap > 16384)
         return fail(SS_EARG, "small_pair_cap must be in [0, 16384]");
+    if (c.slots != 4 && c.slots != 8 && c.slots != 16) return fail(SS_EARG, "slots must be 4, 8 or 16");
     if (c.chunk < 1 || c.chunk > 4096) return fail(SS_EARG, "chunk must be in [1, 4096]");
     if (c.blocks_per_cu < 0 || c.blocks_per_cu > 64) return fail(SS_EARG, "blocks_per_cu must be in [0, 64]");
     if (c.order != 0 && c.order != 1) return fail(SS_EARG, "order must be 0 or 1");
@@ -207,7 +208,7 @@ bool make_wide_cfg(const ss_batch_config &bc, int lmax, int wmax, ss::WideCfg &c
     c.wmax = wmax;
     if (bc.kernel == 0) {
         // the configured size is a minimum: wider rows take larger workgroups
-        const int need = ss::ids_threads_for(wmax);
+        const int need = ss::ids_threads_for(wmax, bc.slots);
         if (need == 0) return false;
         c.threads = std::max(bc.threads, need);
         if (c.threads <= 128) c.pair_cap = bc.small_pair_cap;
@@ -445,8 +446,8 @@ int walk_scan(Scan &sc, hipStream_t s) {
         SS_HIP(ss::launch_zero_u64(sc.w.counter, 1, s));
         TimedRegion t(s);
         SS_TRY(t.begin());
-        SS_HIP(c.kernel == 0 ? ss::launch_ids_batch(sc.w.region, 1, items, sc.w.counter, c, s)
-                             : ss::launch_wide_walk(sc.w.region, 1, items, sc.w.counter, c, s));
+        SS_HIP(c.kernel == 0 ? ss::launch_ids_batch(sc.w.region, 1, items, 1, sc.w.counter, c, s)
+                             : ss::launch_wide_walk(sc.w.region, 1, items, 1, sc.w.counter, c, s));
         return t.end();
     }
     TimedRegion t(s);
@@ -526,7 +527,8 @@ void number_items(Batch &B, const ss_batch_config &bc) {
         const Scan &sc = B.scans[B.wide[i]];
         const int len = list_len(sc.args.nA, sc.args.nB, sc.mode);
         const int wrd = row_words(sc.args.nA, sc.args.nB, sc.mode);
-        const int t = bc.kernel == 0 ? std::max(bc.threads, ss::ids_threads_for(wrd)) : bc.threads;
+        const int t = bc.kernel == 0 ? std::max(bc.threads, ss::ids_threads_for(wrd, bc.slots))
+                                     : bc.threads;
         keys.push_back({t, (int)i, len});
     }
     std::stable_sort(keys.begin(), keys.end(), [&](const Key &x, const Key &y) {
@@ -600,9 +602,9 @@ int build_batch(const ss_scan_request *reqs, int32_t n, const ss_params *p, void
     return SS_OK;
 }
 
-// The persistent walks over the batch's regions, one launch per group (the
-// first item_limit items of each group if item_limit >= 0).
-int launch_batch_wide(Batch &B, const ss_batch_config &bc, int64_t item_limit, hipStream_t s) {
+// The persistent walks over the batch's regions, one launch per group;
+// sample_stride > 1 walks only every sample_stride-th item of each group.
+int launch_batch_wide(Batch &B, const ss_batch_config &bc, int64_t sample_stride, hipStream_t s) {
     if (B.wide.empty()) return SS_OK;
     SS_HIP(ss::launch_fill_regions(B.regions.data(), (int)B.regions.size(), B.d_regions, s));
     SS_HIP(ss::launch_zero_u64(B.d_counter, kMaxGroups, s));
@@ -613,11 +615,16 @@ int launch_batch_wide(Batch &B, const ss_batch_config &bc, int64_t item_limit, h
         gb.threads = g.threads;
         if (!make_wide_cfg(gb, g.lmax, g.wmax, c))
             return fail(SS_EDEV, "persistent walk configuration does not fit this device");
-        const int64_t total = item_limit >= 0 ? std::min(item_limit, g.total_items) : g.total_items;
+        const int64_t stride = sample_stride > 1 ? sample_stride : 1;
+        int64_t total = g.total_items;
+        if (stride > 1) {   // blocks of 256 items, one in every `stride`
+            const int64_t blocks = (g.total_items + 255) / 256;
+            total = 256 * ((blocks + stride - 1) / stride);
+        }
         ss::Region *regs = B.d_regions + g.first;
         unsigned long long *ctr = B.d_counter + gi;
-        SS_HIP(c.kernel == 0 ? ss::launch_ids_batch(regs, g.count, total, ctr, c, s)
-                             : ss::launch_wide_walk(regs, g.count, total, ctr, c, s));
+        SS_HIP(c.kernel == 0 ? ss::launch_ids_batch(regs, g.count, total, stride, ctr, c, s)
+                             : ss::launch_wide_walk(regs, g.count, total, stride, ctr, c, s));
     }
     return SS_OK;
 }
@@ -628,7 +635,7 @@ int enqueue_batch(Batch &B, const ss_params *p, hipStream_t s) {
     SS_TRY(t.begin());
     for (auto &sc : B.scans)
         if (sc.route != RT_WIDE) SS_TRY(walk_direct(sc, s));
-    SS_TRY(launch_batch_wide(B, g_bcfg, -1, s));
+    SS_TRY(launch_batch_wide(B, g_bcfg, 1, s));
     SS_TRY(t.end());
     for (auto &sc : B.scans) SS_TRY(finish_scan(sc, s));
     return SS_OK;
@@ -855,10 +862,18 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
     hipStream_t s = (hipStream_t)stream;
     for (auto &sc : B.scans) SS_TRY(prepare_scan(sc, p, s));
     ss_batch_config cur = g_bcfg;
+    if (cur.kernel == 0) cur.threads = 64;
     double cur_ms = 0.0;
     if (!B.wide.empty()) {
-        const bool whole = sample_items <= 0 || sample_items >= B.total_items;
-        const int64_t limit = whole ? -1 : sample_items;
+        // the sample: blocks of 256 consecutive items (runs of neighbouring
+        // sites, as the full walk sees them), one block in every `stride` of
+        // each launch group -- the same fraction of the work for every
+        // candidate, whether an item is a (site, direction) or, in the list
+        // kernel, one core of it
+        int64_t pairs = 0;
+        for (int i : B.wide) pairs += 2 * B.scans[i].args.M;
+        const bool whole = sample_items <= 0 || sample_items >= pairs;
+        const int64_t stride = whole ? 1 : pairs / sample_items;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         SS_HIP(hipEventCreate(&e0));
         SS_HIP(hipEventCreate(&e1));
@@ -876,7 +891,7 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
             double bestv = 1e30;
             for (int rep = 0; rep < 2; ++rep) {
                 SS_HIP(hipEventRecord(e0, s));
-                SS_TRY(launch_batch_wide(B, c, limit, s));
+                SS_TRY(launch_batch_wide(B, c, stride, s));
                 SS_HIP(hipEventRecord(e1, s));
                 SS_HIP(hipEventSynchronize(e1));
                 float f = 0.f;
@@ -889,11 +904,13 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
         SS_TRY(time_cfg(cur, cur_ms));   // warm-up and baseline
         SS_TRY(time_cfg(cur, cur_ms));
         // kernel and workgroup size together, then one setting at a time
+        // kernel 0 gives each region the smallest workgroup holding its rows
         for (int k : {0, 1}) {
-            for (int t : {64, 128, 256, 512, 1024}) {
+            for (int t : {64, 128, 256, 512}) {
                 ss_batch_config c = cur;
                 c.kernel = k;
                 c.threads = t;
+                if (k == 0 && t != 64) continue;
                 if (check_batch_config(c) != SS_OK) continue;
                 double ms;
                 SS_TRY(time_cfg(c, ms));
@@ -925,7 +942,16 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
                 SS_TRY(time_cfg(c, ms));
                 if (ms < cur_ms) { cur = c; cur_ms = ms; }
             }
-            for (int ch : {1, 2, 8}) {
+            if (cur.kernel == 0) {
+                for (int sl : {4, 8, 16}) {
+                    ss_batch_config c = cur;
+                    c.slots = sl;
+                    double ms;
+                    SS_TRY(time_cfg(c, ms));
+                    if (ms < cur_ms) { cur = c; cur_ms = ms; }
+                }
+            }
+            for (int ch : {1, 2, 4, 8}) {
                 ss_batch_config c = cur;
                 c.chunk = ch;
                 double ms;

@@ -137,16 +137,22 @@ inline int wide_max_list(int threads) { return 64 * threads < 16384 ? 64 * threa
 // Class-id batch walk: slots per thread (0 if the row is too wide), LDS
 // bytes (0 if invalid), workgroups per CU, launch.
 int ids_slots(int threads, int wmax);
-// Smallest workgroup size (64 .. 1024) whose slots hold a row of wmax words.
-int ids_threads_for(int wmax);
+// Smallest workgroup size (64 .. 1024) whose waves hold a row of wmax words
+// with at most `slots` words per wave (16 per wave when that would need more
+// than 1024 threads); 0 if the row does not fit.
+int ids_threads_for(int wmax, int slots);
 size_t ids_lds_bytes(int threads, int lmax, int wmax, int pair_cap, int key_cap);
 int ids_blocks_per_cu(const WideCfg &c);
 hipError_t launch_ids_batch(const Region *regs, int32_t nreg, int64_t total_items,
-                            unsigned long long *counter, const WideCfg &c, hipStream_t s);
+                            int64_t stride, unsigned long long *counter, const WideCfg &c,
+                            hipStream_t s);
 hipError_t launch_fill_regions(const Region *host, int n, Region *dev, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+// Persistent walks over total_items items; with stride > 1 item v stands for
+// item 256 * stride * (v / 256) + v % 256 (a sample in blocks of 256).
 hipError_t launch_wide_walk(const Region *regs, int32_t nreg, int64_t total_items,
-                            unsigned long long *counter, const WideCfg &c, hipStream_t s);
+                            int64_t stride, unsigned long long *counter, const WideCfg &c,
+                            hipStream_t s);
 
 // Site-level kernels.
 hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps,

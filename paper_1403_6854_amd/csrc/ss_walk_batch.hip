@@ -11,11 +11,9 @@
 //   * slot r of wave w holds the 64 haplotypes of word w + r * (T / 64) of the
 //     marker rows; lane l's allele is bit l of the row word, its class id a
 //     register.  Per marker the members with allele 1 count into their
-//     class's LDS counter -- one atomic per word when all live lanes of the
-//     word share a class (a large class of identical haplotypes costs one
-//     atomic per 64 members) -- then one pass over the classes makes the
-//     children, drops those with < 2 members (and the classes of a core whose
-//     walk has stopped), gives the survivors dense ids, and sums C(., 2);
+//     class's LDS counter, then one pass over the classes makes the children,
+//     drops those with < 2 members (and the classes of a core whose walk has
+//     stopped), gives the survivors dense ids, and sums C(., 2);
 //   * once the identical pairs left (the iHS cores' pairs, or the pooled
 //     pairs of XPEHH) number at most the pair capacity, the live classes are
 //     expanded into the list of those pairs and each pass covers 64 markers:
@@ -137,8 +135,11 @@ __host__ __device__ inline BLay batch_layout(int lmax, int pcap, int kcap) {
 }
 
 template <int MODE, int R>
-__device__ void ids_walk(const Region &G, int64_t j, int d, char *base, const BLay &Ly, int pcap,
-                         int kcap) {
+__device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *base,
+                         const BLay &Ly, int pcap, int kcap) {
+    // fields are read through the pointer where they are used (scalar loads),
+    // so that a copy of the descriptor does not hold registers for the walk
+    const Region &G = *Gp;
     const int T = (int)blockDim.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -164,35 +165,21 @@ __device__ void ids_walk(const Region &G, int64_t j, int d, char *base, const BL
         init[tid] = 0u;
     }
 
-    // slot r: 64-haplotype word wave + r * wpg of the pooled word space
-    const uint64_t *src[R];
-    int64_t stride[R];
-    uint32_t incu[R];   // per-slot increment of the class counters (A: 1, B: 1 << 16)
+    // slot r: 64-haplotype word wq = wave + r * wpg of the pooled word space
+    // (A's words, then B's); its row word at site k is computed where needed
+    const int Wused = WA + WB;
+    auto row_at = [&](int r, int64_t k) -> uint64_t {
+        const int wq = wave + r * wpg;
+        return wq < WA ? G.bitsA[k * G.wpsA + wq] : G.bitsB[k * G.wpsB + (wq - WA)];
+    };
+    auto word = [&](int r) -> bool { return wave + r * wpg < Wused; };
+    auto incu = [&](int r) -> uint32_t { return wave + r * wpg < WA ? 1u : 0x10000u; };
     int32_t cls[R];
-    bool word[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int wq = wave + r * wpg;
-        bool valid;
-        if (wq < WA) {
-            src[r] = G.bitsA + wq;
-            stride[r] = G.wpsA;
-            valid = wq * 64 + lane < nA;
-            incu[r] = 1u;
-            word[r] = true;
-        } else if (MODE == MODE_POOLED && wq < WA + WB) {
-            src[r] = G.bitsB + (wq - WA);
-            stride[r] = G.wpsB;
-            valid = (wq - WA) * 64 + lane < nB;
-            incu[r] = 0x10000u;
-            word[r] = true;
-        } else {
-            src[r] = G.bitsA;
-            stride[r] = 0;
-            valid = false;
-            incu[r] = 0u;
-            word[r] = false;
-        }
+        const bool valid = wq < WA ? wq * 64 + lane < nA
+                                   : (wq < Wused && (wq - WA) * 64 + lane < nB);
         cls[r] = valid ? 0 : DEAD;
     }
     __syncthreads();
@@ -200,12 +187,12 @@ __device__ void ids_walk(const Region &G, int64_t j, int d, char *base, const BL
     // classes at x0: id = allele
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        if (word[r]) {
-            const uint64_t w = src[r][j * stride[r]];
+        if (word(r)) {
+            const uint64_t w = row_at(r, j);
             const int32_t bit = (int32_t)((w >> lane) & 1ull);
             if (cls[r] != DEAD) {
                 cls[r] = bit;
-                atomicAdd(&init[bit], incu[r]);
+                atomicAdd(&init[bit], incu(r));
             }
         }
     }
@@ -274,7 +261,7 @@ __device__ void ids_walk(const Region &G, int64_t j, int d, char *base, const BL
         const bool inr = kb >= 0 && kb < G.M;
         uint64_t rowv[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) rowv[r] = (word[r] && inr) ? src[r][kb * stride[r]] : 0ull;
+        for (int r = 0; r < R; ++r) rowv[r] = (word(r) && inr) ? row_at(r, kb) : 0ull;
         int32_t stl = ST_OK;
         double gl = 0.0;
         if (!inr) {
@@ -300,26 +287,15 @@ __device__ void ids_walk(const Region &G, int64_t j, int d, char *base, const BL
             uint32_t *sa = sacc + 4 * par;
             int32_t *kn = knext + par;
 
-            // (1) ones per class; one atomic per word when its live lanes share a class
+            // (1) ones per class
             int32_t bit[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 bit[r] = 0;
-                if (word[r]) {
+                if (word(r)) {
                     const uint64_t w = readlane64(rowv[r], i);
                     bit[r] = (int32_t)((w >> lane) & 1ull);
-                    const bool live = cls[r] != DEAD;
-                    // lane 0's class; when every live lane is in it, one atomic
-                    const int32_t c0 = __builtin_amdgcn_readfirstlane(cls[r]);
-                    const uint64_t other = __ballot(live && cls[r] != c0);
-                    if (!other) {
-                        if (c0 != DEAD) {
-                            const uint32_t ones = (uint32_t)__popcll(__ballot(live && bit[r] != 0));
-                            if (lane == 0 && ones) atomicAdd(&cnt1[c0], ones * incu[r]);
-                        }
-                    } else if (live && bit[r]) {
-                        atomicAdd(&cnt1[cls[r]], incu[r]);
-                    }
+                    if (cls[r] != DEAD && bit[r]) atomicAdd(&cnt1[cls[r]], incu(r));
                 }
             }
             __syncthreads();
@@ -681,26 +657,33 @@ done:
 }
 
 // Persistent grid over the batch's items (region, site, direction).
+// With stride > 1 the items walked are a sample for the autotuner: blocks of
+// 256 consecutive items, one block in every `stride`.
 template <int R>
 __global__ void __launch_bounds__(1024) ids_batch_kernel(const Region *__restrict__ regs,
                                                          int32_t nreg, int64_t total,
+                                                         int64_t stride,
                                                          unsigned long long *counter, int chunk,
                                                          int lmax, int pcap, int kcap) {
     extern __shared__ uint64_t lds_ids[];
-    __shared__ unsigned long long grab;
+    __shared__ unsigned long long grab[2];
     char *base = (char *)lds_ids;
     const BLay Ly = batch_layout(lmax, pcap, kcap);
     // the region of the last item (items of one region are consecutive)
-    Region G;
+    int g_idx = 0;
     int64_t g_lo = 0, g_hi = -1;
+    if (threadIdx.x == 0) grab[0] = atomicAdd(counter, (unsigned long long)chunk);
+    __syncthreads();
+    int gb = 0;
     for (;;) {
-        __syncthreads();   // everyone has read the previous grab
-        if (threadIdx.x == 0) grab = atomicAdd(counter, (unsigned long long)chunk);
-        __syncthreads();
-        const int64_t b0 = (int64_t)grab;
+        const int64_t b0 = (int64_t)grab[gb];
         if (b0 >= total) break;
+        // the next grab is in flight while this chunk is walked
+        unsigned long long nxt = 0ull;
+        if (threadIdx.x == 0) nxt = atomicAdd(counter, (unsigned long long)chunk);
         const int64_t b1 = b0 + chunk < total ? b0 + chunk : total;
-        for (int64_t it = b0; it < b1; ++it) {
+        for (int64_t iv = b0; iv < b1; ++iv) {
+            const int64_t it = stride > 1 ? (((iv >> 8) * stride) << 8) + (iv & 255) : iv;
             if (it < g_lo || it >= g_hi) {
                 int lo = 0, hi = nreg - 1;   // last region with item0 <= it
                 while (lo < hi) {
@@ -708,27 +691,32 @@ __global__ void __launch_bounds__(1024) ids_batch_kernel(const Region *__restric
                     if (regs[mid].item0 <= it) lo = mid;
                     else hi = mid - 1;
                 }
-                G = regs[lo];
-                g_lo = G.item0;
+                g_idx = lo;
+                g_lo = regs[lo].item0;
                 g_hi = lo + 1 < nreg ? regs[lo + 1].item0 : INT64_MAX;
             }
-            const int64_t loc = it - G.item0;
+            const Region *G = regs + g_idx;
+            const int64_t loc = it - g_lo;
             const int64_t j = loc >> 1;
             const int d = (int)(loc & 1);
-            if (j >= G.M) continue;
-            if (G.walk_flag && !G.walk_flag[j]) continue;
-            if (G.mode == MODE_CORE) ids_walk<MODE_CORE, R>(G, j, d, base, Ly, pcap, kcap);
+            if (j >= G->M) continue;
+            if (G->walk_flag && !G->walk_flag[j]) continue;
+            if (G->mode == MODE_CORE) ids_walk<MODE_CORE, R>(G, j, d, base, Ly, pcap, kcap);
             else ids_walk<MODE_POOLED, R>(G, j, d, base, Ly, pcap, kcap);
             __syncthreads();
         }
+        if (threadIdx.x == 0) grab[gb ^ 1] = nxt;
+        __syncthreads();   // the next chunk is visible; grab[gb] is no longer read
+        gb ^= 1;
     }
 }
 
 template <int R>
-hipError_t launch_r(const Region *regs, int32_t nreg, int64_t total, unsigned long long *counter,
-                    const WideCfg &c, hipStream_t s) {
+hipError_t launch_r(const Region *regs, int32_t nreg, int64_t total, int64_t stride,
+                    unsigned long long *counter, const WideCfg &c, hipStream_t s) {
     hipLaunchKernelGGL((ids_batch_kernel<R>), dim3((unsigned)c.blocks), dim3((unsigned)c.threads),
-                       c.lds, s, regs, nreg, total, counter, c.chunk, c.lmax, c.pair_cap, c.key_cap);
+                       c.lds, s, regs, nreg, total, stride, counter, c.chunk, c.lmax, c.pair_cap,
+                       c.key_cap);
     return hipGetLastError();
 }
 
@@ -751,8 +739,10 @@ int ids_slots(int threads, int wmax) {
     return r <= 16 ? r : 0;   // 32 slots would spill registers
 }
 
-int ids_threads_for(int wmax) {
-    const int t = 64 * ((wmax + 15) / 16);   // 16 slots per thread at most
+int ids_threads_for(int wmax, int slots) {
+    if (slots < 1 || slots > 16) return 0;
+    int t = 64 * ((wmax + slots - 1) / slots);
+    if (t > 1024) t = 64 * ((wmax + 15) / 16);   // as many waves as fit, 16 slots each
     return t <= 1024 ? (t > 0 ? t : 64) : 0;
 }
 
@@ -775,15 +765,16 @@ int ids_blocks_per_cu(const WideCfg &c) {
 }
 
 hipError_t launch_ids_batch(const Region *regs, int32_t nreg, int64_t total_items,
-                            unsigned long long *counter, const WideCfg &c, hipStream_t s) {
+                            int64_t stride, unsigned long long *counter, const WideCfg &c,
+                            hipStream_t s) {
     if (nreg <= 0 || total_items <= 0) return hipSuccess;
     if (c.blocks <= 0 || c.chunk <= 0) return hipErrorInvalidValue;
     switch (ids_slots(c.threads, c.wmax)) {
-        case 1: return launch_r<1>(regs, nreg, total_items, counter, c, s);
-        case 2: return launch_r<2>(regs, nreg, total_items, counter, c, s);
-        case 4: return launch_r<4>(regs, nreg, total_items, counter, c, s);
-        case 8: return launch_r<8>(regs, nreg, total_items, counter, c, s);
-        case 16: return launch_r<16>(regs, nreg, total_items, counter, c, s);
+        case 1: return launch_r<1>(regs, nreg, total_items, stride, counter, c, s);
+        case 2: return launch_r<2>(regs, nreg, total_items, stride, counter, c, s);
+        case 4: return launch_r<4>(regs, nreg, total_items, stride, counter, c, s);
+        case 8: return launch_r<8>(regs, nreg, total_items, stride, counter, c, s);
+        case 16: return launch_r<16>(regs, nreg, total_items, stride, counter, c, s);
         default: return hipErrorInvalidValue;
     }
 }

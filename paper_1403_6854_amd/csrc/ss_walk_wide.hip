@@ -674,7 +674,8 @@ __device__ void wide_walk_one(const Region &R, int64_t j, int d, int core, char 
 // loop once the counter has passed the last item.
 template <int T>
 __global__ void __launch_bounds__(T) wide_walk_kernel(const Region *__restrict__ regs, int32_t nreg,
-                                                      int64_t total, unsigned long long *counter,
+                                                      int64_t total, int64_t stride,
+                                                      unsigned long long *counter,
                                                       int chunk, int lmax, int wmax, int pcap,
                                                       int kcap) {
     extern __shared__ uint64_t lds_wide[];
@@ -688,7 +689,9 @@ __global__ void __launch_bounds__(T) wide_walk_kernel(const Region *__restrict__
         const int64_t b0 = (int64_t)grab;
         if (b0 >= total) break;
         const int64_t b1 = b0 + chunk < total ? b0 + chunk : total;
-        for (int64_t it = b0; it < b1; ++it) {
+        for (int64_t iv = b0; iv < b1; ++iv) {
+            // stride > 1: a sample, blocks of 256 items, one in every `stride`
+            const int64_t it = stride > 1 ? (((iv >> 8) * stride) << 8) + (iv & 255) : iv;
             int lo = 0, hi = nreg - 1;   // last region with item0 <= it
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
@@ -734,10 +737,10 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n) {
 }
 
 template <int T>
-hipError_t launch_t(const Region *regs, int32_t nreg, int64_t total, unsigned long long *counter,
-                    const WideCfg &c, hipStream_t s) {
+hipError_t launch_t(const Region *regs, int32_t nreg, int64_t total, int64_t stride,
+                    unsigned long long *counter, const WideCfg &c, hipStream_t s) {
     hipLaunchKernelGGL((wide_walk_kernel<T>), dim3((unsigned)c.blocks), dim3(T), c.lds, s, regs, nreg,
-                       total, counter, c.chunk, c.lmax, c.wmax, c.pair_cap, c.key_cap);
+                       total, stride, counter, c.chunk, c.lmax, c.wmax, c.pair_cap, c.key_cap);
     return hipGetLastError();
 }
 
@@ -785,13 +788,14 @@ hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
 }
 
 hipError_t launch_wide_walk(const Region *regs, int32_t nreg, int64_t total_items,
-                            unsigned long long *counter, const WideCfg &c, hipStream_t s) {
+                            int64_t stride, unsigned long long *counter, const WideCfg &c,
+                            hipStream_t s) {
     if (nreg <= 0 || total_items <= 0) return hipSuccess;
     if (c.blocks <= 0 || c.chunk <= 0) return hipErrorInvalidValue;
     switch (c.threads) {
-        case 128: return launch_t<128>(regs, nreg, total_items, counter, c, s);
-        case 256: return launch_t<256>(regs, nreg, total_items, counter, c, s);
-        case 512: return launch_t<512>(regs, nreg, total_items, counter, c, s);
+        case 128: return launch_t<128>(regs, nreg, total_items, stride, counter, c, s);
+        case 256: return launch_t<256>(regs, nreg, total_items, stride, counter, c, s);
+        case 512: return launch_t<512>(regs, nreg, total_items, stride, counter, c, s);
         default: return hipErrorInvalidValue;
     }
 }

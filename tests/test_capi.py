@@ -119,3 +119,69 @@ def test_product_does_not_reach_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liboracle" not in text and "selscan_oracle" not in text, f
+
+
+def _request(op, na=204, nb=210, m=100, null_out=False):
+    import paper_1403_6854_amd as ss
+    fake = 0x1000
+    out = 0 if null_out else fake
+    a = _desc(na, m, (na + 63) // 64)
+    b = _desc(nb, m, (nb + 63) // 64) if op == ss.OP_XPEHH else ss._HapMat(0, 0, 0, 0, 0, 0)
+    return ss._Request(op, a, b, out, out, out, out, out if op == ss.OP_IHS else 0, out, 0)
+
+
+def test_batch_argument_checks_are_host_only(lib):
+    import paper_1403_6854_amd as ss
+    p = ss._cparams(None)
+    arr = (ss._Request * 3)(_request(ss.OP_IHS), _request(ss.OP_XPEHH), _request(ss.OP_IHS, na=5000))
+    single = lib.ss_workspace_bytes(ss.OP_IHS, ctypes.byref(_desc()), None, ctypes.byref(p), 0)
+    nb = lib.ss_batch_workspace_bytes(arr, 3, ctypes.byref(p))
+    assert nb > single
+    # unknown op, empty batch, null outputs, mismatched sites
+    bad = (ss._Request * 1)(_request(7))
+    assert lib.ss_batch_workspace_bytes(bad, 1, ctypes.byref(p)) == 0
+    assert lib.ss_scan_batch(bad, 1, ctypes.byref(p), ctypes.c_void_p(0x1000), 1 << 30, None) == ss.SS_EARG
+    assert b"unknown op" in lib.ss_last_error()
+    assert lib.ss_scan_batch(arr, 0, ctypes.byref(p), ctypes.c_void_p(0x1000), 1 << 30, None) == ss.SS_EARG
+    nul = (ss._Request * 1)(_request(ss.OP_IHS, null_out=True))
+    assert lib.ss_scan_batch(nul, 1, ctypes.byref(p), ctypes.c_void_p(0x1000), 1 << 30, None) == ss.SS_EARG
+    shp = _request(ss.OP_XPEHH)
+    shp.b.n_sites = 99
+    one = (ss._Request * 1)(shp)
+    assert lib.ss_scan_batch(one, 1, ctypes.byref(p), ctypes.c_void_p(0x1000), 1 << 30, None) == ss.SS_ESHAPE
+    assert b"request 0" in lib.ss_last_error()
+    # workspace too small
+    good = (ss._Request * 1)(_request(ss.OP_IHS))
+    assert lib.ss_scan_batch(good, 1, ctypes.byref(p), ctypes.c_void_p(0x1000), 16, None) == ss.SS_EWS
+
+
+def test_batch_config_round_trip_and_range_checks(lib):
+    import paper_1403_6854_amd as ss
+    base = ss.get_batch_config()
+    try:
+        for cfg in (ss.BatchConfig(threads=320), ss.BatchConfig(kernel=1, threads=128),
+                    ss.BatchConfig(pair_cap=0, small_pair_cap=4096, chunk=16, order=1,
+                                   blocks_per_cu=2, small_kernel=0, slots=8)):
+            ss.set_batch_config(cfg)
+            assert ss.get_batch_config() == cfg
+        for bad in (dict(threads=96), dict(threads=2048), dict(kernel=1, threads=1024),
+                    dict(kernel=2), dict(pair_cap=-1), dict(pair_cap=20000), dict(chunk=0),
+                    dict(order=2), dict(small_kernel=3), dict(small_pair_cap=-5),
+                    dict(blocks_per_cu=-1), dict(slots=5), dict(slots=32)):
+            with pytest.raises(ss.SelscanError) as e:
+                ss.set_batch_config(ss.BatchConfig(**bad))
+            assert e.value.code == ss.SS_EARG
+    finally:
+        ss.set_batch_config(base)
+
+
+def test_walk_kernel_choices(lib):
+    import paper_1403_6854_amd as ss
+    for k in (0, 1, 2, 3):
+        ss.set_walk_kernel(k)
+    with pytest.raises(ss.SelscanError):
+        ss.set_walk_kernel(4)
+    ss.set_walk_kernel(0)
+    ss.set_graph(True)
+    ss.set_graph(False)
+    ss.graph_clear()

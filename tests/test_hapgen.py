@@ -84,3 +84,24 @@ def test_large_batch_input_scaled():
         assert 0.5 * 5000 - 2 <= int(a[s].sum()) <= 0.95 * 5000 + 2
     b, pos2, _, _ = hapgen.large_batch_input(10000)
     assert np.array_equal(pos, pos2) and bool((a == b).all())
+
+
+def test_device_request_generator():
+    import torch
+    reqs = hapgen.request_stream(64)
+    assert len(reqs) == 64 and all(a.arrival_s < b.arrival_s for a, b in zip(reqs, reqs[1:]))
+    assert {r.kind for r in reqs} == {"ihs", "xpehh"}
+    assert all(100 <= r.n_a <= 5000 and 1000 <= r.n_sites <= 200000 for r in reqs)
+    spec = hapgen.RequestSpec(0, "xpehh", 0.0, 300, 250, 3000, 5)
+    a, b, pos, gpos = hapgen.device_region(spec, "cpu")
+    a2, b2, pos2, _ = hapgen.device_region(spec, "cpu")
+    assert tuple(a.shape) == (3000, 300) and tuple(b.shape) == (3000, 250)
+    assert bool((a == a2).all()) and bool((b == b2).all()) and bool((pos == pos2).all())
+    assert bool((pos[1:] > pos[:-1]).all())
+    # switches happen at the model's rate and always move to another founder
+    gen = torch.Generator()
+    gen.manual_seed(3)
+    fo = torch.arange(40, dtype=torch.uint8)[:, None].expand(40, 20000).contiguous()
+    out = hapgen._device_copy(gen, fo, 300, 0.003, 0.0)
+    rate = (out[1:] != out[:-1]).float().mean().item()
+    assert abs(rate - 0.003) < 0.0004
