@@ -89,7 +89,7 @@ def time_scan(fn, warmup: int, steps: int, ss, torch):
     return (t1 - t0), walk_ms / max(1, launches), launches
 
 
-def bench_batched(ss, torch, dev, reps: int = 3):
+def bench_batched(ss, torch, dev, autotune: bool = True, reps: int = 3):
     """5,000 x 10^6 iHS: one persistent launch in a graph vs the plain kernel."""
     import hapgen
     log("batched: generating 5000 x 1e6 on the device")
@@ -101,13 +101,18 @@ def bench_batched(ss, torch, dev, reps: int = 3):
     torch.cuda.empty_cache()
     stream = torch.cuda.Stream()
     req = ss.ScanRequest(h)
-    ss.alloc_outputs(req)
-    log("batched: autotuning the persistent walk")
-    t0 = time.perf_counter()
-    cfg, tune_ms, ws = ss.autotune_batch([req], stream=stream, sample_items=400_000)
-    tune_s = time.perf_counter() - t0
+    ss.alloc_outputs(req, steps=True)
+    ss.set_batch_config(ss.BatchConfig())
+    tune_s = tune_ms = 0.0
+    ws = None
+    if autotune:
+        log("batched: autotuning the persistent walk")
+        t0 = time.perf_counter()
+        cfg, tune_ms, ws = ss.autotune_batch([req], stream=stream, sample_items=400_000)
+        tune_s = time.perf_counter() - t0
+    cfg = ss.get_batch_config()
     # walk kernel alone (eager, timed with events on the stream)
-    ss.scan_batch([req], stream=stream, ws=ws, validate=False)
+    ws = ss.scan_batch([req], stream=stream, ws=ws, validate=False)
     stream.synchronize()
     ss.timing_read(reset=True)
     ss.timing_enable(True)
@@ -128,6 +133,10 @@ def bench_batched(ss, torch, dev, reps: int = 3):
     ss.graph_clear()
     status = req.out["status"]
     loci = int((status != 1).sum().item())
+    # algorithmic work: markers walked by each core times its haplotypes
+    n1 = torch.round(req.out["freq"] * n).to(torch.int64)
+    n_c = torch.stack([n - n1, n1], dim=1)[:, None, :]
+    cells_w = int((req.out["steps"].to(torch.int64) * n_c).sum().item())
     # the plain per-locus kernel (one workgroup per site and direction)
     log("batched: plain per-locus kernel on the same input")
     ss.set_walk_kernel(1)
@@ -152,7 +161,10 @@ def bench_batched(ss, torch, dev, reps: int = 3):
            "autotune_sample_ms": round(tune_ms, 3),
            "plain_kernel": {"value": round(loci / plain_s, 1), "scan_ms": round(plain_s * 1e3, 3),
                             "walk_kernel_ms": round(plain_walk_ms / max(1, launches), 3)},
-           "speedup_vs_plain": round(plain_s / graph_s, 3), "identical_results": same}
+           "speedup_vs_plain": round(plain_s / graph_s, 3), "identical_results": same,
+           "work_cells": cells_w,
+           "achieved_TOPs": round(cells_w / (walk_ms * 1e-3) / 1e12, 4),
+           "roofline_frac": round(cells_w / (walk_ms * 1e-3) / 1e12 / PEAK_INT32_TOPS, 5)}
     del req, plain, h, ws
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -199,7 +211,10 @@ def bench_served(ss, torch, dev, args):
         q = ss.ScanRequest(a, b)
         ss.alloc_outputs(q)
         tune.append(q)
-    cfg, _, _ = ss.autotune_batch(tune, sample_items=0)
+    if args.no_autotune:
+        cfg = ss.get_batch_config()
+    else:
+        cfg, _, _ = ss.autotune_batch(tune, sample_items=0)
     del tune
     warm = [dataclasses.replace(s, arrival_s=0.0) for s in specs[:12]]
     serve.Server(serve.TorchBackend(args.serve_streams), budget).run(reqs_of(warm))
@@ -254,6 +269,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
     ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default persistent-walk configuration (profiling runs)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -355,7 +372,7 @@ def main():
                "sample": "%d full iHS scans of the 204 x 22,147 workload (%d core loci each), "
                          "%.2f s per scan" % (args.cpu_reps, core_loci, t_cpu)}
 
-    batched = None if args.no_batched else bench_batched(ss, torch, dev)
+    batched = None if args.no_batched else bench_batched(ss, torch, dev, not args.no_autotune)
     served = None if args.no_served else bench_served(ss, torch, dev, args)
 
     line = {
