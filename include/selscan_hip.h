@@ -247,6 +247,10 @@ typedef struct ss_batch_config {
     int32_t slots;          /* kernel 0: 64-haplotype words per wave (4, 8 or 16
                                [default]): fewer words per wave spread a walk over more
                                waves; rows wider than 16 waves of them take 16 per wave */
+    int32_t class_cap;      /* kernel 0: classes the LDS table holds (0 = as many as a
+                               walk can have, n/2 + 2; else 64..16386, default 1024):
+                               walks that outgrow it are redone by a second launch with
+                               full tables                                             */
 } ss_batch_config;
 
 int ss_get_batch_config(ss_batch_config *c);

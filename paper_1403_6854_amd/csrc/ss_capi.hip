@@ -110,7 +110,8 @@ struct ScanWs {
     double *seg;          // [M] segment lengths with the gap rules applied
     int32_t *redo;        // [1 + 2M] overflow count, then the walks to redo
     ss::Region *region;   // [1] descriptor for the persistent walk
-    unsigned long long *counter;   // [1] its work counter
+    unsigned long long *counter;   // [3] its work counter, overflow count, redo work counter
+    int64_t *wredo;       // [2M] walks the capped class table could not hold
     size_t bytes;
 };
 
@@ -133,7 +134,8 @@ ScanWs carve_scan(void *base, int64_t M, int nbins, int64_t n_hapmajor) {
     w.seg = (double *)take(8 * (size_t)M);
     w.redo = (int32_t *)take(4 * (1 + 2 * (size_t)M));
     w.region = (ss::Region *)take(sizeof(ss::Region));
-    w.counter = (unsigned long long *)take(sizeof(unsigned long long));
+    w.counter = (unsigned long long *)take(4 * sizeof(unsigned long long));
+    w.wredo = (int64_t *)take(8 * 2 * (size_t)M);
     w.bytes = off;
     return w;
 }
@@ -176,7 +178,7 @@ hipEvent_t take_event() {
 
 int g_walk_kind = ss::WALK_AUTO;
 int g_mask_lpc = 0;   // lanes per class of the bitmask walk; 0 = default
-ss_batch_config g_bcfg = {64, 4096, 1, 0, 0, 1, 0, 1024, 16};
+ss_batch_config g_bcfg = {64, 4096, 1, 0, 0, 1, 0, 1024, 16, 1024};
 bool g_graph_on = false;
 bool g_capturing = false;   // timing events are not recorded into graphs
 
@@ -190,6 +192,8 @@ int check_batch_config(const ss_batch_config &c) {
     if (c.small_pair_cap < 0 || c.small_pair_cap > 16384)
         return fail(SS_EARG, "small_pair_cap must be in [0, 16384]");
     if (c.slots != 4 && c.slots != 8 && c.slots != 16) return fail(SS_EARG, "slots must be 4, 8 or 16");
+    if (c.class_cap != 0 && (c.class_cap < 64 || c.class_cap > 16386))
+        return fail(SS_EARG, "class_cap must be 0 or in [64, 16386]");
     if (c.chunk < 1 || c.chunk > 4096) return fail(SS_EARG, "chunk must be in [1, 4096]");
     if (c.blocks_per_cu < 0 || c.blocks_per_cu > 64) return fail(SS_EARG, "blocks_per_cu must be in [0, 64]");
     if (c.order != 0 && c.order != 1) return fail(SS_EARG, "order must be 0 or 1");
@@ -212,10 +216,20 @@ bool make_wide_cfg(const ss_batch_config &bc, int lmax, int wmax, ss::WideCfg &c
         if (need == 0) return false;
         c.threads = std::max(bc.threads, need);
         if (c.threads <= 128) c.pair_cap = bc.small_pair_cap;
-        // the member list of the pairwise tail holds as many haplotypes as
-        // there are pairs; walks with more members wait in the per-marker phase
-        c.key_cap = std::min(c.pair_cap, 32767);
-        c.lds = ss::ids_lds_bytes(c.threads, lmax, wmax, c.pair_cap, c.key_cap);
+        // the member list of the pairwise tail: P pairs in classes of a few
+        // members or more come from at most ~P / 4 haplotypes; walks with more
+        // members wait in the per-marker phase
+        c.key_cap = c.pair_cap > 0 ? std::min(std::max(256, c.pair_cap / 4), 32767) : 0;
+        c.class_cap = bc.class_cap;
+        // counter copies pay off for the large classes of wide regions; small
+        // workgroups keep one copy and their occupancy
+        c.copies = c.threads >= 256 ? 8 : 1;
+        c.lds = ss::ids_lds_bytes(c.threads, lmax, wmax, c.class_cap, c.pair_cap, c.key_cap,
+                                  c.copies);
+        if (c.lds == 0 || c.lds > (size_t)max_lds_per_block()) {
+            c.copies = 1;
+            c.lds = ss::ids_lds_bytes(c.threads, lmax, wmax, c.class_cap, c.pair_cap, c.key_cap, 1);
+        }
     } else {
         // a pair list of P pairs holds at most ~P / 4 haplotypes in classes of
         // a few members; walks with more wait in the per-marker phase
@@ -434,6 +448,57 @@ int finish_scan(const Scan &sc, hipStream_t s) {
 
 namespace {
 
+// One launch group of the class-id batch walk: the persistent launch with the
+// configured class table and, when that table is capped, a second launch with
+// full tables over the walks the first one listed (it ends at once when the
+// list is empty).  ctr[0..2]: work counter, list count, second work counter,
+// zeroed beforehand.
+int launch_ids_group(const ss::Region *regs, int nreg, int64_t total, int64_t stride,
+                     unsigned long long *ctr, int64_t *redo, const ss::WideCfg &c, hipStream_t s) {
+    ss::IdsArgs a{};
+    a.regs = regs;
+    a.nreg = nreg;
+    a.total = total;
+    a.stride = stride;
+    a.counter = ctr;
+    a.chunk = c.chunk;
+    a.lmax = c.lmax;
+    a.kcls = c.class_cap;
+    a.copies = c.copies;
+    a.pcap = c.pair_cap;
+    a.kcap = c.key_cap;
+    const bool capped = ss::ids_table_capped(c.lmax, c.class_cap);
+    a.redo = capped ? redo : nullptr;
+    a.redo_count = capped ? (int32_t *)(ctr + 1) : nullptr;
+    SS_HIP(ss::launch_ids_batch(a, c, s));
+    if (!capped) return SS_OK;
+    ss::WideCfg full = c;
+    full.class_cap = 0;
+    full.lds = ss::ids_lds_bytes(full.threads, full.lmax, full.wmax, 0, full.pair_cap, full.key_cap,
+                                 full.copies);
+    if (full.lds == 0 || full.lds > (size_t)max_lds_per_block()) {
+        full.copies = 1;
+        full.lds = ss::ids_lds_bytes(full.threads, full.lmax, full.wmax, 0, full.pair_cap,
+                                     full.key_cap, 1);
+    }
+    if (full.lds == 0 || full.lds > (size_t)max_lds_per_block())
+        return fail(SS_EDEV, "full class table does not fit this device");
+    const int occ = ss::ids_blocks_per_cu(full);
+    if (occ < 1) return fail(SS_EDEV, "full class table does not fit this device");
+    full.blocks = std::max(1, device_cus() * occ);
+    ss::IdsArgs b = a;
+    b.kcls = 0;
+    b.copies = full.copies;
+    b.counter = ctr + 2;
+    b.list = redo;
+    b.list_count = (const int32_t *)(ctr + 1);
+    b.redo = nullptr;
+    b.redo_count = nullptr;
+    b.stride = 1;
+    SS_HIP(ss::launch_ids_batch(b, full, s));
+    return SS_OK;
+}
+
 // Walk of one scan, timed when timing is enabled.
 int walk_scan(Scan &sc, hipStream_t s) {
     if (sc.route == RT_WIDE) {
@@ -443,11 +508,13 @@ int walk_scan(Scan &sc, hipStream_t s) {
         if (!make_wide_cfg(g_bcfg, list_len(r.nA, r.nB, sc.mode), row_words(r.nA, r.nB, sc.mode), c))
             return fail(SS_EDEV, "persistent walk does not fit this device");
         SS_HIP(ss::launch_fill_regions(&r, 1, sc.w.region, s));
-        SS_HIP(ss::launch_zero_u64(sc.w.counter, 1, s));
+        SS_HIP(ss::launch_zero_u64(sc.w.counter, 4, s));
         TimedRegion t(s);
         SS_TRY(t.begin());
-        SS_HIP(c.kernel == 0 ? ss::launch_ids_batch(sc.w.region, 1, items, 1, sc.w.counter, c, s)
-                             : ss::launch_wide_walk(sc.w.region, 1, items, 1, sc.w.counter, c, s));
+        if (c.kernel == 0)
+            SS_TRY(launch_ids_group(sc.w.region, 1, items, 1, sc.w.counter, sc.w.wredo, c, s));
+        else
+            SS_HIP(ss::launch_wide_walk(sc.w.region, 1, items, 1, sc.w.counter, c, s));
         return t.end();
     }
     TimedRegion t(s);
@@ -474,14 +541,15 @@ struct Batch {
     std::vector<ss::Region> regions;  // their descriptors, group by group (item0 per group)
     std::vector<Group> groups;
     ss::Region *d_regions = nullptr;
-    unsigned long long *d_counter = nullptr;   // one per group
+    unsigned long long *d_counter = nullptr;   // three per group
+    int64_t *d_redo = nullptr;                 // redo lists, group by group
     int64_t total_items = 0;
     int lmax = 0, wmax = 0;
 };
 
 struct BatchLayout {
     std::vector<size_t> offs;
-    size_t regions = 0, counter = 0, bytes = 0;
+    size_t regions = 0, counter = 0, redo = 0, bytes = 0;
 };
 
 int op_mode(int32_t op) { return op == SS_OP_IHS ? ss::MODE_CORE : ss::MODE_POOLED; }
@@ -510,7 +578,11 @@ BatchLayout batch_layout(const ss_scan_request *reqs, int32_t n, const ss_params
     L.regions = off;
     off += align256(sizeof(ss::Region) * (size_t)n);
     L.counter = off;
-    off += 256;
+    off += align256(sizeof(unsigned long long) * 3 * kMaxGroups);
+    L.redo = off;   // walks listed for the full-table pass, 2 items per site at most
+    size_t sites = 0;
+    for (int32_t i = 0; i < n; ++i) sites += (size_t)reqs[i].a.n_sites;
+    off += align256(8 * 2 * sites);
     L.bytes = off;
     return L;
 }
@@ -597,6 +669,7 @@ int build_batch(const ss_scan_request *reqs, int32_t n, const ss_params *p, void
     }
     B.d_regions = (ss::Region *)((char *)d_ws + L.regions);
     B.d_counter = (unsigned long long *)((char *)d_ws + L.counter);
+    B.d_redo = (int64_t *)((char *)d_ws + L.redo);
     number_items(B, g_bcfg);
     if ((int)B.groups.size() > kMaxGroups) return fail(SS_EDEV, "too many launch groups");
     return SS_OK;
@@ -607,7 +680,8 @@ int build_batch(const ss_scan_request *reqs, int32_t n, const ss_params *p, void
 int launch_batch_wide(Batch &B, const ss_batch_config &bc, int64_t sample_stride, hipStream_t s) {
     if (B.wide.empty()) return SS_OK;
     SS_HIP(ss::launch_fill_regions(B.regions.data(), (int)B.regions.size(), B.d_regions, s));
-    SS_HIP(ss::launch_zero_u64(B.d_counter, kMaxGroups, s));
+    SS_HIP(ss::launch_zero_u64(B.d_counter, 3 * kMaxGroups, s));
+    int64_t redo_off = 0;
     for (size_t gi = 0; gi < B.groups.size(); ++gi) {
         const Group &g = B.groups[gi];
         ss::WideCfg c;
@@ -622,9 +696,12 @@ int launch_batch_wide(Batch &B, const ss_batch_config &bc, int64_t sample_stride
             total = 256 * ((blocks + stride - 1) / stride);
         }
         ss::Region *regs = B.d_regions + g.first;
-        unsigned long long *ctr = B.d_counter + gi;
-        SS_HIP(c.kernel == 0 ? ss::launch_ids_batch(regs, g.count, total, stride, ctr, c, s)
-                             : ss::launch_wide_walk(regs, g.count, total, stride, ctr, c, s));
+        unsigned long long *ctr = B.d_counter + 3 * gi;
+        if (c.kernel == 0)
+            SS_TRY(launch_ids_group(regs, g.count, total, stride, ctr, B.d_redo + redo_off, c, s));
+        else
+            SS_HIP(ss::launch_wide_walk(regs, g.count, total, stride, ctr, c, s));
+        redo_off += g.total_items;
     }
     return SS_OK;
 }
@@ -943,6 +1020,13 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
                 if (ms < cur_ms) { cur = c; cur_ms = ms; }
             }
             if (cur.kernel == 0) {
+                for (int cc : {0, 512, 1024, 2048}) {
+                    ss_batch_config c = cur;
+                    c.class_cap = cc;
+                    double ms;
+                    SS_TRY(time_cfg(c, ms));
+                    if (ms < cur_ms) { cur = c; cur_ms = ms; }
+                }
                 for (int sl : {4, 8, 16}) {
                     ss_batch_config c = cur;
                     c.slots = sl;

@@ -124,6 +124,8 @@ struct WideCfg {
     int chunk;       // items taken per grab of the work counter
     int blocks;      // workgroups of the persistent grid
     int lmax;        // largest haplotype list of the batch (iHS: n, XPEHH: nA + nB)
+    int class_cap;   // kernel 0: class-table capacity (0 = full)
+    int copies;      // kernel 0: copies of each class counter (1 or 8)
     int wmax;        // largest row width in words (iHS: W, XPEHH: WA + WB)
     size_t lds;      // dynamic LDS bytes
 };
@@ -141,11 +143,31 @@ int ids_slots(int threads, int wmax);
 // with at most `slots` words per wave (16 per wave when that would need more
 // than 1024 threads); 0 if the row does not fit.
 int ids_threads_for(int wmax, int slots);
-size_t ids_lds_bytes(int threads, int lmax, int wmax, int pair_cap, int key_cap);
+size_t ids_lds_bytes(int threads, int lmax, int wmax, int class_cap, int pair_cap, int key_cap,
+                     int copies);
+// True when a class capacity leaves some walks of lmax haplotypes to a
+// second launch with full tables.
+bool ids_table_capped(int lmax, int class_cap);
 int ids_blocks_per_cu(const WideCfg &c);
-hipError_t launch_ids_batch(const Region *regs, int32_t nreg, int64_t total_items,
-                            int64_t stride, unsigned long long *counter, const WideCfg &c,
-                            hipStream_t s);
+
+// Arguments of one launch of the class-id batch walk.
+struct IdsArgs {
+    const Region *regs;
+    int32_t nreg;
+    int64_t total;               // items (ignored with a list)
+    int64_t stride;              // > 1: sample in blocks of 256 items
+    unsigned long long *counter; // work counter, zeroed before the launch
+    int chunk;
+    int lmax;                    // largest haplotype list of the regions
+    int kcls;                    // class-table capacity, 0 = full
+    int copies;                  // copies of each class counter (1 or 8)
+    int pcap, kcap;              // pair and member capacity of the pairwise tail
+    const int64_t *list;         // null, or the items to walk ...
+    const int32_t *list_count;   // ... and their number (on the device)
+    int64_t *redo;               // walks that outgrow a capped table go here ...
+    int32_t *redo_count;         // ... counted here (zeroed before the launch)
+};
+hipError_t launch_ids_batch(const IdsArgs &a, const WideCfg &c, hipStream_t s);
 hipError_t launch_fill_regions(const Region *host, int n, Region *dev, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 // Persistent walks over total_items items; with stride > 1 item v stands for

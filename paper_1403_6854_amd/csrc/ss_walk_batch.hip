@@ -31,6 +31,10 @@ namespace {
 
 constexpr int32_t DEAD = -1;
 constexpr int kBig = 1 << 30;
+// Copies of every class counter (8, or 1 where 8 would not fit in LDS):
+// lane l adds into copy l % copies, so that the members of one large class
+// spread their LDS atomics over several addresses (banks) instead of
+// serializing on one.
 
 __device__ __forceinline__ uint32_t choose2(uint32_t x) { return (x * (x - 1u)) >> 1; }
 
@@ -99,25 +103,31 @@ __device__ __forceinline__ uint64_t block_excl_sum(uint64_t v, uint64_t *wtot, u
 // LDS layout (byte offsets).  The class table lives until the pair list is
 // built; keys, the second pair buffer and the histograms then reuse it.
 struct BLay {
-    uint32_t cnt1, szv0, szv1, map, sacc, knext, init, wtot, mem, pairs0;
+    uint32_t cnt1, szv0, szv1, map, sacc, knext, init, ovf, wtot, mem, pairs0;
     uint32_t keys, pairs1, hist, pcnt, total;
-    int kmax;
+    int kmax, copies;
 };
 
 __host__ __device__ inline uint32_t al16(uint32_t x) { return (x + 15u) & ~15u; }
 
-__host__ __device__ inline BLay batch_layout(int lmax, int pcap, int kcap) {
+// kcls > 0 caps the class table (walks that outgrow it are listed for a
+// launch with full tables); kcls = 0: room for every class a walk can have.
+__host__ __device__ inline BLay batch_layout(int lmax, int kcls, int pcap, int kcap,
+                                             int copies) {
     BLay l;
     l.kmax = lmax / 2 + 2;
+    if (kcls > 0 && kcls < l.kmax) l.kmax = kcls;
+    l.copies = copies;
     const uint32_t K = (uint32_t)l.kmax;
     uint32_t o = 0;
-    l.cnt1 = o;  o += 4u * K;
+    l.cnt1 = o;  o += 4u * K * (uint32_t)copies;
     l.szv0 = o;  o += 4u * K;
     l.szv1 = o;  o += 4u * K;
     l.map = o;   o += 8u * K;
     l.sacc = o;  o += 32u;
     l.knext = o; o += 8u;
     l.init = o;  o += 8u;
+    l.ovf = o;   o += 8u;
     o = al16(o);
     const uint32_t table_end = o;
     // reuses the class table once the pair list exists
@@ -136,7 +146,8 @@ __host__ __device__ inline BLay batch_layout(int lmax, int pcap, int kcap) {
 
 template <int MODE, int R>
 __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *base,
-                         const BLay &Ly, int pcap, int kcap) {
+                         const BLay &Ly, int pcap, int kcap, int64_t item, int64_t *redo,
+                         int32_t *redo_count) {
     // fields are read through the pointer where they are used (scalar loads),
     // so that a copy of the descriptor does not hold registers for the walk
     const Region &G = *Gp;
@@ -149,6 +160,7 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
     const int nA = G.nA, nB = MODE == MODE_POOLED ? G.nB : 0;
     const int WA = (nA + 63) >> 6, WB = MODE == MODE_POOLED ? (nB + 63) >> 6 : 0;
     const int kmax = Ly.kmax;
+    const int ncp = Ly.copies;   // 1 or 8
 
     uint32_t *cnt1 = (uint32_t *)(base + Ly.cnt1);
     uint32_t *szv0 = (uint32_t *)(base + Ly.szv0);
@@ -157,13 +169,15 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
     uint32_t *sacc = (uint32_t *)(base + Ly.sacc);
     int32_t *knext = (int32_t *)(base + Ly.knext);
     uint32_t *init = (uint32_t *)(base + Ly.init);
+    int32_t *ovf = (int32_t *)(base + Ly.ovf);   // the class table overflowed
 
-    for (int i = tid; i < kmax; i += T) cnt1[i] = 0u;
+    for (int i = tid; i < kmax * ncp; i += T) cnt1[i] = 0u;
     if (tid < 8) sacc[tid] = 0u;
     if (tid < 2) {
         knext[tid] = 0;
         init[tid] = 0u;
     }
+    if (tid == 0) *ovf = 0;
 
     // slot r: 64-haplotype word wq = wave + r * wpg of the pooled word space
     // (A's words, then B's); its row word at site k is computed where needed
@@ -295,7 +309,8 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
                 if (word(r)) {
                     const uint64_t w = readlane64(rowv[r], i);
                     bit[r] = (int32_t)((w >> lane) & 1ull);
-                    if (cls[r] != DEAD && bit[r]) atomicAdd(&cnt1[cls[r]], incu(r));
+                    if (cls[r] != DEAD && bit[r])
+                        atomicAdd(&cnt1[cls[r] * ncp + (lane & (ncp - 1))], incu(r));
                 }
             }
             __syncthreads();
@@ -306,8 +321,10 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
                 const bool in = c < K;
                 uint32_t one = 0u, sz = 0u;
                 if (in) {
-                    one = cnt1[c];
-                    cnt1[c] = 0u;
+                    for (int q = 0; q < ncp; ++q) {
+                        one += cnt1[c * ncp + q];
+                        cnt1[c * ncp + q] = 0u;
+                    }
                     sz = szc[c];
                 }
                 bool keepz = false, keepo = false;
@@ -349,12 +366,14 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
                 basei = __shfl(basei, 0, 64);
                 const int idz = basei + (int)lanes_below(bz);
                 const int ido = basei + nz + (int)lanes_below(bo);
+                const bool fits = basei + nz + no <= kmax;   // wave-uniform
+                if (!fits && lane == 0) *ovf = 1;
                 if (in) {
                     map[2 * c] = keepz ? idz : DEAD;
                     map[2 * c + 1] = keepo ? ido : DEAD;
                 }
-                if (keepz) szn[idz] = wz;
-                if (keepo) szn[ido] = wo;
+                if (fits && keepz) szn[idz] = wz;
+                if (fits && keepo) szn[ido] = wo;
                 s0 = wave_sum(s0);
                 s1 = wave_sum(s1);
                 if (MODE == MODE_POOLED) s2 = wave_sum(s2);
@@ -367,6 +386,7 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
                 }
             }
             __syncthreads();
+            if (*ovf) goto overflowed;   // the walk is redone with full tables
 
             // (3) new class ids
 #pragma unroll
@@ -472,7 +492,7 @@ pairs : {
             const uint64_t n = csize(c, tg);
             const uint32_t mo = (uint32_t)ex, po = (uint32_t)(ex >> 32);
             sbase[c] = mo;
-            cnt1[c] = mo;              // scatter cursor
+            cnt1[c * ncp] = mo;        // scatter cursor
             map[c] = (int32_t)po;      // pair offset
             if (n >= 2) ex += n | ((uint64_t)(n * (n - 1) / 2) << 32);
         }
@@ -490,7 +510,7 @@ pairs : {
             if (csize(cls[r], tg) >= 2u) {
                 const int wq = wave + r * wpg;
                 const int h = wq < WA ? wq * 64 + lane : (0x8000 | ((wq - WA) * 64 + lane));
-                const int p = (int)atomicAdd(&cnt1[cls[r]], 1u);
+                const int p = (int)atomicAdd(&cnt1[cls[r] * ncp], 1u);
                 mem[p] = (uint16_t)h;
                 mypos[r] = p;
             }
@@ -654,25 +674,27 @@ done:
         G.steps[o * 2 + 0] = steps0;
         G.steps[o * 2 + 1] = MODE == MODE_CORE ? steps1 : 0;
     }
+    return;
+overflowed:
+    if (tid == 0) redo[atomicAdd(redo_count, 1)] = item;
 }
 
 // Persistent grid over the batch's items (region, site, direction).
 // With stride > 1 the items walked are a sample for the autotuner: blocks of
-// 256 consecutive items, one block in every `stride`.
+// 256 consecutive items, one block in every `stride`.  With a list, the items
+// are those listed (count on the device): the walks a launch with a capped
+// class table could not finish.
 template <int R>
-__global__ void __launch_bounds__(1024) ids_batch_kernel(const Region *__restrict__ regs,
-                                                         int32_t nreg, int64_t total,
-                                                         int64_t stride,
-                                                         unsigned long long *counter, int chunk,
-                                                         int lmax, int pcap, int kcap) {
+__global__ void __launch_bounds__(1024) ids_batch_kernel(IdsArgs a) {
     extern __shared__ uint64_t lds_ids[];
     __shared__ unsigned long long grab[2];
     char *base = (char *)lds_ids;
-    const BLay Ly = batch_layout(lmax, pcap, kcap);
+    const BLay Ly = batch_layout(a.lmax, a.kcls, a.pcap, a.kcap, a.copies);
+    const int64_t total = a.list ? (int64_t)*a.list_count : a.total;
     // the region of the last item (items of one region are consecutive)
     int g_idx = 0;
     int64_t g_lo = 0, g_hi = -1;
-    if (threadIdx.x == 0) grab[0] = atomicAdd(counter, (unsigned long long)chunk);
+    if (threadIdx.x == 0) grab[0] = atomicAdd(a.counter, (unsigned long long)a.chunk);
     __syncthreads();
     int gb = 0;
     for (;;) {
@@ -680,29 +702,34 @@ __global__ void __launch_bounds__(1024) ids_batch_kernel(const Region *__restric
         if (b0 >= total) break;
         // the next grab is in flight while this chunk is walked
         unsigned long long nxt = 0ull;
-        if (threadIdx.x == 0) nxt = atomicAdd(counter, (unsigned long long)chunk);
-        const int64_t b1 = b0 + chunk < total ? b0 + chunk : total;
+        if (threadIdx.x == 0) nxt = atomicAdd(a.counter, (unsigned long long)a.chunk);
+        const int64_t b1 = b0 + a.chunk < total ? b0 + a.chunk : total;
         for (int64_t iv = b0; iv < b1; ++iv) {
-            const int64_t it = stride > 1 ? (((iv >> 8) * stride) << 8) + (iv & 255) : iv;
+            const int64_t it = a.list ? a.list[iv]
+                                      : (a.stride > 1 ? (((iv >> 8) * a.stride) << 8) + (iv & 255)
+                                                      : iv);
             if (it < g_lo || it >= g_hi) {
-                int lo = 0, hi = nreg - 1;   // last region with item0 <= it
+                int lo = 0, hi = a.nreg - 1;   // last region with item0 <= it
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    if (regs[mid].item0 <= it) lo = mid;
+                    if (a.regs[mid].item0 <= it) lo = mid;
                     else hi = mid - 1;
                 }
                 g_idx = lo;
-                g_lo = regs[lo].item0;
-                g_hi = lo + 1 < nreg ? regs[lo + 1].item0 : INT64_MAX;
+                g_lo = a.regs[lo].item0;
+                g_hi = lo + 1 < a.nreg ? a.regs[lo + 1].item0 : INT64_MAX;
             }
-            const Region *G = regs + g_idx;
+            const Region *G = a.regs + g_idx;
             const int64_t loc = it - g_lo;
             const int64_t j = loc >> 1;
             const int d = (int)(loc & 1);
             if (j >= G->M) continue;
             if (G->walk_flag && !G->walk_flag[j]) continue;
-            if (G->mode == MODE_CORE) ids_walk<MODE_CORE, R>(G, j, d, base, Ly, pcap, kcap);
-            else ids_walk<MODE_POOLED, R>(G, j, d, base, Ly, pcap, kcap);
+            if (G->mode == MODE_CORE)
+                ids_walk<MODE_CORE, R>(G, j, d, base, Ly, a.pcap, a.kcap, it, a.redo, a.redo_count);
+            else
+                ids_walk<MODE_POOLED, R>(G, j, d, base, Ly, a.pcap, a.kcap, it, a.redo,
+                                         a.redo_count);
             __syncthreads();
         }
         if (threadIdx.x == 0) grab[gb ^ 1] = nxt;
@@ -712,11 +739,9 @@ __global__ void __launch_bounds__(1024) ids_batch_kernel(const Region *__restric
 }
 
 template <int R>
-hipError_t launch_r(const Region *regs, int32_t nreg, int64_t total, int64_t stride,
-                    unsigned long long *counter, const WideCfg &c, hipStream_t s) {
+hipError_t launch_r(const IdsArgs &a, const WideCfg &c, hipStream_t s) {
     hipLaunchKernelGGL((ids_batch_kernel<R>), dim3((unsigned)c.blocks), dim3((unsigned)c.threads),
-                       c.lds, s, regs, nreg, total, stride, counter, c.chunk, c.lmax, c.pair_cap,
-                       c.key_cap);
+                       c.lds, s, a);
     return hipGetLastError();
 }
 
@@ -746,11 +771,17 @@ int ids_threads_for(int wmax, int slots) {
     return t <= 1024 ? (t > 0 ? t : 64) : 0;
 }
 
-size_t ids_lds_bytes(int threads, int lmax, int wmax, int pair_cap, int key_cap) {
+size_t ids_lds_bytes(int threads, int lmax, int wmax, int class_cap, int pair_cap, int key_cap,
+                     int copies) {
     if (threads < 64 || threads > 1024 || threads % 64) return 0;
     if (lmax < 2 || lmax > 32767 || ids_slots(threads, wmax) == 0) return 0;
-    if (pair_cap < 0 || key_cap < 0 || key_cap > 32767) return 0;
-    return batch_layout(lmax, pair_cap, key_cap).total;
+    if (class_cap < 0 || pair_cap < 0 || key_cap < 0 || key_cap > 32767) return 0;
+    if (copies != 1 && copies != 8) return 0;
+    return batch_layout(lmax, class_cap, pair_cap, key_cap, copies).total;
+}
+
+bool ids_table_capped(int lmax, int class_cap) {
+    return class_cap > 0 && class_cap < lmax / 2 + 2;
 }
 
 int ids_blocks_per_cu(const WideCfg &c) {
@@ -764,17 +795,15 @@ int ids_blocks_per_cu(const WideCfg &c) {
     }
 }
 
-hipError_t launch_ids_batch(const Region *regs, int32_t nreg, int64_t total_items,
-                            int64_t stride, unsigned long long *counter, const WideCfg &c,
-                            hipStream_t s) {
-    if (nreg <= 0 || total_items <= 0) return hipSuccess;
+hipError_t launch_ids_batch(const IdsArgs &a, const WideCfg &c, hipStream_t s) {
+    if (a.nreg <= 0 || (!a.list && a.total <= 0)) return hipSuccess;
     if (c.blocks <= 0 || c.chunk <= 0) return hipErrorInvalidValue;
     switch (ids_slots(c.threads, c.wmax)) {
-        case 1: return launch_r<1>(regs, nreg, total_items, stride, counter, c, s);
-        case 2: return launch_r<2>(regs, nreg, total_items, stride, counter, c, s);
-        case 4: return launch_r<4>(regs, nreg, total_items, stride, counter, c, s);
-        case 8: return launch_r<8>(regs, nreg, total_items, stride, counter, c, s);
-        case 16: return launch_r<16>(regs, nreg, total_items, stride, counter, c, s);
+        case 1: return launch_r<1>(a, c, s);
+        case 2: return launch_r<2>(a, c, s);
+        case 4: return launch_r<4>(a, c, s);
+        case 8: return launch_r<8>(a, c, s);
+        case 16: return launch_r<16>(a, c, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -111,6 +111,7 @@ CONFIGS = [dict(threads=64), dict(threads=256), dict(threads=1024), dict(pair_ca
            dict(blocks_per_cu=1), dict(threads=1024, pair_cap=4096, chunk=3, order=1),
            dict(small_pair_cap=1024), dict(threads=128, small_pair_cap=4096, pair_cap=0),
            dict(slots=4), dict(slots=8, chunk=4), dict(slots=4, threads=320, pair_cap=4096),
+           dict(class_cap=64), dict(class_cap=0), dict(class_cap=64, pair_cap=0, slots=8),
            dict(kernel=1, threads=128), dict(kernel=1, threads=256), dict(kernel=1, threads=512),
            dict(kernel=1, threads=256, pair_cap=0), dict(kernel=1, threads=128, pair_cap=8192,
                                                             chunk=3, order=1)]
@@ -224,3 +225,37 @@ def test_large_batch_full_size_sampled_parity(ss):
     z = _standardize_numpy(got["unstd"], got["status"], bins, 40)
     assert_log(got["std"], z, np.isin(got["status"], (0, 5)), "std")
     assert (got["status"] == 0).sum() > 100000
+
+
+@pytest.mark.parametrize("cap", [64, 128])
+def test_walks_that_outgrow_a_capped_class_table_are_redone(ss, cap):
+    # i.i.d. alleles: the classes multiply at every marker, so most walks
+    # outgrow a small table and finish in the full-table launch
+    d = hapgen.random_haplotypes(900, 400, 77, p=0.5)
+    e = hapgen.random_haplotypes(700, 400, 78, n_founders=40, switch_p=0.01)
+    say("capped class table %d" % cap)
+    ha = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
+    he = _hm(ss, e.alleles, e.pos_bp, e.gpos_cm)
+    # a low cutoff keeps the i.i.d. walks going for 7+ markers (hundreds of classes)
+    ref_d = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm, oracle.Params(maf_cutoff=0.0, ehh_cutoff=0.001))
+    ref_e = oracle.ihs(e.alleles, e.pos_bp, e.gpos_cm)
+    params = ss.Params(maf_cutoff=0.0, ehh_cutoff=0.001)
+    reqs = [ss.ScanRequest(ha), ss.ScanRequest(he)]
+    for r in reqs:
+        ss.alloc_outputs(r, steps=True)
+    try:
+        ss.set_batch_config(ss.BatchConfig(small_kernel=0, class_cap=cap))
+        ss.scan_batch(reqs[:1], params)
+        ss.scan_batch(reqs[1:])
+        got = [_np(r.out) for r in reqs]
+        ss.set_batch_config(ss.BatchConfig(small_kernel=0, class_cap=0))
+        ss.scan_batch(reqs[:1], params)
+        full = _np(reqs[0].out)
+    finally:
+        ss.set_batch_config(ss.BatchConfig())
+    check_ihs(got[0], ref_d, "capped iid")
+    check_ihs(got[1], ref_e, "capped copying")
+    for k in full:
+        np.testing.assert_array_equal(got[0][k], full[k], err_msg=k)
+    # the i.i.d. walks really do pass 64 classes
+    assert ref_d["steps"].max() >= 7
