@@ -251,6 +251,9 @@ typedef struct ss_batch_config {
                                walk can have, n/2 + 2; else 64..16386, default 1024):
                                walks that outgrow it are redone by a second launch with
                                full tables                                             */
+    int32_t counter_copies; /* kernel 0: copies of each class counter, over which the
+                               members of one class spread their LDS atomics (1 or 8;
+                               0 = 8 for workgroups of 256 threads or more, else 1)    */
 } ss_batch_config;
 
 int ss_get_batch_config(ss_batch_config *c);

@@ -64,7 +64,8 @@ class _BatchConfig(ctypes.Structure):
                 ("chunk", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("small_kernel", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("small_pair_cap", ctypes.c_int32),
-                ("slots", ctypes.c_int32), ("class_cap", ctypes.c_int32)]
+                ("slots", ctypes.c_int32), ("class_cap", ctypes.c_int32),
+                ("counter_copies", ctypes.c_int32)]
 
 
 _lib = None
@@ -434,19 +435,21 @@ class BatchConfig:
     small_pair_cap: int = 1024
     slots: int = 16
     class_cap: int = 1024
+    counter_copies: int = 0
 
 
 def get_batch_config() -> BatchConfig:
     c = _BatchConfig()
     _check(lib().ss_get_batch_config(ctypes.byref(c)))
     return BatchConfig(c.threads, c.pair_cap, c.chunk, c.blocks_per_cu, c.order, c.small_kernel,
-                       c.kernel, c.small_pair_cap, c.slots, c.class_cap)
+                       c.kernel, c.small_pair_cap, c.slots, c.class_cap, c.counter_copies)
 
 
 def set_batch_config(cfg: BatchConfig):
     c = _BatchConfig(int(cfg.threads), int(cfg.pair_cap), int(cfg.chunk), int(cfg.blocks_per_cu),
                      int(cfg.order), int(cfg.small_kernel), int(cfg.kernel),
-                     int(cfg.small_pair_cap), int(cfg.slots), int(cfg.class_cap))
+                     int(cfg.small_pair_cap), int(cfg.slots), int(cfg.class_cap),
+                     int(cfg.counter_copies))
     _check(lib().ss_set_batch_config(ctypes.byref(c)))
 
 
@@ -468,7 +471,7 @@ def autotune_batch(reqs, params: Optional[Params] = None, stream=None,
                                    int(sample_items), ctypes.byref(best), ctypes.byref(ms)))
     cfg = BatchConfig(best.threads, best.pair_cap, best.chunk, best.blocks_per_cu, best.order,
                       best.small_kernel, best.kernel, best.small_pair_cap, best.slots,
-                      best.class_cap)
+                      best.class_cap, best.counter_copies)
     return cfg, float(ms.value), ws
 
 

@@ -178,7 +178,7 @@ hipEvent_t take_event() {
 
 int g_walk_kind = ss::WALK_AUTO;
 int g_mask_lpc = 0;   // lanes per class of the bitmask walk; 0 = default
-ss_batch_config g_bcfg = {64, 4096, 1, 0, 0, 1, 0, 1024, 16, 1024};
+ss_batch_config g_bcfg = {64, 4096, 1, 0, 0, 1, 0, 1024, 16, 1024, 0};
 bool g_graph_on = false;
 bool g_capturing = false;   // timing events are not recorded into graphs
 
@@ -194,6 +194,8 @@ int check_batch_config(const ss_batch_config &c) {
     if (c.slots != 4 && c.slots != 8 && c.slots != 16) return fail(SS_EARG, "slots must be 4, 8 or 16");
     if (c.class_cap != 0 && (c.class_cap < 64 || c.class_cap > 16386))
         return fail(SS_EARG, "class_cap must be 0 or in [64, 16386]");
+    if (c.counter_copies != 0 && c.counter_copies != 1 && c.counter_copies != 8)
+        return fail(SS_EARG, "counter_copies must be 0, 1 or 8");
     if (c.chunk < 1 || c.chunk > 4096) return fail(SS_EARG, "chunk must be in [1, 4096]");
     if (c.blocks_per_cu < 0 || c.blocks_per_cu > 64) return fail(SS_EARG, "blocks_per_cu must be in [0, 64]");
     if (c.order != 0 && c.order != 1) return fail(SS_EARG, "order must be 0 or 1");
@@ -223,7 +225,7 @@ bool make_wide_cfg(const ss_batch_config &bc, int lmax, int wmax, ss::WideCfg &c
         c.class_cap = bc.class_cap;
         // counter copies pay off for the large classes of wide regions; small
         // workgroups keep one copy and their occupancy
-        c.copies = c.threads >= 256 ? 8 : 1;
+        c.copies = bc.counter_copies ? bc.counter_copies : (c.threads >= 256 ? 8 : 1);
         c.lds = ss::ids_lds_bytes(c.threads, lmax, wmax, c.class_cap, c.pair_cap, c.key_cap,
                                   c.copies);
         if (c.lds == 0 || c.lds > (size_t)max_lds_per_block()) {
@@ -1023,6 +1025,13 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
                 for (int cc : {0, 512, 1024, 2048}) {
                     ss_batch_config c = cur;
                     c.class_cap = cc;
+                    double ms;
+                    SS_TRY(time_cfg(c, ms));
+                    if (ms < cur_ms) { cur = c; cur_ms = ms; }
+                }
+                for (int cp : {1, 8}) {
+                    ss_batch_config c = cur;
+                    c.counter_copies = cp;
                     double ms;
                     SS_TRY(time_cfg(c, ms));
                     if (ms < cur_ms) { cur = c; cur_ms = ms; }

@@ -161,14 +161,15 @@ def test_batch_config_round_trip_and_range_checks(lib):
     try:
         for cfg in (ss.BatchConfig(threads=320), ss.BatchConfig(kernel=1, threads=128),
                     ss.BatchConfig(pair_cap=0, small_pair_cap=4096, chunk=16, order=1,
-                                   blocks_per_cu=2, small_kernel=0, slots=8, class_cap=0)):
+                                   blocks_per_cu=2, small_kernel=0, slots=8, class_cap=0,
+                                   counter_copies=8)):
             ss.set_batch_config(cfg)
             assert ss.get_batch_config() == cfg
         for bad in (dict(threads=96), dict(threads=2048), dict(kernel=1, threads=1024),
                     dict(kernel=2), dict(pair_cap=-1), dict(pair_cap=20000), dict(chunk=0),
                     dict(order=2), dict(small_kernel=3), dict(small_pair_cap=-5),
                     dict(blocks_per_cu=-1), dict(slots=5), dict(slots=32), dict(class_cap=10),
-                    dict(class_cap=20000)):
+                    dict(class_cap=20000), dict(counter_copies=4)):
             with pytest.raises(ss.SelscanError) as e:
                 ss.set_batch_config(ss.BatchConfig(**bad))
             assert e.value.code == ss.SS_EARG

@@ -112,6 +112,7 @@ CONFIGS = [dict(threads=64), dict(threads=256), dict(threads=1024), dict(pair_ca
            dict(small_pair_cap=1024), dict(threads=128, small_pair_cap=4096, pair_cap=0),
            dict(slots=4), dict(slots=8, chunk=4), dict(slots=4, threads=320, pair_cap=4096),
            dict(class_cap=64), dict(class_cap=0), dict(class_cap=64, pair_cap=0, slots=8),
+           dict(counter_copies=1), dict(counter_copies=8), dict(counter_copies=8, class_cap=64),
            dict(kernel=1, threads=128), dict(kernel=1, threads=256), dict(kernel=1, threads=512),
            dict(kernel=1, threads=256, pair_cap=0), dict(kernel=1, threads=128, pair_cap=8192,
                                                             chunk=3, order=1)]
