@@ -32,6 +32,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import Optional, Sequence
 
 import numpy as np
@@ -41,6 +42,7 @@ __all__ = [
     "copy_haplotypes", "plant_sweep", "copying_model", "config_input",
     "random_haplotypes", "CONFIGS", "CopyEvents", "draw_copy_events", "render_alleles",
     "plant_sweep_tensor", "large_batch_input", "poisson_arrivals", "log_uniform_int",
+    "SERVE", "RequestSpec", "request_stream", "device_region", "region_numpy", "build_gpu",
 ]
 
 
@@ -352,8 +354,8 @@ def log_uniform_int(rng: np.random.Generator, lo: int, hi: int) -> int:
 
 # ---------------------------------------------------------------------------
 # Served region-scan requests: many regions of random sizes, generated on the
-# device from per-request seeds (torch's counter-based generator), so that a
-# request stream of ~10^11 alleles does not wait on the host.
+# device from per-request seeds with counter-based hashes, so that a request
+# stream of ~10^11 alleles does not wait on the host.
 # ---------------------------------------------------------------------------
 SERVE = dict(n_requests=4096, rate_per_s=200.0, p_ihs=0.6, n_range=(100, 5000),
              sites_range=(1000, 200_000), bp_per_site=1580, n_founders=40, switch_p=0.003,
@@ -389,59 +391,207 @@ def request_stream(n_requests: Optional[int] = None, rate_per_s: Optional[float]
     return out
 
 
-def _device_copy(gen, founders, n_haps: int, switch_p: float, flip_p: float, chunk: int = 16384):
-    """Founder copying on the device, drawn haplotype-major so that the
-    founder path is a scan along the contiguous axis; returned site-major.
+# The served requests' generator: counter-based hashes (splitmix64's
+# finalizer over key ^ (row << 32 | column)), evaluated by the HIP kernels in
+# gen.hip on the device and by the numpy functions below on the host; both
+# take the same integer and float32 steps, so they give the same arrays.
+# Stream tags per population: 0 (A) or 8 (B) plus 0 site frequency, 1 founder
+# alleles, 2 sharing with A, 3 switches and flips, 5 starting founder; 15 the
+# site spacings.
+HERE = os.path.dirname(os.path.abspath(__file__))
+GEN_LIB = os.path.join(HERE, "libhapgen_gpu.so")
+_U64 = np.uint64
+_F32 = np.float32
 
-    One uniform u per (haplotype, site) decides the switch (u < switch_p) and,
-    rescaled to [0, 1), which other founder is taken next; a second uniform
-    decides the flip."""
+
+def _mix64(z):
+    z = np.asarray(z, dtype=_U64)
+    with np.errstate(over="ignore"):
+        z = z + _U64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> _U64(30))) * _U64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> _U64(27))) * _U64(0x94D049BB133111EB)
+    return z ^ (z >> _U64(31))
+
+
+def _key(seed: int, tag: int) -> int:
+    return int(_mix64(np.array([(int(seed) * 16 + int(tag)) % (1 << 64)], dtype=_U64))[0])
+
+
+def _draw(key: int, row, col):
+    row = np.asarray(row, dtype=_U64)
+    col = np.asarray(col, dtype=_U64)
+    return _mix64(_U64(key) ^ ((row << _U64(32)) | col))
+
+
+def _top24(w):
+    return (w >> _U64(40)).astype(_F32) * _F32(1.0 / 16777216.0)
+
+
+def _mid24(w):
+    return ((w >> _U64(16)) & _U64(0xFFFFFF)).astype(_F32) * _F32(1.0 / 16777216.0)
+
+
+def gaps_numpy(seed: int, n_sites: int, bp_per_site: float) -> np.ndarray:
+    """Site spacings: 1 for the first site, else max(1, floor(-ln(1-u) bp))."""
+    s = np.arange(n_sites, dtype=_U64)
+    u = (_draw(_key(seed, 15), 0, s) >> _U64(11)).astype(np.float64) * 2.0 ** -53
+    g = np.maximum(np.floor(-np.log1p(-u) * float(bp_per_site)), 1.0).astype(np.int64)
+    if n_sites:
+        g[0] = 1
+    return g
+
+
+def site_p_numpy(seed: int, tag: int, n_sites: int):
+    """(x^2, x^2 + y^2) per site for (x, y) uniform in the unit disk; the
+    site frequency is their ratio, arcsine distributed."""
+    kp = _key(seed, tag)
+    xx = np.full(n_sites, 0.5, dtype=_F32)
+    r = np.ones(n_sites, dtype=_F32)
+    todo = np.arange(n_sites, dtype=_U64)
+    for t in range(64):
+        if todo.size == 0:
+            break
+        x = _F32(2.0) * _top24(_draw(kp, 2 * t, todo)) - _F32(1.0)
+        y = _F32(2.0) * _top24(_draw(kp, 2 * t + 1, todo)) - _F32(1.0)
+        x2 = x * x
+        rr = x2 + y * y
+        ok = (rr <= _F32(1.0)) & (rr > _F32(0.0))
+        idx = todo[ok].astype(np.int64)
+        xx[idx] = x2[ok]
+        r[idx] = rr[ok]
+        todo = todo[~ok]
+    return xx, r
+
+
+def founders_numpy(seed: int, tag: int, n_founders: int, n_sites: int,
+                   base: Optional[np.ndarray] = None, share: float = 0.0) -> np.ndarray:
+    """Founder alleles [F][M]: derived when u (x^2 + y^2) < x^2; with base,
+    each entry is base's with probability share."""
+    xx, r = site_p_numpy(seed, tag, n_sites)
+    f = np.arange(n_founders, dtype=_U64)[:, None]
+    s = np.arange(n_sites, dtype=_U64)[None, :]
+    out = ((_top24(_draw(_key(seed, tag + 1), f, s)) * r[None, :]) < xx[None, :]).astype(np.uint8)
+    if base is not None:
+        keep = _top24(_draw(_key(seed, tag + 2), f, s)) < _F32(share)
+        out = np.where(keep, base, out).astype(np.uint8)
+    return out
+
+
+def copy_numpy(seed: int, tag: int, founders: np.ndarray, n_haps: int, switch_p: float,
+               flip_p: float) -> np.ndarray:
+    """Alleles [M][n] copied from the founders along each haplotype's path."""
+    F, M = founders.shape
+    h = np.arange(n_haps, dtype=_U64)
+    w = _draw(_key(seed, tag + 3), h[:, None], np.arange(M, dtype=_U64)[None, :])
+    switch = _top24(w) < _F32(switch_p)
+    switch[:, 0] = False
+    off = np.where(switch, 1 + (((_U64(F - 1) * (w & _U64(0xFFFF))) >> _U64(16)).astype(np.int64)), 0)
+    f0 = ((_draw(_key(seed, tag + 5), h, 0) >> _U64(32)) * _U64(F)) >> _U64(32)
+    path = (f0.astype(np.int64)[:, None] + np.cumsum(off, axis=1)) % F
+    a = founders[path, np.arange(M)[None, :]]
+    a ^= (_mid24(w) < _F32(flip_p)).astype(np.uint8)
+    return np.ascontiguousarray(a.T)
+
+
+def region_numpy(spec: "RequestSpec"):
+    """The served request's inputs on the host: (alleles_a, alleles_b or None,
+    pos_bp, gpos_cm), equal to device_region's."""
+    c = SERVE
+    F, M = c["n_founders"], spec.n_sites
+    pos = np.cumsum(gaps_numpy(spec.seed, M, c["bp_per_site"]))
+    fa = founders_numpy(spec.seed, 0, F, M)
+    a = copy_numpy(spec.seed, 0, fa, spec.n_a, c["switch_p"], c["flip_p"])
+    b = None
+    if spec.kind == "xpehh":
+        fb = founders_numpy(spec.seed, 8, F, M, fa, c["share_p"])
+        b = copy_numpy(spec.seed, 8, fb, spec.n_b, c["switch_p"], c["flip_p"])
+    return a, b, pos, pos.astype(np.float64) * 1e-6
+
+
+def build_gpu(arch: str = "gfx950") -> str:
+    """Compile gen.hip into libhapgen_gpu.so (always recompiles)."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    tmp = GEN_LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc, "-O3", "-std=c++17", "--offload-arch=" + arch, "-fPIC", "-shared",
+           "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           os.path.join(HERE, "gen.hip"), "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + res.stderr[-4000:])
+    os.replace(tmp, GEN_LIB)
+    return GEN_LIB
+
+
+_GEN = None
+
+
+def _gen_lib():
+    global _GEN
+    if _GEN is None:
+        import ctypes as C
+        if not os.path.exists(GEN_LIB):
+            raise RuntimeError("%s is not built (hapgen.build_gpu())" % GEN_LIB)
+        lib = C.CDLL(GEN_LIB)
+        p, i64, u64, i32, f32 = C.c_void_p, C.c_int64, C.c_uint64, C.c_int, C.c_float
+        lib.hg_gaps.argtypes = [u64, i64, C.c_double, p, p]
+        lib.hg_founders.argtypes = [u64, i32, i32, i64, p, f32, p, p]
+        lib.hg_block_offsets.argtypes = [u64, i32, i32, i64, i32, f32, p, p]
+        lib.hg_copy.argtypes = [u64, i32, p, i32, i64, i32, f32, f32, p, p, p]
+        for f in (lib.hg_gaps, lib.hg_founders, lib.hg_block_offsets, lib.hg_copy):
+            f.restype = C.c_int
+        _GEN = lib
+    return _GEN
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError("%s failed (%d)" % (what, rc))
+
+
+def _copy_device(lib, stream, seed: int, tag: int, founders, n_haps: int, switch_p: float,
+                 flip_p: float):
     import torch
     F, M = founders.shape
     dev = founders.device
     out = torch.empty((M, n_haps), dtype=torch.uint8, device=dev)
-    cur = torch.randint(0, F, (n_haps,), generator=gen, device=dev).to(torch.int32)
-    for s0 in range(0, M, chunk):
-        s1 = min(M, s0 + chunk)
-        u = torch.rand((n_haps, s1 - s0), generator=gen, device=dev)
-        if F >= 2:
-            step = torch.where(u < switch_p,
-                               1 + torch.clamp((u * (1.0 / switch_p) * (F - 1)).to(torch.int32),
-                                               max=F - 2),
-                               torch.zeros((), dtype=torch.int32, device=dev))
-        else:
-            step = torch.zeros_like(u, dtype=torch.int32)
-        if s0 == 0:
-            step[:, 0] = 0
-        path = torch.remainder(cur[:, None] + torch.cumsum(step, dim=1, dtype=torch.int32), F)
-        cur = path[:, -1].clone()
-        col = torch.arange(s0, s1, device=dev, dtype=torch.int32)[None, :]
-        block = founders[path.long(), col.long()]
-        flips = torch.rand((n_haps, s1 - s0), generator=gen, device=dev) < flip_p
-        out[s0:s1] = (block ^ flips.to(torch.uint8)).t()
+    if n_haps == 0:
+        return out
+    nb = (M + 63) // 64
+    sums = torch.empty((n_haps, nb), dtype=torch.int32, device=dev)
+    _check(lib.hg_block_offsets(seed, tag, F, M, n_haps, switch_p, sums.data_ptr(), stream),
+           "hg_block_offsets")
+    excl = torch.cumsum(sums, dim=1, dtype=torch.int64) - sums
+    _check(lib.hg_copy(seed, tag, founders.data_ptr(), F, M, n_haps, switch_p, flip_p,
+                       excl.data_ptr(), out.data_ptr(), stream), "hg_copy")
     return out
 
 
 def device_region(spec: RequestSpec, device="cuda"):
-    """Inputs of one served request, generated on ``device``: (alleles_a,
-    alleles_b or None, pos_bp, gpos_cm) as torch tensors; positions are drawn
-    on the host from the same seed."""
+    """Inputs of one served request, generated on the GPU ``device`` from its
+    seed on the current stream: (alleles_a, alleles_b or None, pos_bp,
+    gpos_cm) as torch tensors, equal to region_numpy's.
+
+    Positions: a Poisson process of about one site per bp_per_site bp
+    (exponential spacings, each at least 1 bp) starting at 1; 1 cM/Mb."""
     import torch
     c = SERVE
-    rng = np.random.default_rng(spec.seed)
-    pos, gpos = draw_positions(rng, spec.n_sites, max(spec.n_sites, spec.n_sites * c["bp_per_site"]))
-    gen = torch.Generator(device=device)
-    gen.manual_seed(int(spec.seed))
-    F, M = c["n_founders"], spec.n_sites
-    # Beta(1/2, 1/2) is the arcsine law: sin^2(pi U / 2)
-    p = torch.sin(0.5 * math.pi * torch.rand(M, generator=gen, device=device)) ** 2
-    fa = (torch.rand((F, M), generator=gen, device=device) < p[None, :]).to(torch.uint8)
-    a = _device_copy(gen, fa, spec.n_a, c["switch_p"], c["flip_p"])
+    lib = _gen_lib()
+    dev = torch.device(device)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    F, M, seed = c["n_founders"], spec.n_sites, int(spec.seed)
+    gaps = torch.empty(M, dtype=torch.int64, device=dev)
+    _check(lib.hg_gaps(seed, M, float(c["bp_per_site"]), gaps.data_ptr(), stream), "hg_gaps")
+    pos = torch.cumsum(gaps, 0)
+    gpos = pos.to(torch.float64) * 1e-6
+    fa = torch.empty((F, M), dtype=torch.uint8, device=dev)
+    _check(lib.hg_founders(seed, 0, F, M, None, 0.0, fa.data_ptr(), stream), "hg_founders")
+    a = _copy_device(lib, stream, seed, 0, fa, spec.n_a, c["switch_p"], c["flip_p"])
     b = None
     if spec.kind == "xpehh":
-        p2 = torch.sin(0.5 * math.pi * torch.rand(M, generator=gen, device=device)) ** 2
-        fresh = (torch.rand((F, M), generator=gen, device=device) < p2[None, :]).to(torch.uint8)
-        keep = torch.rand((F, M), generator=gen, device=device) < c["share_p"]
-        fb = torch.where(keep, fa, fresh)
-        b = _device_copy(gen, fb, spec.n_b, c["switch_p"], c["flip_p"])
-    return (a, b, torch.from_numpy(pos).to(device), torch.from_numpy(gpos).to(device))
+        fb = torch.empty((F, M), dtype=torch.uint8, device=dev)
+        _check(lib.hg_founders(seed, 8, F, M, fa.data_ptr(), c["share_p"], fb.data_ptr(), stream),
+               "hg_founders")
+        b = _copy_device(lib, stream, seed, 8, fb, spec.n_b, c["switch_p"], c["flip_p"])
+    return (a, b, pos, gpos)

@@ -86,22 +86,55 @@ def test_large_batch_input_scaled():
     assert np.array_equal(pos, pos2) and bool((a == b).all())
 
 
-def test_device_request_generator():
-    import torch
+def test_request_stream():
     reqs = hapgen.request_stream(64)
     assert len(reqs) == 64 and all(a.arrival_s < b.arrival_s for a, b in zip(reqs, reqs[1:]))
     assert {r.kind for r in reqs} == {"ihs", "xpehh"}
     assert all(100 <= r.n_a <= 5000 and 1000 <= r.n_sites <= 200000 for r in reqs)
+
+
+def test_hash_is_splitmix64():
+    # splitmix64's published output for state 0: the finalizer applied to the
+    # state after one increment
+    assert int(hapgen._mix64(np.array([0], dtype=np.uint64))[0]) == 0xE220A8397B1DCDAF
+    assert int(hapgen._mix64(np.array([0x9E3779B97F4A7C15], dtype=np.uint64))[0]) == 0x6E789E6AA1B965F4
+
+
+def test_served_region_generator_statistics():
     spec = hapgen.RequestSpec(0, "xpehh", 0.0, 300, 250, 3000, 5)
-    a, b, pos, gpos = hapgen.device_region(spec, "cpu")
-    a2, b2, pos2, _ = hapgen.device_region(spec, "cpu")
-    assert tuple(a.shape) == (3000, 300) and tuple(b.shape) == (3000, 250)
-    assert bool((a == a2).all()) and bool((b == b2).all()) and bool((pos == pos2).all())
-    assert bool((pos[1:] > pos[:-1]).all())
-    # switches happen at the model's rate and always move to another founder
-    gen = torch.Generator()
-    gen.manual_seed(3)
-    fo = torch.arange(40, dtype=torch.uint8)[:, None].expand(40, 20000).contiguous()
-    out = hapgen._device_copy(gen, fo, 300, 0.003, 0.0)
-    rate = (out[1:] != out[:-1]).float().mean().item()
-    assert abs(rate - 0.003) < 0.0004
+    a, b, pos, gpos = hapgen.region_numpy(spec)
+    a2, b2, pos2, _ = hapgen.region_numpy(spec)
+    assert a.shape == (3000, 300) and b.shape == (3000, 250) and a.dtype == np.uint8
+    assert np.array_equal(a, a2) and np.array_equal(b, b2) and np.array_equal(pos, pos2)
+    assert set(np.unique(a)) <= {0, 1}
+    assert pos[0] == 1 and np.all(np.diff(pos) >= 1)
+    np.testing.assert_array_equal(gpos, pos * 1e-6)
+    # exponential spacings of mean about bp_per_site
+    g = hapgen.gaps_numpy(11, 40000, 1580)[1:]
+    assert abs(g.mean() - 1579.5) < 25 and abs(np.median(g) - 1580 * np.log(2)) < 40
+    # site frequencies follow the arcsine law: CDF (2/pi) asin(sqrt(p))
+    xx, r = hapgen.site_p_numpy(3, 0, 20000)
+    p = np.sort(xx.astype(np.float64) / r)
+    cdf = 2 / np.pi * np.arcsin(np.sqrt(p))
+    emp = np.arange(1, p.size + 1) / p.size
+    assert np.max(np.abs(cdf - emp)) < 0.015
+    # founders carry the derived allele at the site frequency
+    fo = hapgen.founders_numpy(3, 0, 400, 2000)
+    pp = xx[:2000].astype(np.float64) / r[:2000]
+    assert np.abs(fo.mean(axis=0) - pp).max() < 0.12 and abs((fo.mean(axis=0) - pp).mean()) < 0.005
+    # population B keeps A's founder entries with probability share (plus chance agreement)
+    fb = hapgen.founders_numpy(3, 8, 400, 2000, fo, 0.8)
+    same = (fb == fo).mean()
+    assert 0.8 < same < 0.8 + 0.2 * 0.75
+    # switches happen at the model's rate and always move to another founder,
+    # uniformly; flips at theirs
+    ident = np.repeat(np.arange(40, dtype=np.uint8)[:, None], 20000, axis=1)
+    out = hapgen.copy_numpy(3, 0, ident, 300, 0.003, 0.0)
+    moved = out[1:] != out[:-1]
+    assert abs(moved.mean() - 0.003) < 0.0004
+    step = ((out[1:].astype(int) - out[:-1].astype(int)) % 40)[moved]
+    assert step.min() >= 1 and np.bincount(step, minlength=40)[1:].min() > 0.5 * moved.sum() / 39
+    assert np.bincount(out[0], minlength=40).min() > 0     # starting founders cover all 40
+    zero = np.zeros((40, 20000), dtype=np.uint8)
+    fl = hapgen.copy_numpy(3, 0, zero, 300, 0.003, 0.001)
+    assert abs(fl.mean() - 0.001) < 0.0002
