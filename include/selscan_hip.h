@@ -190,8 +190,9 @@ int ss_set_walk_kernel(int kind);
  * Batched scans.  One call scans many regions -- iHS regions and XPEHH
  * region pairs of any sizes -- and runs the EHH walks of all of them in one
  * persistent launch: a grid sized to the GPU takes work items (region, site,
- * direction[, core]) from a device counter, so walks of very uneven length
- * and regions of different haplotype counts share the launch.  Every result
+ * direction[, core]) from device counters (the items cut into 8 parts, one
+ * counter each), so walks of very uneven length and regions of different
+ * haplotype counts share the launch.  Every result
  * is the one ss_ihs / ss_xpehh gives for that region alone (Sec. 1.2 and
  * Sec. 1.3; standardization is per region).
  */

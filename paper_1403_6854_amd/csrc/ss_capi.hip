@@ -98,6 +98,11 @@ int device_cus() {
 }
 
 // Workspace of one scan.
+// Counters of one launch group of the persistent walk: the first launch's
+// work queue, the second (full-table) launch's, and the count of the walks
+// listed for the second launch on a line of its own.
+constexpr int kGroupCtrWords = 2 * ss::kQueueWords + ss::kCtrStride;
+
 struct ScanWs {
     uint8_t *walk_flag;   // [M]
     int32_t *bin;         // [M]
@@ -110,7 +115,7 @@ struct ScanWs {
     double *seg;          // [M] segment lengths with the gap rules applied
     int32_t *redo;        // [1 + 2M] overflow count, then the walks to redo
     ss::Region *region;   // [1] descriptor for the persistent walk
-    unsigned long long *counter;   // [3] its work counter, overflow count, redo work counter
+    unsigned long long *counter;   // [kGroupCtrWords] work queues of the two launches, redo count
     int64_t *wredo;       // [2M] walks the capped class table could not hold
     size_t bytes;
 };
@@ -134,7 +139,7 @@ ScanWs carve_scan(void *base, int64_t M, int nbins, int64_t n_hapmajor) {
     w.seg = (double *)take(8 * (size_t)M);
     w.redo = (int32_t *)take(4 * (1 + 2 * (size_t)M));
     w.region = (ss::Region *)take(sizeof(ss::Region));
-    w.counter = (unsigned long long *)take(4 * sizeof(unsigned long long));
+    w.counter = (unsigned long long *)take(kGroupCtrWords * sizeof(unsigned long long));
     w.wredo = (int64_t *)take(8 * 2 * (size_t)M);
     w.bytes = off;
     return w;
@@ -246,6 +251,36 @@ bool make_wide_cfg(const ss_batch_config &bc, int lmax, int wmax, ss::WideCfg &c
     return true;
 }
 
+// Whether a walk of the scan can reach the pairwise tail of the class-id
+// persistent walk, which starts once at most pcap identical pairs are left on
+// live cores: a live core with n_c haplotypes holds at least cutoff * C(n_c, 2)
+// pairs, and the smallest core a scan walks has at least floor(maf * n) of
+// them (XPEHH: the pooled sample).  Scans that cannot get there run without
+// pair buffers, and their workgroups take less LDS.
+bool tail_possible(int mode, int32_t nA, int32_t nB, double maf, double cutoff, int pcap) {
+    if (pcap <= 0) return false;
+    int64_t m;
+    if (mode == ss::MODE_POOLED) {
+        m = (int64_t)nA + nB;
+    } else {
+        m = (int64_t)std::floor(maf * (double)nA);
+        if (m < 2) m = 2;
+    }
+    return cutoff * 0.5 * (double)m * (double)(m - 1) <= (double)pcap;
+}
+
+// The configuration one launch runs with: the group's workgroup size, and no
+// pair buffers for scans that cannot reach the pairwise tail.
+ss_batch_config launch_config(const ss_batch_config &bc, int threads, bool pairs) {
+    ss_batch_config c = bc;
+    c.threads = threads;
+    if (!pairs && bc.kernel == 0) {
+        c.pair_cap = 0;
+        c.small_pair_cap = 0;
+    }
+    return c;
+}
+
 // Which kernel walks a scan.
 enum Route { RT_MASK, RT_WIDE, RT_IDS };
 
@@ -329,6 +364,7 @@ struct Scan {
     int8_t *status;
     int32_t *steps;
     int nbins;
+    double maf;             // MAF filter of the scan (iHS cores)
     Route route;
     ScanWs w;
     ss::WalkArgs args;
@@ -453,8 +489,8 @@ namespace {
 // One launch group of the class-id batch walk: the persistent launch with the
 // configured class table and, when that table is capped, a second launch with
 // full tables over the walks the first one listed (it ends at once when the
-// list is empty).  ctr[0..2]: work counter, list count, second work counter,
-// zeroed beforehand.
+// list is empty).  ctr: the first launch's work queue, the second launch's,
+// then the count of listed walks, zeroed beforehand (kGroupCtrWords words).
 int launch_ids_group(const ss::Region *regs, int nreg, int64_t total, int64_t stride,
                      unsigned long long *ctr, int64_t *redo, const ss::WideCfg &c, hipStream_t s) {
     ss::IdsArgs a{};
@@ -471,7 +507,7 @@ int launch_ids_group(const ss::Region *regs, int nreg, int64_t total, int64_t st
     a.kcap = c.key_cap;
     const bool capped = ss::ids_table_capped(c.lmax, c.class_cap);
     a.redo = capped ? redo : nullptr;
-    a.redo_count = capped ? (int32_t *)(ctr + 1) : nullptr;
+    a.redo_count = capped ? (int32_t *)(ctr + 2 * ss::kQueueWords) : nullptr;
     SS_HIP(ss::launch_ids_batch(a, c, s));
     if (!capped) return SS_OK;
     ss::WideCfg full = c;
@@ -491,9 +527,9 @@ int launch_ids_group(const ss::Region *regs, int nreg, int64_t total, int64_t st
     ss::IdsArgs b = a;
     b.kcls = 0;
     b.copies = full.copies;
-    b.counter = ctr + 2;
+    b.counter = ctr + ss::kQueueWords;
     b.list = redo;
-    b.list_count = (const int32_t *)(ctr + 1);
+    b.list_count = (const int32_t *)(ctr + 2 * ss::kQueueWords);
     b.redo = nullptr;
     b.redo_count = nullptr;
     b.stride = 1;
@@ -507,10 +543,14 @@ int walk_scan(Scan &sc, hipStream_t s) {
         ss::Region r = region_of(sc);
         const int64_t items = ss::region_items(sc.mode, sc.args.M, g_bcfg.kernel);
         ss::WideCfg c;
-        if (!make_wide_cfg(g_bcfg, list_len(r.nA, r.nB, sc.mode), row_words(r.nA, r.nB, sc.mode), c))
+        const int lmax = list_len(r.nA, r.nB, sc.mode), wmax = row_words(r.nA, r.nB, sc.mode);
+        if (!make_wide_cfg(g_bcfg, lmax, wmax, c))
+            return fail(SS_EDEV, "persistent walk does not fit this device");
+        if (c.kernel == 0 && !tail_possible(sc.mode, r.nA, r.nB, sc.maf, r.cutoff, c.pair_cap) &&
+            !make_wide_cfg(launch_config(g_bcfg, g_bcfg.threads, false), lmax, wmax, c))
             return fail(SS_EDEV, "persistent walk does not fit this device");
         SS_HIP(ss::launch_fill_regions(&r, 1, sc.w.region, s));
-        SS_HIP(ss::launch_zero_u64(sc.w.counter, 4, s));
+        SS_HIP(ss::launch_zero_u64(sc.w.counter, kGroupCtrWords, s));
         TimedRegion t(s);
         SS_TRY(t.begin());
         if (c.kernel == 0)
@@ -533,9 +573,10 @@ struct Group {
     int first = 0, count = 0;   // range of Batch::regions
     int64_t total_items = 0;
     int lmax = 0, wmax = 0, threads = 0;
+    bool pairs = true;          // some walk can reach the pairwise tail
 };
 
-constexpr int kMaxGroups = 16;
+constexpr int kMaxGroups = 32;
 
 struct Batch {
     std::vector<Scan> scans;
@@ -543,7 +584,7 @@ struct Batch {
     std::vector<ss::Region> regions;  // their descriptors, group by group (item0 per group)
     std::vector<Group> groups;
     ss::Region *d_regions = nullptr;
-    unsigned long long *d_counter = nullptr;   // three per group
+    unsigned long long *d_counter = nullptr;   // kGroupCtrWords per group
     int64_t *d_redo = nullptr;                 // redo lists, group by group
     int64_t total_items = 0;
     int lmax = 0, wmax = 0;
@@ -580,7 +621,7 @@ BatchLayout batch_layout(const ss_scan_request *reqs, int32_t n, const ss_params
     L.regions = off;
     off += align256(sizeof(ss::Region) * (size_t)n);
     L.counter = off;
-    off += align256(sizeof(unsigned long long) * 3 * kMaxGroups);
+    off += align256(sizeof(unsigned long long) * kGroupCtrWords * kMaxGroups);
     L.redo = off;   // walks listed for the full-table pass, 2 items per site at most
     size_t sites = 0;
     for (int32_t i = 0; i < n; ++i) sites += (size_t)reqs[i].a.n_sites;
@@ -595,6 +636,7 @@ BatchLayout batch_layout(const ss_scan_request *reqs, int32_t n, const ss_params
 void number_items(Batch &B, const ss_batch_config &bc) {
     struct Key {
         int threads, idx, len;
+        bool pairs;
     };
     std::vector<Key> keys;
     for (size_t i = 0; i < B.wide.size(); ++i) {
@@ -603,10 +645,14 @@ void number_items(Batch &B, const ss_batch_config &bc) {
         const int wrd = row_words(sc.args.nA, sc.args.nB, sc.mode);
         const int t = bc.kernel == 0 ? std::max(bc.threads, ss::ids_threads_for(wrd, bc.slots))
                                      : bc.threads;
-        keys.push_back({t, (int)i, len});
+        const bool pairs = bc.kernel != 0 ||
+                           tail_possible(sc.mode, sc.args.nA, sc.args.nB, sc.maf, sc.args.cutoff,
+                                         t <= 128 ? bc.small_pair_cap : bc.pair_cap);
+        keys.push_back({t, (int)i, len, pairs});
     }
     std::stable_sort(keys.begin(), keys.end(), [&](const Key &x, const Key &y) {
         if (x.threads != y.threads) return x.threads > y.threads;
+        if (x.pairs != y.pairs) return x.pairs;
         if (bc.order == 1) return x.len > y.len;
         return false;
     });
@@ -615,10 +661,12 @@ void number_items(Batch &B, const ss_batch_config &bc) {
     B.total_items = 0;
     int64_t item = 0;
     for (const Key &k : keys) {
-        if (B.groups.empty() || B.groups.back().threads != k.threads) {
+        if (B.groups.empty() || B.groups.back().threads != k.threads ||
+            B.groups.back().pairs != k.pairs) {
             Group g;
             g.first = (int)B.regions.size();
             g.threads = k.threads;
+            g.pairs = k.pairs;
             B.groups.push_back(g);
             item = 0;
         }
@@ -657,6 +705,7 @@ int build_batch(const ss_scan_request *reqs, int32_t n, const ss_params *p, void
         sc.status = r.d_status;
         sc.steps = r.d_steps;
         sc.nbins = sc.mode == ss::MODE_CORE ? nbins_of(p) : 1;
+        sc.maf = p->maf_cutoff;
         init_scan(sc, (char *)d_ws + L.offs[(size_t)i], p);
         const int32_t nB = sc.mode == ss::MODE_POOLED ? (int32_t)r.b.n_haps : 0;
         sc.route = route_for((int32_t)r.a.n_haps, nB, sc.mode, true);
@@ -682,14 +731,12 @@ int build_batch(const ss_scan_request *reqs, int32_t n, const ss_params *p, void
 int launch_batch_wide(Batch &B, const ss_batch_config &bc, int64_t sample_stride, hipStream_t s) {
     if (B.wide.empty()) return SS_OK;
     SS_HIP(ss::launch_fill_regions(B.regions.data(), (int)B.regions.size(), B.d_regions, s));
-    SS_HIP(ss::launch_zero_u64(B.d_counter, 3 * kMaxGroups, s));
+    SS_HIP(ss::launch_zero_u64(B.d_counter, kGroupCtrWords * kMaxGroups, s));
     int64_t redo_off = 0;
     for (size_t gi = 0; gi < B.groups.size(); ++gi) {
         const Group &g = B.groups[gi];
         ss::WideCfg c;
-        ss_batch_config gb = bc;
-        gb.threads = g.threads;
-        if (!make_wide_cfg(gb, g.lmax, g.wmax, c))
+        if (!make_wide_cfg(launch_config(bc, g.threads, g.pairs), g.lmax, g.wmax, c))
             return fail(SS_EDEV, "persistent walk configuration does not fit this device");
         const int64_t stride = sample_stride > 1 ? sample_stride : 1;
         int64_t total = g.total_items;
@@ -698,7 +745,7 @@ int launch_batch_wide(Batch &B, const ss_batch_config &bc, int64_t sample_stride
             total = 256 * ((blocks + stride - 1) / stride);
         }
         ss::Region *regs = B.d_regions + g.first;
-        unsigned long long *ctr = B.d_counter + 3 * gi;
+        unsigned long long *ctr = B.d_counter + kGroupCtrWords * gi;
         if (c.kernel == 0)
             SS_TRY(launch_ids_group(regs, g.count, total, stride, ctr, B.d_redo + redo_off, c, s));
         else
@@ -828,6 +875,7 @@ static int run_single(Scan &sc, const ss_params *p, void *d_ws, size_t ws_bytes,
     const size_t need = scan_bytes(sc.mode, sc.a, sc.b, p);
     if (!d_ws || ws_bytes < need) return fail(SS_EWS, "workspace smaller than ss_workspace_bytes()");
     sc.nbins = sc.mode == ss::MODE_CORE ? nbins_of(p) : 1;
+    sc.maf = p->maf_cutoff;
     init_scan(sc, d_ws, p);
     const int32_t nB = sc.mode == ss::MODE_POOLED ? (int32_t)sc.b->n_haps : 0;
     sc.route = route_for((int32_t)sc.a->n_haps, nB, sc.mode, false);
@@ -960,9 +1008,8 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
             number_items(B, c);
             for (const Group &g : B.groups) {
                 ss::WideCfg wc;
-                ss_batch_config gb = c;
-                gb.threads = g.threads;
-                if ((int)B.groups.size() > kMaxGroups || !make_wide_cfg(gb, g.lmax, g.wmax, wc)) {
+                if ((int)B.groups.size() > kMaxGroups ||
+                    !make_wide_cfg(launch_config(c, g.threads, g.pairs), g.lmax, g.wmax, wc)) {
                     ms = 1e30;
                     return SS_OK;
                 }

@@ -150,13 +150,65 @@ size_t ids_lds_bytes(int threads, int lmax, int wmax, int class_cap, int pair_ca
 bool ids_table_capped(int lmax, int class_cap);
 int ids_blocks_per_cu(const WideCfg &c);
 
+// Work distribution of the persistent walks.  The items [0, total) are cut
+// into kParts equal parts, each with its own counter on its own cache line, so
+// that the grabs spread over kParts addresses instead of queueing on one (a
+// device-wide atomic on a single address completes only some tens of millions
+// of times a second).  A workgroup starts on part blockIdx.x % kParts --
+// workgroups are dealt to the XCDs in turn, so one part's neighbouring sites
+// stay in one XCD's L2 -- and moves on to the next part when its own is used
+// up; it is done once it has found every part empty.  Thread 0 alone holds a
+// queue and calls it; the counters are zeroed before the launch.
+constexpr int kParts = 8;
+constexpr int kCtrStride = 32;                   // u64 words from one counter to the next
+constexpr int kQueueWords = kParts * kCtrStride;
+
+struct WorkQueue {
+    unsigned long long *ctr;
+    int64_t total;
+    unsigned long long chunk;
+    int part, left;
+    unsigned long long pend;   // offset taken in `part`, not yet handed out
+
+    __device__ int64_t bound(int x) const { return total * x / kParts; }
+    __device__ void init(unsigned long long *c, int64_t t, int ch) {
+        ctr = c;
+        total = t;
+        chunk = (unsigned long long)ch;
+        part = (int)(blockIdx.x % kParts);
+        left = kParts;
+        pend = atomicAdd(ctr + part * kCtrStride, chunk);
+    }
+    // The grab issued last as the chunk [lo, hi); lo == hi == total once every
+    // part is used up.
+    __device__ void resolve(int64_t &lo, int64_t &hi) {
+        for (;;) {
+            const int64_t a = bound(part), b = bound(part + 1);
+            const int64_t s = a + (int64_t)pend;
+            if (s < b) {
+                lo = s;
+                hi = s + (int64_t)chunk < b ? s + (int64_t)chunk : b;
+                return;
+            }
+            if (--left == 0) {
+                lo = hi = total;
+                return;
+            }
+            part = part + 1 == kParts ? 0 : part + 1;
+            pend = atomicAdd(ctr + part * kCtrStride, chunk);
+        }
+    }
+    // The next grab in the current part, in flight while a chunk is walked.
+    __device__ void prefetch() { pend = atomicAdd(ctr + part * kCtrStride, chunk); }
+};
+
 // Arguments of one launch of the class-id batch walk.
 struct IdsArgs {
     const Region *regs;
     int32_t nreg;
     int64_t total;               // items (ignored with a list)
     int64_t stride;              // > 1: sample in blocks of 256 items
-    unsigned long long *counter; // work counter, zeroed before the launch
+    unsigned long long *counter; // kQueueWords work-queue counters, zeroed before the launch
     int chunk;
     int lmax;                    // largest haplotype list of the regions
     int kcls;                    // class-table capacity, 0 = full
@@ -172,6 +224,7 @@ hipError_t launch_fill_regions(const Region *host, int n, Region *dev, hipStream
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 // Persistent walks over total_items items; with stride > 1 item v stands for
 // item 256 * stride * (v / 256) + v % 256 (a sample in blocks of 256).
+// counter: kQueueWords work-queue counters, zeroed before the launch.
 hipError_t launch_wide_walk(const Region *regs, int32_t nreg, int64_t total_items,
                             int64_t stride, unsigned long long *counter, const WideCfg &c,
                             hipStream_t s);

@@ -46,6 +46,15 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int i) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// A value every lane holds alike, marked wave-uniform for the compiler (so that
+// addresses built from it stay in scalar registers and loads through them are
+// scalar loads).
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ double readlane_f64(double v, int i) {
     return __builtin_bit_cast(double, readlane64(__builtin_bit_cast(uint64_t, v), i));
 }
@@ -361,9 +370,14 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
                 const uint64_t bz = __ballot(keepz);
                 const uint64_t bo = __ballot(keepo);
                 const int nz = __popcll(bz), no = __popcll(bo);
+                // one wave owns the counters outright; several share them
                 int basei = 0;
-                if (lane == 0 && nz + no > 0) basei = atomicAdd(kn, nz + no);
-                basei = __shfl(basei, 0, 64);
+                if (wpg == 1) {
+                    basei = kn[0];
+                } else {
+                    if (lane == 0 && nz + no > 0) basei = atomicAdd(kn, nz + no);
+                    basei = __shfl(basei, 0, 64);
+                }
                 const int idz = basei + (int)lanes_below(bz);
                 const int ido = basei + nz + (int)lanes_below(bo);
                 const bool fits = basei + nz + no <= kmax;   // wave-uniform
@@ -379,11 +393,20 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
                 if (MODE == MODE_POOLED) s2 = wave_sum(s2);
                 if (can_pair) s3 = wave_sum(s3);
                 if (lane == 0) {
-                    if (s0) atomicAdd(&sa[0], s0);
-                    if (s1) atomicAdd(&sa[1], s1);
-                    if (MODE == MODE_POOLED && s2) atomicAdd(&sa[2], s2);
-                    if (s3) atomicAdd(&sa[3], s3);
+                    if (wpg == 1) {
+                        kn[0] = basei + nz + no;
+                        sa[0] += s0;
+                        sa[1] += s1;
+                        if (MODE == MODE_POOLED) sa[2] += s2;
+                        sa[3] += s3;
+                    } else {
+                        if (s0) atomicAdd(&sa[0], s0);
+                        if (s1) atomicAdd(&sa[1], s1);
+                        if (MODE == MODE_POOLED && s2) atomicAdd(&sa[2], s2);
+                        if (s3) atomicAdd(&sa[3], s3);
+                    }
                 }
+                if (wpg == 1) __syncthreads();   // kn[0] is read again next round
             }
             __syncthreads();
             if (*ovf) goto overflowed;   // the walk is redone with full tables
@@ -679,35 +702,41 @@ overflowed:
     if (tid == 0) redo[atomicAdd(redo_count, 1)] = item;
 }
 
-// Persistent grid over the batch's items (region, site, direction).
-// With stride > 1 the items walked are a sample for the autotuner: blocks of
+// Persistent grid over the batch's items (region, site, direction), taken a
+// chunk at a time from the partitioned work queue.  With stride > 1 the items walked are a sample for the autotuner: blocks of
 // 256 consecutive items, one block in every `stride`.  With a list, the items
 // are those listed (count on the device): the walks a launch with a capped
 // class table could not finish.
 template <int R>
 __global__ void __launch_bounds__(1024) ids_batch_kernel(IdsArgs a) {
     extern __shared__ uint64_t lds_ids[];
-    __shared__ unsigned long long grab[2];
+    __shared__ int64_t rng[2];   // the chunk being walked
     char *base = (char *)lds_ids;
     const BLay Ly = batch_layout(a.lmax, a.kcls, a.pcap, a.kcap, a.copies);
     const int64_t total = a.list ? (int64_t)*a.list_count : a.total;
     // the region of the last item (items of one region are consecutive)
     int g_idx = 0;
     int64_t g_lo = 0, g_hi = -1;
-    if (threadIdx.x == 0) grab[0] = atomicAdd(a.counter, (unsigned long long)a.chunk);
+    WorkQueue q;   // thread 0's
+    if (threadIdx.x == 0) {
+        q.init(a.counter, total, a.chunk);
+        int64_t lo, hi;
+        q.resolve(lo, hi);
+        rng[0] = lo;
+        rng[1] = hi;
+    }
     __syncthreads();
-    int gb = 0;
     for (;;) {
-        const int64_t b0 = (int64_t)grab[gb];
-        if (b0 >= total) break;
-        // the next grab is in flight while this chunk is walked
-        unsigned long long nxt = 0ull;
-        if (threadIdx.x == 0) nxt = atomicAdd(a.counter, (unsigned long long)a.chunk);
-        const int64_t b1 = b0 + a.chunk < total ? b0 + a.chunk : total;
+        const int64_t b0 = uniform64(rng[0]), b1 = uniform64(rng[1]);
+        if (b0 >= b1) break;
+        __syncthreads();   // everyone has read the chunk before it is replaced
+        if (threadIdx.x == 0) q.prefetch();
         for (int64_t iv = b0; iv < b1; ++iv) {
-            const int64_t it = a.list ? a.list[iv]
-                                      : (a.stride > 1 ? (((iv >> 8) * a.stride) << 8) + (iv & 255)
-                                                      : iv);
+            // the item, and with it the region and everything read through
+            // it, is the same in every lane
+            const int64_t it = uniform64(
+                a.list ? a.list[iv]
+                       : (a.stride > 1 ? (((iv >> 8) * a.stride) << 8) + (iv & 255) : iv));
             if (it < g_lo || it >= g_hi) {
                 int lo = 0, hi = a.nreg - 1;   // last region with item0 <= it
                 while (lo < hi) {
@@ -715,9 +744,9 @@ __global__ void __launch_bounds__(1024) ids_batch_kernel(IdsArgs a) {
                     if (a.regs[mid].item0 <= it) lo = mid;
                     else hi = mid - 1;
                 }
-                g_idx = lo;
-                g_lo = a.regs[lo].item0;
-                g_hi = lo + 1 < a.nreg ? a.regs[lo + 1].item0 : INT64_MAX;
+                g_idx = __builtin_amdgcn_readfirstlane(lo);
+                g_lo = uniform64(a.regs[g_idx].item0);
+                g_hi = g_idx + 1 < a.nreg ? uniform64(a.regs[g_idx + 1].item0) : INT64_MAX;
             }
             const Region *G = a.regs + g_idx;
             const int64_t loc = it - g_lo;
@@ -732,9 +761,13 @@ __global__ void __launch_bounds__(1024) ids_batch_kernel(IdsArgs a) {
                                          a.redo_count);
             __syncthreads();
         }
-        if (threadIdx.x == 0) grab[gb ^ 1] = nxt;
-        __syncthreads();   // the next chunk is visible; grab[gb] is no longer read
-        gb ^= 1;
+        if (threadIdx.x == 0) {
+            int64_t lo, hi;
+            q.resolve(lo, hi);
+            rng[0] = lo;
+            rng[1] = hi;
+        }
+        __syncthreads();   // the next chunk is visible
     }
 }
 

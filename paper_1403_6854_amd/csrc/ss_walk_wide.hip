@@ -45,6 +45,13 @@ __device__ __forceinline__ uint32_t choose2(uint32_t x) { return (x * (x - 1u)) 
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return __ockl_wfred_add_u32(v); }
 
+// A value every lane holds alike, marked wave-uniform for the compiler.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int i) {
     const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, i);
     const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), i);
@@ -670,8 +677,8 @@ __device__ void wide_walk_one(const Region &R, int64_t j, int d, int core, char 
 }
 
 // Persistent grid: every workgroup takes `chunk` consecutive items at a time
-// from the counter until the batch is exhausted; every workgroup leaves the
-// loop once the counter has passed the last item.
+// from the partitioned work queue and leaves the loop once it has found every
+// part of the queue used up.
 template <int T>
 __global__ void __launch_bounds__(T) wide_walk_kernel(const Region *__restrict__ regs, int32_t nreg,
                                                       int64_t total, int64_t stride,
@@ -679,16 +686,23 @@ __global__ void __launch_bounds__(T) wide_walk_kernel(const Region *__restrict__
                                                       int chunk, int lmax, int wmax, int pcap,
                                                       int kcap) {
     extern __shared__ uint64_t lds_wide[];
-    __shared__ unsigned long long grab;
+    __shared__ int64_t rng[2];   // the chunk being walked
     char *base = (char *)lds_wide;
     const Lay Ly = wide_layout(T, lmax, wmax, pcap, kcap);
+    WorkQueue q;   // thread 0's
+    if (threadIdx.x == 0) {
+        q.init(counter, total, chunk);
+        int64_t lo, hi;
+        q.resolve(lo, hi);
+        rng[0] = lo;
+        rng[1] = hi;
+    }
+    __syncthreads();
     for (;;) {
-        __syncthreads();   // everyone has read the previous grab
-        if (threadIdx.x == 0) grab = atomicAdd(counter, (unsigned long long)chunk);
-        __syncthreads();
-        const int64_t b0 = (int64_t)grab;
-        if (b0 >= total) break;
-        const int64_t b1 = b0 + chunk < total ? b0 + chunk : total;
+        const int64_t b0 = uniform64(rng[0]), b1 = uniform64(rng[1]);
+        if (b0 >= b1) break;
+        __syncthreads();   // everyone has read the chunk before it is replaced
+        if (threadIdx.x == 0) q.prefetch();
         for (int64_t iv = b0; iv < b1; ++iv) {
             // stride > 1: a sample, blocks of 256 items, one in every `stride`
             const int64_t it = stride > 1 ? (((iv >> 8) * stride) << 8) + (iv & 255) : iv;
@@ -698,7 +712,8 @@ __global__ void __launch_bounds__(T) wide_walk_kernel(const Region *__restrict__
                 if (regs[mid].item0 <= it) lo = mid;
                 else hi = mid - 1;
             }
-            const Region R = regs[lo];
+            // the same region in every lane: its fields are scalar loads
+            const Region R = regs[__builtin_amdgcn_readfirstlane(lo)];
             const int64_t loc = it - R.item0;
             int64_t j;
             int d, core;
@@ -716,6 +731,13 @@ __global__ void __launch_bounds__(T) wide_walk_kernel(const Region *__restrict__
             wide_walk_one<T>(R, j, d, core, base, Ly, pcap, kcap);
             __syncthreads();
         }
+        if (threadIdx.x == 0) {
+            int64_t lo, hi;
+            q.resolve(lo, hi);
+            rng[0] = lo;
+            rng[1] = hi;
+        }
+        __syncthreads();   // the next chunk is visible
     }
 }
 
