@@ -293,6 +293,116 @@ __global__ void __launch_bounds__(kBlock) standardize_kernel(int64_t M,
     z[j] = out;
 }
 
+// Regions of up to kFusedMaxSites sites with kFusedMinBins to kFusedMaxBins
+// bins: one workgroup per bin reads the region's sites three times -- count
+// and sum of the bin's OK scores, their squared deviations from the mean, then
+// the bin's z-scores -- so the five launches of the tiled path above become
+// one.  (With fewer bins too few workgroups share the work, and the tiled path
+// is faster.)  Each thread accumulates its sites in site order and the block
+// combines the threads in a fixed tree, so the results repeat exactly from run
+// to run.
+constexpr int kFusedBlock = 1024;
+constexpr int64_t kFusedMaxSites = (int64_t)1 << 16;
+constexpr int32_t kFusedMinBins = 8, kFusedMaxBins = 256;
+
+__device__ __forceinline__ double block_sum_f64(double v, double *red) {
+    v = wave_sum_f64(v);
+    __syncthreads();   // red is no longer read by an earlier sum
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kFusedBlock / 64; ++w) t += red[w];
+    return t;
+}
+
+// Eight sites per thread per round, their loads issued together.
+constexpr int kFusedUnroll = 8;
+
+__global__ void __launch_bounds__(kFusedBlock) bin_fused_kernel(int64_t M,
+                                                                const double *__restrict__ u,
+                                                                int8_t *__restrict__ status,
+                                                                const int32_t *__restrict__ bin,
+                                                                double *__restrict__ binstat,
+                                                                double *__restrict__ z) {
+    __shared__ double red[kFusedBlock / 64];
+    const int b = (int)blockIdx.x;
+    // OK scores of bin b among the round's sites of this thread (site order)
+    auto load = [&](int64_t j0, bool (&in)[kFusedUnroll], double (&uu)[kFusedUnroll]) {
+#pragma unroll
+        for (int q = 0; q < kFusedUnroll; ++q) {
+            const int64_t j = j0 + (int64_t)q * kFusedBlock;
+            const bool inr = j < M;
+            const int32_t bj = inr ? (bin ? bin[j] : 0) : -1;
+            const int8_t st = inr ? status[j] : (int8_t)ST_MAF;
+            uu[q] = inr ? u[j] : 0.0;
+            in[q] = bj == b && st == ST_OK;
+        }
+    };
+    constexpr int64_t kRound = (int64_t)kFusedUnroll * kFusedBlock;
+    double c = 0.0, sum = 0.0;
+    for (int64_t j0 = threadIdx.x; j0 < M; j0 += kRound) {
+        bool in[kFusedUnroll];
+        double uu[kFusedUnroll];
+        load(j0, in, uu);
+#pragma unroll
+        for (int q = 0; q < kFusedUnroll; ++q) {
+            if (in[q]) {
+                c += 1.0;
+                sum += uu[q];
+            }
+        }
+    }
+    const double N = block_sum_f64(c, red);
+    const double S = block_sum_f64(sum, red);
+    const double mean = N > 0.0 ? S / N : __builtin_nan("");
+    double sq = 0.0;
+    for (int64_t j0 = threadIdx.x; j0 < M; j0 += kRound) {
+        bool in[kFusedUnroll];
+        double uu[kFusedUnroll];
+        load(j0, in, uu);
+#pragma unroll
+        for (int q = 0; q < kFusedUnroll; ++q) {
+            if (in[q]) {
+                const double dlt = uu[q] - mean;
+                sq += dlt * dlt;
+            }
+        }
+    }
+    const double Q = block_sum_f64(sq, red);
+    const double sd = N > 1.0 ? sqrt(Q / (N - 1.0)) : __builtin_nan("");
+    if (threadIdx.x == 0) {
+        binstat[3 * b + 0] = N;
+        binstat[3 * b + 1] = mean;
+        binstat[3 * b + 2] = sd;
+    }
+    const bool good = N >= 2.0 && sd > 0.0;
+    for (int64_t j0 = threadIdx.x; j0 < M; j0 += kRound) {
+        int32_t bj[kFusedUnroll];
+        int8_t st[kFusedUnroll];
+        double uu[kFusedUnroll];
+#pragma unroll
+        for (int q = 0; q < kFusedUnroll; ++q) {
+            const int64_t j = j0 + (int64_t)q * kFusedBlock;
+            const bool inr = j < M;
+            bj[q] = inr ? (bin ? bin[j] : 0) : -1;
+            st[q] = inr ? status[j] : (int8_t)ST_MAF;
+            uu[q] = inr ? u[j] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kFusedUnroll; ++q) {
+            if (bj[q] != b) continue;
+            const int64_t j = j0 + (int64_t)q * kFusedBlock;
+            double out = __builtin_nan("");
+            if (st[q] == ST_OK) {
+                if (good) out = (uu[q] - mean) / sd;
+                else status[j] = ST_BIN;
+            }
+            z[j] = out;
+        }
+    }
+}
+
 // ss_ehh epilogue: EHH curves from the traced integer sums (S_c at x0 is
 // C(n_c, 2), the denominator of Eq. 3), iHH = downstream + upstream, status.
 __global__ void ehh_finish_kernel(int64_t n, int64_t cap, const uint64_t *__restrict__ S,
@@ -398,6 +508,11 @@ int64_t standardize_scratch_doubles(int64_t M, int32_t nbins) {
 hipError_t launch_standardize(int64_t M, const double *unstd, int8_t *status, const int32_t *bin,
                               int32_t nbins, double *binstat, double *scratch, double *z,
                               hipStream_t s) {
+    if (M <= kFusedMaxSites && nbins >= kFusedMinBins && nbins <= kFusedMaxBins) {
+        hipLaunchKernelGGL(bin_fused_kernel, dim3((unsigned)nbins), dim3(kFusedBlock), 0, s, M, unstd,
+                           status, bin, binstat, z);
+        return hipGetLastError();
+    }
     const int64_t ntiles = (M + kTile - 1) / kTile;
     double *first = scratch;
     double *second = scratch + 2 * ntiles * (int64_t)nbins;
