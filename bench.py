@@ -229,7 +229,7 @@ def bench_served(ss, torch, dev, args):
     s1.update({"batches": srv.batches, "mean_batch": round(float(np.mean(srv.batch_sizes)), 2),
                "peak_admitted_GB": round(srv.peak_bytes / 2**30, 2),
                "streams": args.serve_streams, "budget_GB": args.serve_budget_gb,
-               "config": dataclasses.asdict(cfg)})
+               "config": dataclasses.asdict(cfg), "group_tuning": ss.group_tuning()})
     del done
     torch.cuda.empty_cache()
 

@@ -258,15 +258,32 @@ typedef struct ss_batch_config {
 } ss_batch_config;
 
 int ss_get_batch_config(ss_batch_config *c);
-/* Errors: SS_EARG for a field out of range. */
+/* Errors: SS_EARG for a field out of range.  Also drops the per-group
+ * settings the autotuner found (ss_get_group_tuning). */
 int ss_set_batch_config(const ss_batch_config *c);
+
+/*
+ * ss_get_group_tuning -- the settings ss_autotune_batch refined for single
+ * launch groups of kernel 0 (a group: the regions of one workgroup size, with
+ * or without pair buffers).  They replace the process-wide counter_copies,
+ * class_cap, chunk and blocks_per_cu for launches of that group, in batches
+ * and in single scans taken by the persistent walk.  rows: host int32 array
+ * of 6 * max_rows, filled with {threads, pair buffers (0/1), counter_copies,
+ * class_cap, chunk, blocks_per_cu} per group; *n_rows: the number of groups
+ * with refined settings (may exceed max_rows; the rest are not written).
+ * Host only.  Errors: SS_EARG for a null n_rows, or null rows with
+ * max_rows > 0.
+ */
+int ss_get_group_tuning(int32_t *rows, int32_t max_rows, int32_t *n_rows);
 
 /*
  * ss_autotune_batch -- time candidate configurations of the persistent walk on
  * these requests (the walks of about sample_items work items per launch group,
  * spread evenly over its sites, or all if sample_items <= 0), keep the fastest
- * as the process-wide configuration and
- * return it with its time.  Blocks until the timings are done; the outputs of
+ * as the process-wide configuration and return it with its time.  With several
+ * launch groups it then refines counter_copies, class_cap, chunk and
+ * blocks_per_cu for each group on its own (kept if the whole batch is then at
+ * least as fast; see ss_get_group_tuning).  Blocks until the timings are done; the outputs of
  * the requests are left undefined (run ss_scan_batch afterwards).
  * Errors: as ss_scan_batch.
  */

@@ -106,9 +106,12 @@ def lib():
                                         ctypes.POINTER(ctypes.c_double)]
         L.ss_set_graph.argtypes = [ctypes.c_int]
         L.ss_graph_clear.argtypes = []
+        L.ss_get_group_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32)]
         for f in ("ss_pack", "ss_ehh", "ss_ihs", "ss_xpehh", "ss_set_walk_kernel", "ss_set_mask_lanes",
                   "ss_timing_enable", "ss_timing_read", "ss_scan_batch", "ss_get_batch_config",
-                  "ss_set_batch_config", "ss_autotune_batch", "ss_set_graph", "ss_graph_clear"):
+                  "ss_set_batch_config", "ss_autotune_batch", "ss_set_graph", "ss_graph_clear",
+                  "ss_get_group_tuning"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -451,6 +454,17 @@ def set_batch_config(cfg: BatchConfig):
                      int(cfg.small_pair_cap), int(cfg.slots), int(cfg.class_cap),
                      int(cfg.counter_copies))
     _check(lib().ss_set_batch_config(ctypes.byref(c)))
+
+
+def group_tuning() -> list:
+    """Settings the autotuner refined per launch group: a list of dicts
+    {threads, pairs, counter_copies, class_cap, chunk, blocks_per_cu}."""
+    n = ctypes.c_int32(0)
+    _check(lib().ss_get_group_tuning(None, 0, ctypes.byref(n)))
+    rows = (ctypes.c_int32 * (6 * max(1, n.value)))()
+    _check(lib().ss_get_group_tuning(rows, n.value, ctypes.byref(n)))
+    keys = ("threads", "pairs", "counter_copies", "class_cap", "chunk", "blocks_per_cu")
+    return [dict(zip(keys, rows[6 * i: 6 * i + 6])) for i in range(n.value)]
 
 
 def autotune_batch(reqs, params: Optional[Params] = None, stream=None,

@@ -269,14 +269,40 @@ bool tail_possible(int mode, int32_t nA, int32_t nB, double maf, double cutoff, 
     return cutoff * 0.5 * (double)m * (double)(m - 1) <= (double)pcap;
 }
 
-// The configuration one launch runs with: the group's workgroup size, and no
-// pair buffers for scans that cannot reach the pairwise tail.
+// Settings the autotuner refined for one launch group of the class-id walk,
+// keyed by workgroup size and pair buffers.  Only settings that leave the
+// grouping of the regions unchanged are refined per group.
+struct GroupTune {
+    int32_t set;
+    int32_t counter_copies, class_cap, chunk, blocks_per_cu;
+};
+constexpr int kTuneSizes = 1024 / 64 + 1;
+GroupTune g_gtune[kTuneSizes][2];
+
+void clear_group_tuning() {
+    for (auto &row : g_gtune)
+        for (auto &t : row) t = GroupTune{};
+}
+
+// The configuration one launch runs with: the group's workgroup size, no pair
+// buffers for scans that cannot reach the pairwise tail, and the group's
+// refined settings if the autotuner found any.
 ss_batch_config launch_config(const ss_batch_config &bc, int threads, bool pairs) {
     ss_batch_config c = bc;
     c.threads = threads;
-    if (!pairs && bc.kernel == 0) {
+    if (bc.kernel != 0) return c;
+    if (!pairs) {
         c.pair_cap = 0;
         c.small_pair_cap = 0;
+    }
+    if (threads > 0 && threads % 64 == 0 && threads / 64 < kTuneSizes) {
+        const GroupTune &t = g_gtune[threads / 64][pairs ? 1 : 0];
+        if (t.set) {
+            c.counter_copies = t.counter_copies;
+            c.class_cap = t.class_cap;
+            c.chunk = t.chunk;
+            c.blocks_per_cu = t.blocks_per_cu;
+        }
     }
     return c;
 }
@@ -546,9 +572,11 @@ int walk_scan(Scan &sc, hipStream_t s) {
         const int lmax = list_len(r.nA, r.nB, sc.mode), wmax = row_words(r.nA, r.nB, sc.mode);
         if (!make_wide_cfg(g_bcfg, lmax, wmax, c))
             return fail(SS_EDEV, "persistent walk does not fit this device");
-        if (c.kernel == 0 && !tail_possible(sc.mode, r.nA, r.nB, sc.maf, r.cutoff, c.pair_cap) &&
-            !make_wide_cfg(launch_config(g_bcfg, g_bcfg.threads, false), lmax, wmax, c))
-            return fail(SS_EDEV, "persistent walk does not fit this device");
+        if (c.kernel == 0) {   // as the region's launch group in a batch would run
+            const bool pairs = tail_possible(sc.mode, r.nA, r.nB, sc.maf, r.cutoff, c.pair_cap);
+            if (!make_wide_cfg(launch_config(g_bcfg, c.threads, pairs), lmax, wmax, c))
+                return fail(SS_EDEV, "persistent walk does not fit this device");
+        }
         SS_HIP(ss::launch_fill_regions(&r, 1, sc.w.region, s));
         SS_HIP(ss::launch_zero_u64(sc.w.counter, kGroupCtrWords, s));
         TimedRegion t(s);
@@ -728,13 +756,19 @@ int build_batch(const ss_scan_request *reqs, int32_t n, const ss_params *p, void
 
 // The persistent walks over the batch's regions, one launch per group;
 // sample_stride > 1 walks only every sample_stride-th item of each group.
-int launch_batch_wide(Batch &B, const ss_batch_config &bc, int64_t sample_stride, hipStream_t s) {
+// only >= 0: that group alone (the autotuner's per-group timing).
+int launch_batch_wide(Batch &B, const ss_batch_config &bc, int64_t sample_stride, hipStream_t s,
+                      int only = -1) {
     if (B.wide.empty()) return SS_OK;
     SS_HIP(ss::launch_fill_regions(B.regions.data(), (int)B.regions.size(), B.d_regions, s));
     SS_HIP(ss::launch_zero_u64(B.d_counter, kGroupCtrWords * kMaxGroups, s));
     int64_t redo_off = 0;
     for (size_t gi = 0; gi < B.groups.size(); ++gi) {
         const Group &g = B.groups[gi];
+        if (only >= 0 && (int)gi != only) {
+            redo_off += g.total_items;
+            continue;
+        }
         ss::WideCfg c;
         if (!make_wide_cfg(launch_config(bc, g.threads, g.pairs), g.lmax, g.wmax, c))
             return fail(SS_EDEV, "persistent walk configuration does not fit this device");
@@ -792,6 +826,7 @@ std::string graph_key(const ss_scan_request *reqs, int32_t n, const ss_params *p
     put(k, ws_bytes);
     put(k, stream);
     put(k, g_bcfg);
+    put(k, g_gtune);
     put(k, g_walk_kind);
     put(k, g_mask_lpc);
     return k;
@@ -977,6 +1012,31 @@ int ss_set_batch_config(const ss_batch_config *c) {
     if (!c) return fail(SS_EARG, "config is null");
     SS_TRY(check_batch_config(*c));
     g_bcfg = *c;
+    clear_group_tuning();
+    return SS_OK;
+}
+
+int ss_get_group_tuning(int32_t *rows, int32_t max_rows, int32_t *n_rows) {
+    if (!n_rows) return fail(SS_EARG, "n_rows is null");
+    if (max_rows < 0 || (max_rows > 0 && !rows)) return fail(SS_EARG, "rows is null");
+    int32_t n = 0;
+    for (int t = 0; t < kTuneSizes; ++t) {
+        for (int pr = 0; pr < 2; ++pr) {
+            const GroupTune &g = g_gtune[t][pr];
+            if (!g.set) continue;
+            if (n < max_rows) {
+                int32_t *r = rows + 6 * n;
+                r[0] = 64 * t;
+                r[1] = pr;
+                r[2] = g.counter_copies;
+                r[3] = g.class_cap;
+                r[4] = g.chunk;
+                r[5] = g.blocks_per_cu;
+            }
+            ++n;
+        }
+    }
+    *n_rows = n;
     return SS_OK;
 }
 
@@ -988,6 +1048,7 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
     SS_TRY(build_batch(reqs, n_reqs, p, d_ws, ws_bytes, B));
     hipStream_t s = (hipStream_t)stream;
     for (auto &sc : B.scans) SS_TRY(prepare_scan(sc, p, s));
+    clear_group_tuning();
     ss_batch_config cur = g_bcfg;
     if (cur.kernel == 0) cur.threads = 64;
     double cur_ms = 0.0;
@@ -1107,6 +1168,55 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
                     if (ms < cur_ms) { cur = c; cur_ms = ms; }
                 }
             }
+        }
+        // then each launch group on its own: the settings that leave the
+        // grouping unchanged, one at a time, starting from the batch's
+        if (cur.kernel == 0 && B.groups.size() > 1) {
+            number_items(B, cur);
+            for (size_t gi = 0; gi < B.groups.size(); ++gi) {
+                const Group &g = B.groups[gi];
+                if (g.threads % 64 || g.threads / 64 >= kTuneSizes) continue;
+                GroupTune &slot = g_gtune[g.threads / 64][g.pairs ? 1 : 0];
+                auto time_group = [&](const GroupTune &t, double &ms) -> int {
+                    slot = t;
+                    ss::WideCfg wc;
+                    if (!make_wide_cfg(launch_config(cur, g.threads, g.pairs), g.lmax, g.wmax, wc)) {
+                        ms = 1e30;
+                        return SS_OK;
+                    }
+                    double bestv = 1e30;
+                    for (int rep = 0; rep < 2; ++rep) {
+                        SS_HIP(hipEventRecord(e0, s));
+                        SS_TRY(launch_batch_wide(B, cur, stride, s, (int)gi));
+                        SS_HIP(hipEventRecord(e1, s));
+                        SS_HIP(hipEventSynchronize(e1));
+                        float f = 0.f;
+                        SS_HIP(hipEventElapsedTime(&f, e0, e1));
+                        bestv = std::min(bestv, (double)f);
+                    }
+                    ms = bestv;
+                    return SS_OK;
+                };
+                GroupTune bt{1, cur.counter_copies, cur.class_cap, cur.chunk, cur.blocks_per_cu};
+                double bms;
+                SS_TRY(time_group(bt, bms));
+                auto try_t = [&](GroupTune t) -> int {
+                    double ms;
+                    SS_TRY(time_group(t, ms));
+                    if (ms < bms) { bt = t; bms = ms; }
+                    return SS_OK;
+                };
+                for (int cp : {1, 8}) { GroupTune t = bt; t.counter_copies = cp; SS_TRY(try_t(t)); }
+                for (int cc : {0, 512, 1024, 2048}) { GroupTune t = bt; t.class_cap = cc; SS_TRY(try_t(t)); }
+                for (int ch : {1, 2, 4, 8}) { GroupTune t = bt; t.chunk = ch; SS_TRY(try_t(t)); }
+                for (int bpc : {0, 2, 3, 4}) { GroupTune t = bt; t.blocks_per_cu = bpc; SS_TRY(try_t(t)); }
+                slot = bt;
+            }
+            // kept if the whole batch runs at least as fast with them
+            double with_ms;
+            SS_TRY(time_cfg(cur, with_ms));
+            if (with_ms <= cur_ms) cur_ms = with_ms;
+            else clear_group_tuning();
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);

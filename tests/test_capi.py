@@ -177,6 +177,17 @@ def test_batch_config_round_trip_and_range_checks(lib):
         ss.set_batch_config(base)
 
 
+def test_group_tuning_is_host_only_and_cleared_by_set_config(lib):
+    import ctypes
+    import paper_1403_6854_amd as ss
+    ss.set_batch_config(ss.get_batch_config())
+    assert ss.group_tuning() == []
+    n = ctypes.c_int32(-1)
+    assert lib.ss_get_group_tuning(None, 0, ctypes.byref(n)) == 0 and n.value == 0
+    assert lib.ss_get_group_tuning(None, 0, None) == ss.SS_EARG
+    assert lib.ss_get_group_tuning(None, 3, ctypes.byref(n)) == ss.SS_EARG
+
+
 def test_walk_kernel_choices(lib):
     import paper_1403_6854_amd as ss
     for k in (0, 1, 2, 3):

@@ -170,11 +170,24 @@ def test_autotune_then_parity(ss, regions):
         assert cfg.kernel in (0, 1) and cfg.small_kernel == 0
         assert cfg.threads in ((64, 128, 256, 512, 1024) if cfg.kernel == 0 else (128, 256, 512))
         assert ss.get_batch_config() == cfg
+        tuned = ss.group_tuning()
+        say("group tuning %s" % tuned)
+        for t in tuned:
+            assert t["threads"] % 64 == 0 and 64 <= t["threads"] <= 1024 and t["pairs"] in (0, 1)
+            assert t["counter_copies"] in (0, 1, 8) and t["chunk"] >= 1
+            assert t["class_cap"] in (0, 512, 1024, 2048) and 0 <= t["blocks_per_cu"] <= 4
         ss.scan_batch(reqs, ws=ws)
         got = [_np(r.out) for r in reqs]
+        # single scans by the persistent walk take the groups' settings too
+        one = [_np(ss.ihs(ha, steps=True) if kind == "ihs" else ss.xpehh(ha, hb, steps=True))
+               for kind, ha, hb, _ in regions]
     finally:
         ss.set_batch_config(ss.BatchConfig())
+    assert ss.group_tuning() == []
     _check_all(got, regions, "tuned")
+    for g, o in zip(got, one):
+        for k in o:
+            np.testing.assert_array_equal(g[k], o[k], err_msg=k)
 
 
 def _standardize_numpy(u, status, bins, nbins):
