@@ -28,9 +28,9 @@
 //     the markers have been refined, and added to iHH one by one in marker
 //     order, so the sums round exactly as the definition's left-to-right sum;
 //   * pairwise phase (iHS walks): sum_h C(n_h, 2) counts the pairs of
-//     haplotypes still identical from x0 to x_i.  Once that count S is at most
-//     kPairCap, the classes are expanded into an explicit list of those pairs
-//     in LDS, and each pass then covers 64 markers: a pair's 64-bit keys
+//     haplotypes still identical from x0 to x_i.  Once that count S is at
+//     most the pair capacity, the classes are expanded into an explicit list
+//     of those pairs in LDS, and each pass then covers 64 markers: a pair's 64-bit keys
 //     (its haplotypes' alleles at the next 64 markers, read from a
 //     haplotype-major copy of the matrix) are XORed, the lowest set bit is
 //     the marker where the pair splits, a 64-bin histogram of those markers
@@ -66,9 +66,19 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t v) {
     return v;
 }
 
-// Pairs the pairwise phase keeps in LDS (4 KB; LDS per wave bounds how
-// many walks a CU keeps in flight).
-constexpr int kPairCap = 1024;
+// Pairs the pairwise phase keeps in LDS, by mask width.  The list is where a
+// walk switches from per-marker refinement to 64-marker passes over pairs,
+// and its buffer shares LDS with the class records of the per-marker phase;
+// LDS per wave bounds how many walks a CU keeps in flight.  Measured (walk ms,
+// copying-model regions of 20,000 sites, 204 x 22,147 for W = 4) over
+// capacities 128 / 256 / 384 / 512 / 1,024:
+//   W = 2 (100 haplotypes): 0.63 / 0.46 / 0.36 / 0.34 / --
+//   W = 4 (204 haplotypes): 0.35 / 0.34 / 0.35 / 0.36 / 0.47 (25 waves per CU
+//                           at 1,024 against 32 below it)
+//   W = 8 (400 haplotypes): 1.87 / 1.63 / 1.49 / 1.39 / 1.19
+__host__ __device__ constexpr int mask_pair_cap(int W) {
+    return W >= 8 ? 1024 : (W == 4 ? 256 : 512);
+}
 
 // Inclusive prefix sum over the 64 lanes (once per 64-marker pass).
 __device__ __forceinline__ uint32_t wave_prefix(uint32_t v, int lane) {
@@ -100,7 +110,7 @@ template <int MODE, int W, int LPC, int NR>
 __global__ void __launch_bounds__(64) mask_walk_kernel(WalkArgs a) {
     constexpr int WPL = W / LPC;    // words per lane
     constexpr int CPR = 64 / LPC;   // classes per row
-    constexpr int PCAP = MODE == MODE_CORE ? kPairCap : 0;
+    constexpr int PCAP = MODE == MODE_CORE ? mask_pair_cap(W) : 0;
     extern __shared__ uint64_t lds64[];
     // LDS regions; the pairwise phase stages no rows and compacts no classes,
     // so its buffers share space with those of the per-marker phase.
@@ -698,7 +708,7 @@ MaskShape mask_walk_shape(int32_t nA, int32_t nB, int mode, int lpc) {
     (void)kmax;
     sh.rows = 1;
     if (sh.rows > 16) return MaskShape{};
-    sh.pair_cap = mode == MODE_CORE ? kPairCap : 0;
+    sh.pair_cap = mode == MODE_CORE ? mask_pair_cap(sh.words) : 0;
     const size_t stage_words = (size_t)sh.rows * cpr * (sh.words + 1);
     const size_t union_words = stage_words > (size_t)sh.pair_cap / 2 ? stage_words
                                                                       : (size_t)sh.pair_cap / 2;
