@@ -66,15 +66,15 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t v) {
     return v;
 }
 
-// Pairs the pairwise phase keeps in LDS, by mask width.  The list is where a
-// walk switches from per-marker refinement to 64-marker passes over pairs,
-// and its buffer shares LDS with the class records of the per-marker phase;
-// LDS per wave bounds how many walks a CU keeps in flight.  Measured (walk ms,
+// Pairs the pairwise phase keeps in LDS, by mask width.  The capacity is
+// where a walk switches from per-marker refinement to 64-marker passes over
+// its pair list, and a pass costs in proportion to the pairs: at 4 words a
+// pass over up to 1,024 pairs costs more than the per-marker steps it
+// replaces while there are that many.  Measured (walk ms,
 // copying-model regions of 20,000 sites, 204 x 22,147 for W = 4) over
 // capacities 128 / 256 / 384 / 512 / 1,024:
 //   W = 2 (100 haplotypes): 0.63 / 0.46 / 0.36 / 0.34 / --
-//   W = 4 (204 haplotypes): 0.35 / 0.34 / 0.35 / 0.36 / 0.47 (25 waves per CU
-//                           at 1,024 against 32 below it)
+//   W = 4 (204 haplotypes): 0.35 / 0.34 / 0.35 / 0.36 / 0.47
 //   W = 8 (400 haplotypes): 1.87 / 1.63 / 1.49 / 1.39 / 1.19
 __host__ __device__ constexpr int mask_pair_cap(int W) {
     return W >= 8 ? 1024 : (W == 4 ? 256 : 512);
@@ -104,10 +104,18 @@ __device__ __forceinline__ uint32_t stop_threshold(uint32_t P, double cutoff, in
     return (uint32_t)__builtin_amdgcn_readlane((uint32_t)s, top);
 }
 
+// Waves per SIMD the compiler is held to: 4-word iHS walks (129-256
+// haplotypes) take 86 VGPRs unbounded (5 waves per SIMD); bounded to 7 they
+// take 72 with a few bytes of spills and the 204-haplotype walk runs 0.316
+// instead of 0.337 ms.  Wider masks spill heavily under a bound, and the
+// pooled walks were not measured bounded: they keep the default.
+template <int MODE, int W>
+constexpr int mask_waves_per_eu() { return MODE == MODE_CORE && W == 4 ? 7 : 1; }
+
 // W: mask words per class (pooled: A's words, then B's); LPC: lanes per
 // class; NR: rows of 64 / LPC classes (capacity NR * 64 / LPC classes).
 template <int MODE, int W, int LPC, int NR>
-__global__ void __launch_bounds__(64) mask_walk_kernel(WalkArgs a) {
+__global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_kernel(WalkArgs a) {
     constexpr int WPL = W / LPC;    // words per lane
     constexpr int CPR = 64 / LPC;   // classes per row
     constexpr int PCAP = MODE == MODE_CORE ? mask_pair_cap(W) : 0;
