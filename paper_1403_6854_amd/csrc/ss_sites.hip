@@ -15,22 +15,39 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Bit-pack 0/1 bytes: one wave per (site, 64-haplotype word); lane l reads
-// haplotype 64w + l (64 consecutive bytes) and a ballot forms the word
-// (Sec. 1.1 encoding: bit set = derived allele).
+// Bit-pack 0/1 bytes (Sec. 1.1 encoding: bit set = derived allele).  A wave
+// packs kPackItems consecutive (site, 64-haplotype word) items at a time:
+// lane l reads haplotype 64w + l of each (64 consecutive bytes per item), the
+// loads of all items in flight together; a ballot per item forms its word,
+// and lanes 0 .. kPackItems-1 store the words with one coalesced store.
+constexpr int kPackItems = 8;
+
 __global__ void __launch_bounds__(kBlock) pack_kernel(const uint8_t *__restrict__ alleles,
                                                       int64_t n, int64_t M, int64_t wps,
                                                       uint64_t *__restrict__ bits) {
     const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); item < M * wps;
-         item += stride) {
-        const int64_t site = item / wps;
-        const int64_t w = item - site * wps;
-        const int64_t h = w * 64 + lane;
-        const bool one = h < n && alleles[site * n + h] != 0;
-        const uint64_t word = __ballot(one);
-        if (lane == 0) bits[item] = word;
+    const int64_t total = M * wps;
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / 64) * kPackItems;
+    for (int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * kPackItems;
+         base < total; base += stride) {
+        int64_t site = base / wps, w = base - site * wps;
+        bool one[kPackItems];
+#pragma unroll
+        for (int q = 0; q < kPackItems; ++q) {
+            const int64_t h = w * 64 + lane;
+            one[q] = base + q < total && h < n && alleles[site * n + h] != 0;
+            if (++w == wps) {
+                w = 0;
+                ++site;
+            }
+        }
+        uint64_t mine = 0;
+#pragma unroll
+        for (int q = 0; q < kPackItems; ++q) {
+            const uint64_t word = __ballot(one[q]);
+            if (lane == q) mine = word;
+        }
+        if (lane < kPackItems && base + lane < total) bits[base + lane] = mine;
     }
 }
 
@@ -458,7 +475,7 @@ static int64_t wave_blocks(int64_t items) {
 
 hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps,
                        uint64_t *bits, hipStream_t s) {
-    const int64_t blocks = wave_blocks(M * wps);
+    const int64_t blocks = wave_blocks((M * wps + kPackItems - 1) / kPackItems);
     hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, alleles, n, M,
                        wps, bits);
     return hipGetLastError();

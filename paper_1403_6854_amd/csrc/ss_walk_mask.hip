@@ -105,10 +105,10 @@ __device__ __forceinline__ uint32_t stop_threshold(uint32_t P, double cutoff, in
 }
 
 // Waves per SIMD the compiler is held to: 4-word iHS walks (129-256
-// haplotypes) take 86 VGPRs unbounded (5 waves per SIMD); bounded to 7 they
-// take 72 with a few bytes of spills and the 204-haplotype walk runs 0.316
-// instead of 0.337 ms.  Wider masks spill heavily under a bound, and the
-// pooled walks were not measured bounded: they keep the default.
+// haplotypes) take 72 VGPRs bounded to 7 waves per SIMD, without spills (5
+// waves unbounded); the 204-haplotype walk runs 0.306 ms against 0.337 ms
+// unbounded.  Wider masks spill heavily under a bound, and the pooled walks
+// were not measured bounded: they keep the default.
 template <int MODE, int W>
 constexpr int mask_waves_per_eu() { return MODE == MODE_CORE && W == 4 ? 7 : 1; }
 
@@ -402,18 +402,14 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
         int nterm = 0;              // trapezoid terms of this batch
         int i = 0;
         bool to_pairs = false;
-        uint64_t rn[WPL];
-#pragma unroll
-        for (int t = 0; t < WPL; ++t) rn[t] = rowbuf[g * WPL + t];
         for (; i < 64 && act; ++i) {
             if (i == nb) { status = abort_st; break; }
+            // the marker's row words, read from LDS where they are used: a
+            // copy of the next marker's words held in registers cost more
+            // (spills at 4 words, fewer waves at 8) than the LDS latency
             uint64_t rw[WPL];
 #pragma unroll
-            for (int t = 0; t < WPL; ++t) rw[t] = rn[t];
-            if (i + 1 < 64) {
-#pragma unroll
-                for (int t = 0; t < WPL; ++t) rn[t] = rowbuf[(i + 1) * W + g * WPL + t];
-            }
+            for (int t = 0; t < WPL; ++t) rw[t] = rowbuf[i * W + g * WPL + t];
 
             uint32_t acc = 0, accB = 0, accP = 0;
             bool split[NR];

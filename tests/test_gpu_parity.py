@@ -365,3 +365,19 @@ def test_xpehh_self_is_zero(ss, walk):
     assert m.sum() > 10000
     assert np.all(got["unstd"][m] == 0.0)
     np.testing.assert_array_equal(got["ihhA"][m], got["ihhB"][m])
+
+
+@pytest.mark.parametrize("n,m", [(1, 3), (63, 17), (64, 9), (65, 130), (204, 1001), (1000, 77)])
+def test_pack_matches_numpy(n, m):
+    """ss_pack against its definition: bit l of word w of site s is set when
+    haplotype 64 w + l carries the derived allele (any nonzero byte)."""
+    import torch
+    import paper_1403_6854_amd as ss
+    rng = np.random.default_rng(n * 1000 + m)
+    a = rng.integers(0, 2, size=(m, n), dtype=np.uint8) * rng.integers(1, 4, size=(m, n), dtype=np.uint8)
+    got = ss.pack(torch.from_numpy(a).cuda()).cpu().numpy().view(np.uint64)
+    W = (n + 63) // 64
+    want = np.zeros((m, W), dtype=np.uint64)
+    for h in range(n):
+        want[:, h // 64] |= (a[:, h] != 0).astype(np.uint64) << np.uint64(h % 64)
+    np.testing.assert_array_equal(got, want)
