@@ -273,3 +273,32 @@ def test_walks_that_outgrow_a_capped_class_table_are_redone(ss, cap):
         np.testing.assert_array_equal(got[0][k], full[k], err_msg=k)
     # the i.i.d. walks really do pass 64 classes
     assert ref_d["steps"].max() >= 7
+
+
+@pytest.mark.parametrize("chunk", [1, 3])
+def test_tiny_regions_leave_work_queue_parts_empty(ss, chunk):
+    """Regions of 1 to 5 sites give launch groups of fewer items than the work
+    queue has parts (some parts are empty from the start); every walk still
+    runs once: results equal the oracle's and the single calls'."""
+    specs = [("ihs", 600, 0, 1, 11), ("ihs", 700, 0, 2, 12), ("xpehh", 300, 400, 3, 13),
+             ("ihs", 900, 0, 5, 14), ("xpehh", 520, 30, 4, 15)]
+    regs = []
+    for kind, na, nb, m, seed in specs:
+        a, b = _data(kind, na, nb, m, seed)
+        ha = _hm(ss, a.alleles, a.pos_bp, a.gpos_cm)
+        hb = _hm(ss, b.alleles, a.pos_bp, a.gpos_cm) if b is not None else None
+        ref = (oracle.ihs(a.alleles, a.pos_bp, a.gpos_cm) if b is None
+               else oracle.xpehh(a.alleles, b.alleles, a.pos_bp, a.gpos_cm))
+        regs.append((kind, ha, hb, ref))
+    say("tiny regions, chunk %d" % chunk)
+    ss.set_batch_config(ss.BatchConfig(small_kernel=0, chunk=chunk))
+    try:
+        _, got = _run_batch(ss, regs)
+        one = [_np(ss.ihs(ha, steps=True) if kind == "ihs" else ss.xpehh(ha, hb, steps=True))
+               for kind, ha, hb, _ in regs]
+    finally:
+        ss.set_batch_config(ss.BatchConfig())
+    _check_all(got, regs, "tiny")
+    for g, o in zip(got, one):
+        for k in o:
+            np.testing.assert_array_equal(g[k], o[k], err_msg=k)
