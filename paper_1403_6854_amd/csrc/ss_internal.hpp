@@ -121,7 +121,7 @@ struct WideCfg {
     int threads;     // workgroup size: 64 .. 1024 (kernel 0); 128, 256 or 512 (kernel 1)
     int pair_cap;    // pairs held by the pairwise phase
     int key_cap;     // haplotypes whose 64-marker keys the pairwise phase holds
-    int chunk;       // items taken per grab of the work counter
+    int chunk;       // items taken per grab of the work queue
     int blocks;      // workgroups of the persistent grid
     int lmax;        // largest haplotype list of the batch (iHS: n, XPEHH: nA + nB)
     int class_cap;   // kernel 0: class-table capacity (0 = full)

@@ -1,5 +1,5 @@
 // EHH walks of a batch of regions in one persistent launch: class ids per
-// haplotype, a pairwise tail for long walks, and a device work counter.
+// haplotype, a pairwise tail for long walks, and a device work queue.
 //
 // What it computes is the partition refinement of ss_walk.hip (Sec. 1.1,
 // Eqs. 1-3; Sec. 1.2, Eq. 4 and the rules below it; Sec. 1.3, Eq. 7 for the

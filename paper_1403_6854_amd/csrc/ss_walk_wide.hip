@@ -7,8 +7,9 @@
 // pooled XPEHH walk), walk by walk, with the same FP64 arithmetic in the same
 // order.  The work items of a batch are (region, site, direction, core) for
 // iHS regions and (region, site, direction) for XPEHH regions; a grid sized to
-// fill the GPU takes them from one global counter, so walks of very uneven
-// length and regions of different haplotype counts share one launch.
+// fill the GPU takes them from the partitioned work queue (WorkQueue), so
+// walks of very uneven length and regions of different haplotype counts share
+// one launch.
 //
 // One workgroup walks one item:
 //   * the walk's haplotypes are a list in LDS in which every class is a
