@@ -266,15 +266,25 @@ int ss_set_batch_config(const ss_batch_config *c);
  * ss_get_group_tuning -- the settings ss_autotune_batch refined for single
  * launch groups of kernel 0 (a group: the regions of one workgroup size, with
  * or without pair buffers).  They replace the process-wide counter_copies,
- * class_cap, chunk and blocks_per_cu for launches of that group, in batches
- * and in single scans taken by the persistent walk.  rows: host int32 array
- * of 6 * max_rows, filled with {threads, pair buffers (0/1), counter_copies,
- * class_cap, chunk, blocks_per_cu} per group; *n_rows: the number of groups
- * with refined settings (may exceed max_rows; the rest are not written).
- * Host only.  Errors: SS_EARG for a null n_rows, or null rows with
- * max_rows > 0.
+ * class_cap, chunk and blocks_per_cu for launches of that group, or (plain =
+ * 1) walk the group's regions with the plain per-locus class-id kernel
+ * instead, in batches and in single scans taken by the persistent walk.
+ * rows: host int32 array of 7 * max_rows, filled with {threads, pair buffers
+ * (0/1), counter_copies, class_cap, chunk, blocks_per_cu, plain (0/1)} per
+ * group; *n_rows: the number of groups with refined settings (may exceed
+ * max_rows; the rest are not written).  Host only.
+ * Errors: SS_EARG for a null n_rows, or null rows with max_rows > 0.
  */
 int ss_get_group_tuning(int32_t *rows, int32_t max_rows, int32_t *n_rows);
+
+/*
+ * ss_set_group_tuning -- replace the per-group settings by n_rows rows of
+ * the layout ss_get_group_tuning fills (host int32, 7 * n_rows; n_rows = 0
+ * drops them all).  The plain kernel is used for a group only where every
+ * region's class table fits in LDS.  Host only.  Errors: SS_EARG for a null
+ * rows with n_rows > 0 or a field out of range (nothing is changed then).
+ */
+int ss_set_group_tuning(const int32_t *rows, int32_t n_rows);
 
 /*
  * ss_autotune_batch -- time candidate configurations of the persistent walk on

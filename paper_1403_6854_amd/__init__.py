@@ -106,12 +106,13 @@ def lib():
                                         ctypes.POINTER(ctypes.c_double)]
         L.ss_set_graph.argtypes = [ctypes.c_int]
         L.ss_graph_clear.argtypes = []
+        L.ss_set_group_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
         L.ss_get_group_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32)]
         for f in ("ss_pack", "ss_ehh", "ss_ihs", "ss_xpehh", "ss_set_walk_kernel", "ss_set_mask_lanes",
                   "ss_timing_enable", "ss_timing_read", "ss_scan_batch", "ss_get_batch_config",
                   "ss_set_batch_config", "ss_autotune_batch", "ss_set_graph", "ss_graph_clear",
-                  "ss_get_group_tuning"):
+                  "ss_get_group_tuning", "ss_set_group_tuning"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -458,13 +459,23 @@ def set_batch_config(cfg: BatchConfig):
 
 def group_tuning() -> list:
     """Settings the autotuner refined per launch group: a list of dicts
-    {threads, pairs, counter_copies, class_cap, chunk, blocks_per_cu}."""
+    {threads, pairs, counter_copies, class_cap, chunk, blocks_per_cu, plain}."""
     n = ctypes.c_int32(0)
     _check(lib().ss_get_group_tuning(None, 0, ctypes.byref(n)))
-    rows = (ctypes.c_int32 * (6 * max(1, n.value)))()
+    rows = (ctypes.c_int32 * (7 * max(1, n.value)))()
     _check(lib().ss_get_group_tuning(rows, n.value, ctypes.byref(n)))
-    keys = ("threads", "pairs", "counter_copies", "class_cap", "chunk", "blocks_per_cu")
-    return [dict(zip(keys, rows[6 * i: 6 * i + 6])) for i in range(n.value)]
+    return [dict(zip(_TUNE_KEYS, rows[7 * i: 7 * i + 7])) for i in range(n.value)]
+
+
+_TUNE_KEYS = ("threads", "pairs", "counter_copies", "class_cap", "chunk", "blocks_per_cu", "plain")
+
+
+def set_group_tuning(rows: list):
+    """Replace the per-launch-group settings (dicts with the keys group_tuning
+    returns; an empty list drops them)."""
+    flat = [int(r[k]) for r in rows for k in _TUNE_KEYS]
+    arr = (ctypes.c_int32 * max(1, len(flat)))(*flat)
+    _check(lib().ss_set_group_tuning(arr, len(rows)))
 
 
 def autotune_batch(reqs, params: Optional[Params] = None, stream=None,

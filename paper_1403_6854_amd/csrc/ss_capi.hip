@@ -275,8 +275,10 @@ bool tail_possible(int mode, int32_t nA, int32_t nB, double maf, double cutoff, 
 struct GroupTune {
     int32_t set;
     int32_t counter_copies, class_cap, chunk, blocks_per_cu;
+    int32_t plain;   // 1: the group's regions are walked by the plain per-locus kernel
 };
 constexpr int kTuneSizes = 1024 / 64 + 1;
+constexpr int kTuneCols = 7;   // a row of ss_get/set_group_tuning
 GroupTune g_gtune[kTuneSizes][2];
 
 void clear_group_tuning() {
@@ -574,6 +576,14 @@ int walk_scan(Scan &sc, hipStream_t s) {
             return fail(SS_EDEV, "persistent walk does not fit this device");
         if (c.kernel == 0) {   // as the region's launch group in a batch would run
             const bool pairs = tail_possible(sc.mode, r.nA, r.nB, sc.maf, r.cutoff, c.pair_cap);
+            const GroupTune &gt = g_gtune[c.threads / 64][pairs ? 1 : 0];
+            const ss::WalkShape ws = ss::walk_shape(r.nA, r.nB, sc.mode);
+            if (gt.set && gt.plain && ws.threads <= 1024 && ws.lds <= (size_t)max_lds_per_block()) {
+                TimedRegion t(s);
+                SS_TRY(t.begin());
+                SS_HIP(ss::launch_walk(sc.args, sc.mode, false, sc.args.M, s));
+                return t.end();
+            }
             if (!make_wide_cfg(launch_config(g_bcfg, c.threads, pairs), lmax, wmax, c))
                 return fail(SS_EDEV, "persistent walk does not fit this device");
         }
@@ -606,10 +616,22 @@ struct Group {
 
 constexpr int kMaxGroups = 32;
 
+struct Batch;
+bool plain_fits(const Batch &B, const Group &g);
+
+// The group is walked by the plain per-locus class-id kernel (the autotuner
+// found it faster for this group, and its class tables fit in LDS).
+bool group_plain(const ss_batch_config &bc, const Batch &B, const Group &g) {
+    if (bc.kernel != 0 || g.threads % 64 || g.threads / 64 >= kTuneSizes) return false;
+    const GroupTune &t = g_gtune[g.threads / 64][g.pairs ? 1 : 0];
+    return t.set && t.plain && plain_fits(B, g);
+}
+
 struct Batch {
     std::vector<Scan> scans;
     std::vector<int> wide;            // scans walked by the persistent kernel
     std::vector<ss::Region> regions;  // their descriptors, group by group (item0 per group)
+    std::vector<int> region_scan;     // the scan of each of them
     std::vector<Group> groups;
     ss::Region *d_regions = nullptr;
     unsigned long long *d_counter = nullptr;   // kGroupCtrWords per group
@@ -617,6 +639,15 @@ struct Batch {
     int64_t total_items = 0;
     int lmax = 0, wmax = 0;
 };
+
+bool plain_fits(const Batch &B, const Group &g) {
+    for (int q = g.first; q < g.first + g.count; ++q) {
+        const Scan &sc = B.scans[B.region_scan[q]];
+        const ss::WalkShape sh = ss::walk_shape(sc.args.nA, sc.args.nB, sc.mode);
+        if (sh.threads > 1024 || sh.lds > (size_t)max_lds_per_block()) return false;
+    }
+    return true;
+}
 
 struct BatchLayout {
     std::vector<size_t> offs;
@@ -685,6 +716,7 @@ void number_items(Batch &B, const ss_batch_config &bc) {
         return false;
     });
     B.regions.clear();
+    B.region_scan.clear();
     B.groups.clear();
     B.total_items = 0;
     int64_t item = 0;
@@ -710,6 +742,7 @@ void number_items(Batch &B, const ss_batch_config &bc) {
         g.wmax = std::max(g.wmax, row_words(sc.args.nA, sc.args.nB, sc.mode));
         B.total_items += n_items;
         B.regions.push_back(r);
+        B.region_scan.push_back(B.wide[k.idx]);
     }
 }
 
@@ -769,10 +802,21 @@ int launch_batch_wide(Batch &B, const ss_batch_config &bc, int64_t sample_stride
             redo_off += g.total_items;
             continue;
         }
+        const int64_t stride = sample_stride > 1 ? sample_stride : 1;
+        if (group_plain(bc, B, g)) {
+            // the plain per-locus kernel, region by region (a sample: the
+            // first 1 / stride of each region's sites)
+            for (int q = g.first; q < g.first + g.count; ++q) {
+                const Scan &sc = B.scans[B.region_scan[q]];
+                const int64_t sites = stride > 1 ? (sc.args.M + stride - 1) / stride : sc.args.M;
+                SS_HIP(ss::launch_walk(sc.args, sc.mode, false, sites, s));
+            }
+            redo_off += g.total_items;
+            continue;
+        }
         ss::WideCfg c;
         if (!make_wide_cfg(launch_config(bc, g.threads, g.pairs), g.lmax, g.wmax, c))
             return fail(SS_EDEV, "persistent walk configuration does not fit this device");
-        const int64_t stride = sample_stride > 1 ? sample_stride : 1;
         int64_t total = g.total_items;
         if (stride > 1) {   // blocks of 256 items, one in every `stride`
             const int64_t blocks = (g.total_items + 255) / 256;
@@ -1016,6 +1060,24 @@ int ss_set_batch_config(const ss_batch_config *c) {
     return SS_OK;
 }
 
+int ss_set_group_tuning(const int32_t *rows, int32_t n_rows) {
+    if (n_rows < 0 || (n_rows > 0 && !rows)) return fail(SS_EARG, "rows is null");
+    for (int32_t i = 0; i < n_rows; ++i) {
+        const int32_t *r = rows + kTuneCols * i;
+        const bool ok = r[0] >= 64 && r[0] <= 1024 && r[0] % 64 == 0 && (r[1] == 0 || r[1] == 1) &&
+                        (r[2] == 0 || r[2] == 1 || r[2] == 8) &&
+                        (r[3] == 0 || (r[3] >= 64 && r[3] <= 16386)) && r[4] >= 1 && r[4] <= 4096 &&
+                        r[5] >= 0 && r[5] <= 64 && (r[6] == 0 || r[6] == 1);
+        if (!ok) return fail(SS_EARG, "group tuning row " + std::to_string(i) + " out of range");
+    }
+    clear_group_tuning();
+    for (int32_t i = 0; i < n_rows; ++i) {
+        const int32_t *r = rows + kTuneCols * i;
+        g_gtune[r[0] / 64][r[1]] = GroupTune{1, r[2], r[3], r[4], r[5], r[6]};
+    }
+    return SS_OK;
+}
+
 int ss_get_group_tuning(int32_t *rows, int32_t max_rows, int32_t *n_rows) {
     if (!n_rows) return fail(SS_EARG, "n_rows is null");
     if (max_rows < 0 || (max_rows > 0 && !rows)) return fail(SS_EARG, "rows is null");
@@ -1025,13 +1087,14 @@ int ss_get_group_tuning(int32_t *rows, int32_t max_rows, int32_t *n_rows) {
             const GroupTune &g = g_gtune[t][pr];
             if (!g.set) continue;
             if (n < max_rows) {
-                int32_t *r = rows + 6 * n;
+                int32_t *r = rows + kTuneCols * n;
                 r[0] = 64 * t;
                 r[1] = pr;
                 r[2] = g.counter_copies;
                 r[3] = g.class_cap;
                 r[4] = g.chunk;
                 r[5] = g.blocks_per_cu;
+                r[6] = g.plain;
             }
             ++n;
         }
@@ -1180,7 +1243,9 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
                 auto time_group = [&](const GroupTune &t, double &ms) -> int {
                     slot = t;
                     ss::WideCfg wc;
-                    if (!make_wide_cfg(launch_config(cur, g.threads, g.pairs), g.lmax, g.wmax, wc)) {
+                    if (t.plain ? !plain_fits(B, g)
+                                : !make_wide_cfg(launch_config(cur, g.threads, g.pairs), g.lmax,
+                                                 g.wmax, wc)) {
                         ms = 1e30;
                         return SS_OK;
                     }
@@ -1210,6 +1275,11 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
                 for (int cc : {0, 512, 1024, 2048}) { GroupTune t = bt; t.class_cap = cc; SS_TRY(try_t(t)); }
                 for (int ch : {1, 2, 4, 8}) { GroupTune t = bt; t.chunk = ch; SS_TRY(try_t(t)); }
                 for (int bpc : {0, 2, 3, 4}) { GroupTune t = bt; t.blocks_per_cu = bpc; SS_TRY(try_t(t)); }
+                {   // or the plain per-locus kernel for this group's regions
+                    GroupTune t = bt;
+                    t.plain = 1;
+                    SS_TRY(try_t(t));
+                }
                 slot = bt;
             }
             // kept if the whole batch runs at least as fast with them

@@ -188,6 +188,28 @@ def test_group_tuning_is_host_only_and_cleared_by_set_config(lib):
     assert lib.ss_get_group_tuning(None, 3, ctypes.byref(n)) == ss.SS_EARG
 
 
+def test_group_tuning_round_trip_and_range_checks(lib):
+    import paper_1403_6854_amd as ss
+    rows = [dict(threads=64, pairs=1, counter_copies=1, class_cap=512, chunk=2, blocks_per_cu=0, plain=0),
+            dict(threads=320, pairs=0, counter_copies=8, class_cap=0, chunk=1, blocks_per_cu=3, plain=1)]
+    try:
+        ss.set_group_tuning(rows)
+        assert ss.group_tuning() == rows
+        for bad in (dict(threads=96), dict(threads=2048), dict(pairs=2), dict(counter_copies=4),
+                    dict(class_cap=10), dict(chunk=0), dict(blocks_per_cu=-1), dict(plain=2)):
+            with pytest.raises(ss.SelscanError) as e:
+                ss.set_group_tuning([dict(rows[0], **bad)])
+            assert e.value.code == ss.SS_EARG
+            assert ss.group_tuning() == rows          # nothing changed
+        ss.set_group_tuning([])
+        assert ss.group_tuning() == []
+        ss.set_group_tuning(rows)
+        ss.set_batch_config(ss.get_batch_config())
+        assert ss.group_tuning() == []
+    finally:
+        ss.set_group_tuning([])
+
+
 def test_walk_kernel_choices(lib):
     import paper_1403_6854_amd as ss
     for k in (0, 1, 2, 3):

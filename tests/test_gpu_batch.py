@@ -176,6 +176,7 @@ def test_autotune_then_parity(ss, regions):
             assert t["threads"] % 64 == 0 and 64 <= t["threads"] <= 1024 and t["pairs"] in (0, 1)
             assert t["counter_copies"] in (0, 1, 8) and t["chunk"] >= 1
             assert t["class_cap"] in (0, 512, 1024, 2048) and 0 <= t["blocks_per_cu"] <= 4
+            assert t["plain"] in (0, 1)
         ss.scan_batch(reqs, ws=ws)
         got = [_np(r.out) for r in reqs]
         # single scans by the persistent walk take the groups' settings too
@@ -302,3 +303,26 @@ def test_tiny_regions_leave_work_queue_parts_empty(ss, chunk):
     for g, o in zip(got, one):
         for k in o:
             np.testing.assert_array_equal(g[k], o[k], err_msg=k)
+
+
+@pytest.mark.parametrize("which", ["all", "no_pairs"])
+def test_groups_walked_by_the_plain_kernel(ss, regions, which):
+    """Launch groups set to the plain per-locus kernel give the results of the
+    persistent walk, in batches and in single scans."""
+    say("plain groups: %s" % which)
+    rows = [dict(threads=t, pairs=p, counter_copies=0, class_cap=1024, chunk=1, blocks_per_cu=0, plain=1)
+            for t in range(64, 1025, 64) for p in (0, 1) if which == "all" or p == 0]
+    ss.set_batch_config(ss.BatchConfig(small_kernel=0))
+    try:
+        _, base = _run_batch(ss, regions)
+        ss.set_group_tuning(rows)
+        _, got = _run_batch(ss, regions)
+        one = [_np(ss.ihs(ha, steps=True) if kind == "ihs" else ss.xpehh(ha, hb, steps=True))
+               for kind, ha, hb, _ in regions]
+    finally:
+        ss.set_batch_config(ss.BatchConfig())
+    _check_all(got, regions, "plain groups")
+    for b, g, o in zip(base, got, one):
+        for k in b:
+            np.testing.assert_array_equal(g[k], b[k], err_msg=k)
+            np.testing.assert_array_equal(o[k], b[k], err_msg=k)
