@@ -268,7 +268,7 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
-    ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default persistent-walk configuration (profiling runs)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
