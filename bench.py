@@ -188,7 +188,9 @@ def bench_served(ss, torch, dev, args):
     def reqs_of(sp):
         return [serve.ServeRequest(s.rid, s.arrival_s, s.kind,
                                    serve.request_bytes(s.kind, s.n_a, s.n_b, s.n_sites),
-                                   make(s), s.n_sites) for s in sp]
+                                   make(s), s.n_sites,
+                                   serve.request_work(s.kind, s.n_a, s.n_b, s.n_sites))
+                for s in sp]
 
     def loci_of(done, sp):
         kinds = {s.rid: s for s in sp}
@@ -221,7 +223,8 @@ def bench_served(ss, torch, dev, args):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     log("served: %d requests, continuous batching" % len(specs))
-    srv = serve.Server(serve.TorchBackend(args.serve_streams), budget, max_batch=64)
+    srv = serve.Server(serve.TorchBackend(args.serve_streams), budget, max_batch=64,
+                       work_ratio=args.serve_work_ratio)
     done = srv.run(reqs_of(specs))
     torch.cuda.synchronize()
     s1 = serve.summarize(done)
@@ -229,6 +232,7 @@ def bench_served(ss, torch, dev, args):
     s1.update({"batches": srv.batches, "mean_batch": round(float(np.mean(srv.batch_sizes)), 2),
                "peak_admitted_GB": round(srv.peak_bytes / 2**30, 2),
                "streams": args.serve_streams, "budget_GB": args.serve_budget_gb,
+               "work_ratio": args.serve_work_ratio,
                "config": dataclasses.asdict(cfg), "group_tuning": ss.group_tuning()})
     del done
     torch.cuda.empty_cache()
@@ -269,6 +273,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
     ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-work-ratio", type=float, default=0.0,
+                    help="close a served batch at a request whose estimated work differs "
+                         "from the batch's first by more than this factor (0: off)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default persistent-walk configuration (profiling runs)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,

@@ -39,6 +39,7 @@ class ServeRequest:
     nbytes: int                  # device memory held while admitted
     make: Callable               # () -> (HapMat a, HapMat b or None), enqueued on the current stream
     n_sites: int = 0
+    work: float = 0.0            # estimated walk work (request_work); 0 = unknown
 
 
 @dataclasses.dataclass
@@ -71,6 +72,13 @@ def request_bytes(kind: str, n_a: int, n_b: int, n_sites: int, steps: bool = Fal
     per_site = 16 + 1 + 4 + 32 + 16 + 16 + 8 + 8 + 8 + 8   # positions, flags, bins, walk records, segments, redo
     outputs = m * (5 * 8 + 1 + (16 if steps else 0))
     return alleles + bits + hapmajor + per_site * m + outputs + (1 << 16)
+
+
+def request_work(kind: str, n_a: int, n_b: int, n_sites: int) -> float:
+    """Estimated walk work of a request: sites times haplotypes walked (a
+    proxy for the marker steps of its walks times the haplotypes each
+    refines)."""
+    return float(n_sites) * float(n_a + (n_b if kind == "xpehh" else 0))
 
 
 class TorchBackend:
@@ -124,13 +132,23 @@ class Server:
     ``backend`` provides slots() (free streams), launch(list) -> handle,
     done(handle) -> bool and retire(handle) -> per-request outputs; ``clock``
     and ``sleep`` are injectable so the policy can be exercised off the GPU.
+
+    ``work_ratio`` > 0 closes a batch at the first waiting request whose
+    estimated work differs from the batch's first request's by more than
+    that factor (first come, first served is kept: that request opens the
+    next batch), so that small requests do not wait for the longest walk of
+    a large one in the same batch.
     """
 
     def __init__(self, backend, budget_bytes: int, max_batch: int = 64,
                  clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep, poll_s: float = 1e-4):
+                 sleep: Callable[[float], None] = time.sleep, poll_s: float = 1e-4,
+                 work_ratio: float = 0.0):
         if budget_bytes <= 0 or max_batch < 1:
             raise ValueError("budget_bytes and max_batch must be positive")
+        if work_ratio < 0.0 or (0.0 < work_ratio < 1.0):
+            raise ValueError("work_ratio must be 0 or at least 1")
+        self.work_ratio = float(work_ratio)
         self.backend = backend
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
@@ -140,6 +158,12 @@ class Server:
         self.peak_bytes = 0
         self.batches = 0
         self.batch_sizes: List[int] = []
+
+    def _apart(self, first: ServeRequest, r: ServeRequest) -> bool:
+        if self.work_ratio <= 0.0 or first.work <= 0.0 or r.work <= 0.0:
+            return False
+        q = r.work / first.work
+        return q > self.work_ratio or q * self.work_ratio < 1.0
 
     def run(self, requests: List[ServeRequest]) -> List[Completion]:
         reqs = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
@@ -169,6 +193,8 @@ class Server:
                 batch, nbytes = [], 0
                 while pending and len(batch) < self.max_batch:
                     r = pending[0]
+                    if batch and self._apart(batch[0], r):
+                        break
                     if used + nbytes + r.nbytes > self.budget:
                         # a request larger than the whole budget runs alone
                         if not (r.nbytes > self.budget and not batch and not inflight):

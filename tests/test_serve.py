@@ -60,10 +60,12 @@ def _reqs(n, rate=100.0, nbytes=10, seed=0):
     return out
 
 
-def _run(reqs, budget=10**9, max_batch=64, n_streams=2, cost=lambda b: 0.01 * len(b)):
+def _run(reqs, budget=10**9, max_batch=64, n_streams=2, cost=lambda b: 0.01 * len(b),
+         work_ratio=0.0):
     clk = FakeClock()
     be = FakeBackend(clk, n_streams, cost)
-    srv = serve.Server(be, budget, max_batch=max_batch, clock=clk, sleep=clk.sleep, poll_s=1e-4)
+    srv = serve.Server(be, budget, max_batch=max_batch, clock=clk, sleep=clk.sleep, poll_s=1e-4,
+                       work_ratio=work_ratio)
     done = srv.run(reqs)
     return done, be, srv
 
@@ -144,3 +146,25 @@ def test_request_bytes_grow_with_the_region():
     d = serve.request_bytes("xpehh", 5000, 5000, 200000)
     assert a < b < c < d
     assert d > 5000 * 2 * 200000   # the 0/1 matrices alone
+
+
+def test_work_ratio_keeps_dissimilar_requests_apart_in_arrival_order():
+    rng = np.random.default_rng(5)
+    reqs = _reqs(300, rate=2000.0)
+    for r in reqs:
+        r.work = float(rng.choice([1.0, 3.0, 100.0, 400.0]))
+    done, be, srv = _run(reqs, n_streams=4, work_ratio=4.0)
+    assert sorted(c.rid for c in done) == list(range(300))
+    work = {r.rid: r.work for r in reqs}
+    order = [rid for _, rids in be.launches for rid in rids]
+    assert order == list(range(300))              # first come, first served
+    for _, rids in be.launches:
+        w = [work[i] for i in rids]
+        assert max(w) <= 4.0 * w[0] and min(w) * 4.0 >= w[0]
+    assert max(len(rids) for _, rids in be.launches) > 1   # similar ones still batch
+    # without the ratio the same stream mixes them
+    _, be0, _ = _run(reqs, n_streams=4)
+    assert any(max(work[i] for i in rids) > 4.0 * min(work[i] for i in rids)
+               for _, rids in be0.launches)
+    with pytest.raises(ValueError):
+        serve.Server(be, 10, work_ratio=0.5)
