@@ -335,7 +335,18 @@ __device__ __forceinline__ double block_sum_f64(double v, double *red) {
 
 // Eight sites per thread per round, their loads issued together.
 constexpr int kFusedUnroll = 8;
+constexpr int64_t kFusedRound = (int64_t)kFusedUnroll * kFusedBlock;
+// Regions of up to kFusedMaxRounds rounds keep their sites in registers
+// (kFusedMaxRounds * kFusedUnroll doubles per thread): the three steps then
+// read global memory once, all of its loads in flight together, instead of
+// once per step.
+constexpr int kFusedMaxRounds = 4;
+static_assert(kFusedMaxRounds * kFusedUnroll <= 32, "held sites are flagged in 32-bit masks");
 
+// R > 0: the region's sites (at most R rounds) held in registers; R = 0: each
+// step reads them again.  Both accumulate in the same order (rounds, then the
+// eight sites of a round), so they give identical results.
+template <int R>
 __global__ void __launch_bounds__(kFusedBlock) bin_fused_kernel(int64_t M,
                                                                 const double *__restrict__ u,
                                                                 int8_t *__restrict__ status,
@@ -344,6 +355,15 @@ __global__ void __launch_bounds__(kFusedBlock) bin_fused_kernel(int64_t M,
                                                                 double *__restrict__ z) {
     __shared__ double red[kFusedBlock / 64];
     const int b = (int)blockIdx.x;
+    constexpr int kHeld = R > 0 ? R * kFusedUnroll : 1;
+    double held[kHeld];
+    uint32_t inbin = 0, okbin = 0;   // R > 0: bit r * 8 + q of the held sites
+    // held slot i = r * 8 + q: site q of round r (32-bit: fused regions hold
+    // at most 2^16 sites).  Accesses add threadIdx.x to a wave-uniform base,
+    // which keeps one address register per array instead of one per slot.
+    auto held_site = [&](int i) -> uint32_t {
+        return threadIdx.x + (uint32_t)((i / kFusedUnroll) * kFusedRound + (i % kFusedUnroll) * kFusedBlock);
+    };
     // OK scores of bin b among the round's sites of this thread (site order)
     auto load = [&](int64_t j0, bool (&in)[kFusedUnroll], double (&uu)[kFusedUnroll]) {
 #pragma unroll
@@ -356,17 +376,42 @@ __global__ void __launch_bounds__(kFusedBlock) bin_fused_kernel(int64_t M,
             in[q] = bj == b && st == ST_OK;
         }
     };
-    constexpr int64_t kRound = (int64_t)kFusedUnroll * kFusedBlock;
     double c = 0.0, sum = 0.0;
-    for (int64_t j0 = threadIdx.x; j0 < M; j0 += kRound) {
-        bool in[kFusedUnroll];
-        double uu[kFusedUnroll];
-        load(j0, in, uu);
+    if (R > 0) {
+        // bins and statuses of the held sites first, then the scores of the
+        // bin's OK sites only: two loads in flight per site at a time
 #pragma unroll
-        for (int q = 0; q < kFusedUnroll; ++q) {
-            if (in[q]) {
+        for (int i = 0; i < kHeld; ++i) {
+            const uint32_t j = held_site(i), j0 = j - threadIdx.x;
+            const bool inr = j < (uint32_t)M;
+            const int32_t bj = inr ? (bin ? (bin + j0)[threadIdx.x] : 0) : -1;
+            const int8_t st = inr ? (status + j0)[threadIdx.x] : (int8_t)ST_MAF;
+            if (bj == b) inbin |= 1u << i;
+            if (bj == b && st == ST_OK) okbin |= 1u << i;
+        }
+#pragma unroll
+        for (int i = 0; i < kHeld; ++i) {
+            const double *ui = u + (held_site(i) - threadIdx.x);
+            held[i] = ((okbin >> i) & 1u) ? ui[threadIdx.x] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kHeld; ++i) {
+            if ((okbin >> i) & 1u) {
                 c += 1.0;
-                sum += uu[q];
+                sum += held[i];
+            }
+        }
+    } else {
+        for (int64_t j0 = threadIdx.x; j0 < M; j0 += kFusedRound) {
+            bool in[kFusedUnroll];
+            double uu[kFusedUnroll];
+            load(j0, in, uu);
+#pragma unroll
+            for (int q = 0; q < kFusedUnroll; ++q) {
+                if (in[q]) {
+                    c += 1.0;
+                    sum += uu[q];
+                }
             }
         }
     }
@@ -374,15 +419,25 @@ __global__ void __launch_bounds__(kFusedBlock) bin_fused_kernel(int64_t M,
     const double S = block_sum_f64(sum, red);
     const double mean = N > 0.0 ? S / N : __builtin_nan("");
     double sq = 0.0;
-    for (int64_t j0 = threadIdx.x; j0 < M; j0 += kRound) {
-        bool in[kFusedUnroll];
-        double uu[kFusedUnroll];
-        load(j0, in, uu);
+    if (R > 0) {
 #pragma unroll
-        for (int q = 0; q < kFusedUnroll; ++q) {
-            if (in[q]) {
-                const double dlt = uu[q] - mean;
+        for (int i = 0; i < kHeld; ++i) {
+            if ((okbin >> i) & 1u) {
+                const double dlt = held[i] - mean;
                 sq += dlt * dlt;
+            }
+        }
+    } else {
+        for (int64_t j0 = threadIdx.x; j0 < M; j0 += kFusedRound) {
+            bool in[kFusedUnroll];
+            double uu[kFusedUnroll];
+            load(j0, in, uu);
+#pragma unroll
+            for (int q = 0; q < kFusedUnroll; ++q) {
+                if (in[q]) {
+                    const double dlt = uu[q] - mean;
+                    sq += dlt * dlt;
+                }
             }
         }
     }
@@ -394,7 +449,21 @@ __global__ void __launch_bounds__(kFusedBlock) bin_fused_kernel(int64_t M,
         binstat[3 * b + 2] = sd;
     }
     const bool good = N >= 2.0 && sd > 0.0;
-    for (int64_t j0 = threadIdx.x; j0 < M; j0 += kRound) {
+    if (R > 0) {
+#pragma unroll
+        for (int i = 0; i < kHeld; ++i) {
+            if (!((inbin >> i) & 1u)) continue;
+            const uint32_t j0 = held_site(i) - threadIdx.x;
+            double out = __builtin_nan("");
+            if ((okbin >> i) & 1u) {
+                if (good) out = (held[i] - mean) / sd;
+                else (status + j0)[threadIdx.x] = ST_BIN;
+            }
+            (z + j0)[threadIdx.x] = out;
+        }
+        return;
+    }
+    for (int64_t j0 = threadIdx.x; j0 < M; j0 += kFusedRound) {
         int32_t bj[kFusedUnroll];
         int8_t st[kFusedUnroll];
         double uu[kFusedUnroll];
@@ -526,8 +595,15 @@ hipError_t launch_standardize(int64_t M, const double *unstd, int8_t *status, co
                               int32_t nbins, double *binstat, double *scratch, double *z,
                               hipStream_t s) {
     if (M <= kFusedMaxSites && nbins >= kFusedMinBins && nbins <= kFusedMaxBins) {
-        hipLaunchKernelGGL(bin_fused_kernel, dim3((unsigned)nbins), dim3(kFusedBlock), 0, s, M, unstd,
-                           status, bin, binstat, z);
+        const dim3 grid((unsigned)nbins), block(kFusedBlock);
+        static_assert(kFusedMaxRounds == 4, "one case per round count below");
+        switch ((M + kFusedRound - 1) / kFusedRound) {
+            case 1: hipLaunchKernelGGL(bin_fused_kernel<1>, grid, block, 0, s, M, unstd, status, bin, binstat, z); break;
+            case 2: hipLaunchKernelGGL(bin_fused_kernel<2>, grid, block, 0, s, M, unstd, status, bin, binstat, z); break;
+            case 3: hipLaunchKernelGGL(bin_fused_kernel<3>, grid, block, 0, s, M, unstd, status, bin, binstat, z); break;
+            case 4: hipLaunchKernelGGL(bin_fused_kernel<4>, grid, block, 0, s, M, unstd, status, bin, binstat, z); break;
+            default: hipLaunchKernelGGL(bin_fused_kernel<0>, grid, block, 0, s, M, unstd, status, bin, binstat, z); break;
+        }
         return hipGetLastError();
     }
     const int64_t ntiles = (M + kTile - 1) / kTile;

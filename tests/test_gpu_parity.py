@@ -381,3 +381,24 @@ def test_pack_matches_numpy(n, m):
     for h in range(n):
         want[:, h // 64] |= (a[:, h] != 0).astype(np.uint64) << np.uint64(h % 64)
     np.testing.assert_array_equal(got, want)
+
+
+# Frequency-bin standardization takes one of several launch forms by region
+# size: sites held in registers (1 to 4 rounds of 8,192), sites re-read per
+# step (up to 65,536), or the tiled form (larger regions, and XPEHH's single
+# bin); every form must agree with the oracle.
+@pytest.mark.parametrize("m", [900, 12_000, 22_147, 30_000, 40_000, 70_000])
+def test_standardization_forms(ss, m):
+    say("ss_ihs / ss_xpehh 64 (+60) x %d standardization" % m)
+    d = hapgen.copying_model(64, m, 80 * m, n_founders=12, switch_p=0.01, seed=m)
+    h = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm)
+    got = _np(ss.ihs(h, steps=True))
+    ref = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm)
+    check_ihs(got, ref, "ihs M=%d" % m)
+    assert (ref["status"] == 0).sum() > m // 4
+    e = hapgen.copying_model(60, m, 80 * m, n_founders=12, switch_p=0.01, seed=m + 1,
+                             positions=(d.pos_bp, d.gpos_cm))
+    hb = _hm(ss, e.alleles, d.pos_bp, d.gpos_cm)
+    got = _np(ss.xpehh(h, hb, steps=True))
+    ref = oracle.xpehh(d.alleles, e.alleles, d.pos_bp, d.gpos_cm)
+    check_xpehh(got, ref, "xpehh M=%d" % m)
