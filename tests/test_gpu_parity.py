@@ -384,9 +384,10 @@ def test_pack_matches_numpy(n, m):
 
 
 # Frequency-bin standardization takes one of several launch forms by region
-# size: sites held in registers (1 to 4 rounds of 8,192), sites re-read per
-# step (up to 65,536), or the tiled form (larger regions, and XPEHH's single
-# bin); every form must agree with the oracle.
+# size and bin count: one workgroup per bin with the sites held in registers
+# (1 to 4 rounds of 8,192) or re-read per step (up to 65,536 sites, 8 or more
+# bins), or tiled partial sums (fewer bins, e.g. XPEHH's single bin, or larger
+# regions); every form must agree with the oracle.
 @pytest.mark.parametrize("m", [900, 12_000, 22_147, 30_000, 40_000, 70_000])
 def test_standardization_forms(ss, m):
     say("ss_ihs / ss_xpehh 64 (+60) x %d standardization" % m)
@@ -396,6 +397,10 @@ def test_standardization_forms(ss, m):
     ref = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm)
     check_ihs(got, ref, "ihs M=%d" % m)
     assert (ref["status"] == 0).sum() > m // 4
+    wide = oracle.Params(bin_width=0.25)    # 4 bins: the tiled form
+    got = _np(ss.ihs(h, ss.Params(**vars(wide)), steps=True))
+    ref = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm, wide)
+    check_ihs(got, ref, "ihs 4 bins M=%d" % m)
     e = hapgen.copying_model(60, m, 80 * m, n_founders=12, switch_p=0.01, seed=m + 1,
                              positions=(d.pos_bp, d.gpos_cm))
     hb = _hm(ss, e.alleles, d.pos_bp, d.gpos_cm)
