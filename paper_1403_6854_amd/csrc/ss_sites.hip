@@ -311,10 +311,10 @@ __global__ void __launch_bounds__(kBlock) standardize_kernel(int64_t M,
 }
 
 // Regions of up to kFusedMaxSites sites with kFusedMinBins to kFusedMaxBins
-// bins: one workgroup per bin reads the region's sites three times -- count
-// and sum of the bin's OK scores, their squared deviations from the mean, then
-// the bin's z-scores -- so the five launches of the tiled path above become
-// one.  (With fewer bins too few workgroups share the work, and the tiled path
+// bins: one workgroup per bin takes three steps over the region's sites --
+// count and sum of the bin's OK scores, their squared deviations from the
+// mean, then the bin's z-scores -- so the five launches of the tiled path
+// above become one.  (With fewer bins too few workgroups share the work, and the tiled path
 // is faster.)  Each thread accumulates its sites in site order and the block
 // combines the threads in a fixed tree, so the results repeat exactly from run
 // to run.
@@ -338,8 +338,8 @@ constexpr int kFusedUnroll = 8;
 constexpr int64_t kFusedRound = (int64_t)kFusedUnroll * kFusedBlock;
 // Regions of up to kFusedMaxRounds rounds keep their sites in registers
 // (kFusedMaxRounds * kFusedUnroll doubles per thread): the three steps then
-// read global memory once, all of its loads in flight together, instead of
-// once per step.
+// share one read of global memory (bins and statuses, then the bin's OK
+// scores) instead of reading the sites once per step.
 constexpr int kFusedMaxRounds = 4;
 static_assert(kFusedMaxRounds * kFusedUnroll <= 32, "held sites are flagged in 32-bit masks");
 
