@@ -38,12 +38,36 @@ def flags():
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source into the shared library (always recompiles)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + flags() + ["-shared"] + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+    """Compile every HIP source into the shared library (always recompiles).
+
+    Each source launches only its own kernels, so the sources are compiled to
+    objects in parallel and then linked."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    tag = "%d" % os.getpid()
+
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + "." + tag + ".o")
+        cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("hipcc failed on %s:\n%s" % (src, res.stderr[-8000:]))
+        if verbose:
+            print(" ".join(cmd))
+        return obj
+
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", "0") or 0) or (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
+    tmp = LIB + ".tmp" + tag
+    cmd = [hipcc()] + flags() + ["-shared"] + objs + ["-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
+    for o in objs:
+        os.remove(o)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stderr[-8000:])
+        raise RuntimeError("hipcc link failed:\n" + res.stderr[-8000:])
     if verbose:
         print(" ".join(cmd))
     os.replace(tmp, LIB)

@@ -665,14 +665,10 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
 template <int MODE, int W, int LPC>
 hipError_t launch_nr(const WalkArgs &a, int nr, size_t lds, int64_t n_blocks, hipStream_t s) {
     dim3 grid((unsigned)n_blocks, 2u, MODE == MODE_CORE ? 2u : 1u);
-    switch (nr) {
-        case 1: hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 1>), grid, dim3(64), lds, s, a); break;
-        case 2: hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 2>), grid, dim3(64), lds, s, a); break;
-        case 4: hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 4>), grid, dim3(64), lds, s, a); break;
-        case 8: hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 8>), grid, dim3(64), lds, s, a); break;
-        case 16: hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 16>), grid, dim3(64), lds, s, a); break;
-        default: return hipErrorInvalidValue;
-    }
+    // one register row of classes (mask_walk_shape); walks that need more
+    // are listed for the class-id walk
+    if (nr != 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 1>), grid, dim3(64), lds, s, a);
     return hipGetLastError();
 }
 

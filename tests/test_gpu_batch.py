@@ -326,3 +326,36 @@ def test_groups_walked_by_the_plain_kernel(ss, regions, which):
         for k in b:
             np.testing.assert_array_equal(g[k], b[k], err_msg=k)
             np.testing.assert_array_equal(o[k], b[k], err_msg=k)
+
+
+BIG_POOLED_CONFIGS = [dict(), dict(class_cap=64), dict(class_cap=64, counter_copies=8),
+                      dict(counter_copies=8, pair_cap=0), dict(class_cap=512, chunk=3),
+                      dict(kernel=1, threads=512)]
+
+
+@pytest.mark.parametrize("cfg", BIG_POOLED_CONFIGS,
+                         ids=[",".join("%s=%s" % kv for kv in c.items()) or "default"
+                              for c in BIG_POOLED_CONFIGS])
+def test_batch_pooled_9000_haplotypes(ss, cfg):
+    """XPEHH regions of 5,000 + 4,000 haplotypes in one batch (workgroups of
+    the widest rows; with a capped class table, the full-table second launch,
+    whose LDS holds one counter copy) against the oracle."""
+    from tests.test_gpu_parity import pooled_pair
+    regs = []
+    for kind in ("copying", "iid"):
+        A, B, pos, gpos, params = pooled_pair(kind)
+        regs.append((_hm(ss, A, pos, gpos), _hm(ss, B, pos, gpos), params,
+                     oracle.xpehh(A, B, pos, gpos, params)))
+    say("ss_scan_batch 5000+4000 pooled, config %s" % cfg)
+    ss.set_batch_config(ss.BatchConfig(small_kernel=0, **cfg))
+    try:
+        got = []
+        for ha, hb, params, _ in regs:
+            r = ss.ScanRequest(ha, hb)
+            ss.alloc_outputs(r, steps=True)
+            ss.scan_batch([r], ss.Params(**vars(params)))
+            got.append(_np(r.out))
+    finally:
+        ss.set_batch_config(ss.BatchConfig())
+    for g, (_, _, _, ref) in zip(got, regs):
+        check_xpehh(g, ref, "batch pooled 9000 %s" % cfg)

@@ -407,3 +407,64 @@ def test_standardization_forms(ss, m):
     got = _np(ss.xpehh(h, hb, steps=True))
     ref = oracle.xpehh(d.alleles, e.alleles, d.pos_bp, d.gpos_cm)
     check_xpehh(got, ref, "xpehh M=%d" % m)
+
+
+# ---------------------------------------------------------------------------
+# The oracle's pinned constructions: which abort a locus reports when its two
+# directions abort differently, and the pooled stop at an exact tie
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("gap_side", [+1, -1])
+def test_status_when_directions_abort_differently(ss, walk, gap_side):
+    from tests.test_oracle_pins import _gap_one_side_edge_other
+    H, pos, gpos, core = _gap_one_side_edge_other(gap_side)
+    say("abort precedence, gap side %+d walk=%s" % (gap_side, walk))
+    params = oracle.Params(maf_cutoff=0.0)
+    got = _np(ss.ihs(_hm(ss, H, pos, gpos), ss.Params(**vars(params)), steps=True))
+    ref = oracle.ihs(H, pos, gpos, params)
+    check_ihs(got, ref, "ihs precedence")
+    assert got["status"][core] == (3 if gap_side > 0 else 2)
+    A, B = H[:, :4].copy(), H[:, 2:].copy()
+    got = _np(ss.xpehh(_hm(ss, A, pos, gpos), _hm(ss, B, pos, gpos), steps=True))
+    ref = oracle.xpehh(A, B, pos, gpos)
+    check_xpehh(got, ref, "xpehh precedence")
+    assert got["status"][core] == (3 if gap_side > 0 else 2)
+
+
+def test_pooled_cutoff_tie(ss, walk):
+    from tests.test_oracle_pins import _pooled_peel
+    A, B, pos, gpos, core, _ = _pooled_peel(13, 12)
+    say("pooled cutoff tie walk=%s" % walk)
+    got = _np(ss.xpehh(_hm(ss, A, pos, gpos), _hm(ss, B, pos, gpos), steps=True))
+    ref = oracle.xpehh(A, B, pos, gpos)
+    check_xpehh(got, ref, "pooled tie")
+    assert got["steps"][core].tolist() == [20, 20]
+
+
+# ---------------------------------------------------------------------------
+# Pooled XPEHH regions of 9,000 haplotypes (the served stream draws up to
+# 5,000 per population): wide workgroups, thousands of classes
+# ---------------------------------------------------------------------------
+def pooled_pair(kind, na=5000, nb=4000, m=300):
+    """(A alleles, B alleles, pos, gpos, params): a copying-model pair whose B
+    shares A's founders with probability 0.8 (the served stream's regions), or
+    i.i.d. alleles with a low cutoff, whose pooled walks hold thousands of
+    classes before they stop."""
+    if kind == "copying":
+        a = hapgen.copying_model(na, m, 1580 * m, 40, 0.003, 51)
+        rng = np.random.default_rng(52)
+        fb = hapgen.derive_founders(rng, a.founders, 0.8)
+        return a.alleles, hapgen.copy_haplotypes(rng, fb, nb, 0.003, 0.001), a.pos_bp, a.gpos_cm, oracle.Params()
+    A = hapgen.random_haplotypes(na, m, 61, p=0.5)
+    B = hapgen.random_haplotypes(nb, m, 62, p=0.5)
+    return A.alleles, B.alleles, A.pos_bp, A.gpos_cm, oracle.Params(ehh_cutoff=2e-4)
+
+
+@pytest.mark.parametrize("kind", ["copying", "iid"])
+def test_xpehh_pooled_9000_haplotypes(ss, walk, kind):
+    A, B, pos, gpos, params = pooled_pair(kind)
+    say("ss_xpehh 5000+4000 x 300 %s walk=%s" % (kind, walk))
+    got = _np(ss.xpehh(_hm(ss, A, pos, gpos), _hm(ss, B, pos, gpos), ss.Params(**vars(params)),
+                       steps=True))
+    ref = oracle.xpehh(A, B, pos, gpos, params)
+    check_xpehh(got, ref, "xpehh 9000 %s" % kind)
+    assert (ref["status"] == 0).sum() > 200

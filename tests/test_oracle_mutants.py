@@ -41,6 +41,16 @@ MUTANTS = {
                           "if (k < 0 || k >= M) return OR_OK;\n        double g;\n        if (segment(pos, gpos, k, dir, p, &g)) return OR_GAP;\n        if (tr && tr->len >= tr->cap) { tr->capped = 1; return OR_CAP; }\n        part_refine(pt, H + k * n);"),
     "upstream_segment_shifted": ("int64_t lo = dir > 0 ? k - 1 : k;", "int64_t lo = k - 1;"),
     "ratio_swapped": ("unstd[j] = log(i1 / i0);", "unstd[j] = log(i0 / i1);"),
+    # the upstream abort reported ahead of the downstream one (reading R15)
+    "ihs_status_precedence_swapped": (
+        "int st = s_dn != OR_OK ? s_dn : s_up;\n            if (st != OR_OK) { status[j] = (int8_t)st; continue; }\n            double i0",
+        "int st = s_up != OR_OK ? s_up : s_dn;\n            if (st != OR_OK) { status[j] = (int8_t)st; continue; }\n            double i0"),
+    "xpehh_status_precedence_swapped": (
+        "int st = s_dn != OR_OK ? s_dn : s_up;\n            if (st != OR_OK) { status[j] = (int8_t)st; continue; }\n            double a =",
+        "int st = s_up != OR_OK ? s_up : s_dn;\n            if (st != OR_OK) { status[j] = (int8_t)st; continue; }\n            double a ="),
+    # a pooled EHH exactly at the cutoff stops the XPEHH walk (reading R2)
+    "pooled_tie_stops": ("if ((double)SP / PP < p->ehh_cutoff) return OR_OK;",
+                         "if ((double)SP / PP <= p->ehh_cutoff) return OR_OK;"),
     "pooled_pairs_across_cores": ("SP += (uint64_t)choose2(pt->cntA[l] + pt->cntB[l]);\n        }\n        if (tr) {\n            tr->len",
                                   "SP += (uint64_t)choose2(pt->cntA[l] + pt->cntB[l]) + (uint64_t)(pt->cntA[l] * pt->cntB[l]);\n        }\n        if (tr) {\n            tr->len"),
 }

@@ -427,3 +427,108 @@ def test_last_site_is_an_edge():
     out = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm, oracle.Params(maf_cutoff=0.0))
     assert out["status"][0] in (EDGE, UNDEF, MAF)
     assert out["status"][-1] in (EDGE, UNDEF, MAF)
+
+
+# ---------------------------------------------------------------------------
+# Which abort a locus reports when its two directions abort differently
+# (reading R15: the downstream abort if there is one, else the upstream one)
+# ---------------------------------------------------------------------------
+def _gap_one_side_edge_other(gap_side, n_per_core=3, w=6):
+    """Haplotypes identical away from the core, so every walk stays at
+    EHH = 1: on one side a gap longer than the abort gap is crossed two
+    markers out, on the other side the walk runs into the end of the data."""
+    H, pos, gpos, core = _two_core_block(n_per_core, w, 1000, killer=False)
+    pos = pos.copy()
+    if gap_side > 0:
+        pos[core + 3:] += 250_000          # segment (core+2, core+3) is 251 kb
+    else:
+        pos[: core - 2] -= 250_000         # segment (core-3, core-2) is 251 kb
+    return H, pos, gpos, core
+
+
+@pytest.mark.parametrize("gap_side,want", [(+1, GAP), (-1, EDGE)])
+def test_ihs_status_when_directions_abort_differently(gap_side, want):
+    H, pos, gpos, core = _gap_one_side_edge_other(gap_side)
+    out = oracle.ihs(H, pos, gpos, oracle.Params(maf_cutoff=0.0))
+    assert out["status"][core] == want
+    assert np.isnan(out["ihh1"][core]) and np.isnan(out["unstd"][core])
+    # each direction alone: the gap side gives GAP, the other side EDGE
+    r = oracle.ehh(H, pos, gpos, core, P, cap=64)
+    assert r["status"] == want
+
+
+@pytest.mark.parametrize("gap_side,want", [(+1, GAP), (-1, EDGE)])
+def test_xpehh_status_when_directions_abort_differently(gap_side, want):
+    H, pos, gpos, core = _gap_one_side_edge_other(gap_side)
+    A, B = H[:, :4].copy(), H[:, 2:].copy()     # 3+1 and 1+3 derived at the core
+    out = oracle.xpehh(A, B, pos, gpos, P)
+    assert out["status"][core] == want
+    assert np.isnan(out["ihhA"][core]) and np.isnan(out["unstd"][core])
+
+
+# ---------------------------------------------------------------------------
+# Pooled truncation of XPEHH at an exact tie (Sec. 1.3 with reading R2)
+# ---------------------------------------------------------------------------
+def _pooled_peel(nA, nB):
+    """Every pooled haplotype carries the ancestral allele at the core; at
+    the i-th marker on either side, haplotype i-1 of the pooled order (A's
+    then B's, interleaved) alone carries the derived allele, so it leaves the
+    one class: S_pool(i) = C(n - i, 2)."""
+    n = nA + nB
+    M = 2 * n + 1
+    core = n
+    order = []                                   # alternate A and B haplotypes
+    ia, ib = 0, 0
+    while ia < nA or ib < nB:
+        if ia < nA:
+            order.append(("A", ia)); ia += 1
+        if ib < nB:
+            order.append(("B", ib)); ib += 1
+    A = np.zeros((M, nA), dtype=np.uint8)
+    B = np.zeros((M, nB), dtype=np.uint8)
+    for i in range(1, n + 1):
+        pop, h = order[i - 1]
+        for s in (core + i, core - i):
+            (A if pop == "A" else B)[s, h] = 1
+    pos = (np.arange(M, dtype=np.int64) + 1) * 10_000
+    gpos = np.arange(M, dtype=np.float64) * 0.0625
+    return A, B, pos, gpos, core, order
+
+
+def _pooled_peel_exact(nA, nB, order, cutoff, g):
+    """One direction, exactly: the pooled stop at the first i with
+    fl(S_pool(i)/C(n,2)) < cutoff, each population's trapezoid up to there."""
+    n = nA + nB
+    PP = Fraction(n * (n - 1), 2)
+    left = {"A": nA, "B": nB}
+    c2 = lambda k: Fraction(k * (k - 1), 2)
+    prev = {"A": Fraction(1), "B": Fraction(1)}
+    tot = {"A": Fraction(0), "B": Fraction(0)}
+    i = 0
+    while True:
+        i += 1
+        left[order[i - 1][0]] -= 1
+        sp = c2(n - i)
+        if float(sp / PP) < cutoff:
+            return tot, i
+        for q, nq in (("A", nA), ("B", nB)):
+            e = c2(left[q]) / c2(nq)
+            tot[q] += (prev[q] + e) / 2 * g
+            prev[q] = e
+
+
+def test_xpehh_pooled_cutoff_tie_does_not_stop():
+    # pooled n = 25: S_pool = C(6, 2) = 15 of C(25, 2) = 300 is exactly 1/20,
+    # which rounds to the double 0.05 and so does not stop the walk; the stop
+    # comes one marker later at 10/300
+    nA, nB = 13, 12
+    A, B, pos, gpos, core, order = _pooled_peel(nA, nB)
+    out = oracle.xpehh(A, B, pos, gpos, P)
+    tot, stop = _pooled_peel_exact(nA, nB, order, 0.05, Fraction(0.0625))
+    assert stop == 20
+    assert out["steps"][core].tolist() == [stop, stop]
+    for q, key in (("A", "ihhA"), ("B", "ihhB")):
+        want = 2 * tot[q]
+        assert abs(Fraction(out[key][core]) - want) <= Fraction(1, 10**15) * want
+    tr = oracle.xpehh_trace(A, B, pos, gpos, core, P, cap=64)
+    assert int(tr["S"][0, 19, 2]) == 15 and int(tr["S"][0, 20, 2]) == 10
