@@ -191,21 +191,11 @@ def test_autotune_then_parity(ss, regions):
             np.testing.assert_array_equal(g[k], o[k], err_msg=k)
 
 
-def _standardize_numpy(u, status, bins, nbins):
-    z = np.full_like(u, np.nan)
-    for b in range(nbins):
-        m = (bins == b) & np.isin(status, (0, 5))
-        if m.sum() >= 2:
-            v = u[m]
-            sd = v.std(ddof=1)
-            if sd > 0:
-                z[m] = (v - v.mean()) / sd
-    return z
-
-
 def test_large_batch_full_size_sampled_parity(ss):
-    """5,000 haplotypes x 10^6 sites in one persistent launch; the oracle
-    checks every 2,000th scored site and every sweep site."""
+    """5,000 haplotypes x 10^6 sites in one persistent launch.  The oracle
+    walks every 50th scored site, every 5th scored site within 200 kb of each
+    sweep and the sweep sites themselves; the oracle's standardization of the
+    device's scores over all 10^6 sites is compared with the device's."""
     import torch
     say("large batch: generating 5000 x 1e6 on the device")
     alleles, pos, gpos, sweeps = hapgen.large_batch_input(None, device="cuda")
@@ -215,11 +205,13 @@ def test_large_batch_full_size_sampled_parity(ss):
     say("large batch: scanning")
     ss.scan_batch([req])
     got = _np(req.out)
-    say("large batch: oracle on sampled loci")
     host = alleles.cpu().numpy()
-    del alleles
+    del alleles, h, req
     scored = np.flatnonzero(got["status"] != 1)
-    sample = np.unique(np.concatenate([scored[::2000], np.asarray(sweeps)]))
+    near = [np.arange(*np.searchsorted(pos, [pos[s] - 200_000, pos[s] + 200_001])) for s in sweeps]
+    near = np.intersect1d(np.concatenate(near), scored)[::5]
+    sample = np.unique(np.concatenate([scored[::50], near, np.asarray(sweeps)]))
+    say("large batch: oracle on %d sampled loci (%d near sweeps)" % (len(sample), len(near)))
     ref = oracle.ihs(host, pos, gpos, loci=sample)
     g = {k: v[sample] for k, v in got.items()}
     r = {k: v[sample] for k, v in ref.items()}
@@ -233,12 +225,18 @@ def test_large_batch_full_size_sampled_parity(ss):
     assert_rel(g["ihh1"], r["ihh1"], every, "ihh1")
     assert_rel(g["ihh0"], r["ihh0"], every, "ihh0")
     assert_log(g["unstd"], r["unstd"], every, "unstd")
-    # standardization over all 10^6 sites, checked against numpy on the
-    # device's own unstandardized scores
-    n1 = np.rint(got["freq"] * 5000).astype(np.int64)
-    bins = np.minimum((40 * n1) // 5000, 39)
-    z = _standardize_numpy(got["unstd"], got["status"], bins, 40)
-    assert_log(got["std"], z, np.isin(got["status"], (0, 5)), "std")
+    assert r["steps"].max() > 1000          # the sweeps' long walks are in the sample
+    # standardization over all 10^6 sites: the oracle's routine on the
+    # device's scores, bins from the derived-allele counts of the matrix
+    say("large batch: oracle standardization of all sites")
+    n1 = host.sum(axis=1, dtype=np.int64)
+    del host
+    bins = np.minimum((40 * n1) // 5000, 39).astype(np.int32)
+    np.testing.assert_array_equal(bins[sample], r["bin"])
+    pre = np.where(got["status"] == 5, 0, got["status"]).astype(np.int8)
+    z = oracle.standardize(got["unstd"], pre, bins, 40)
+    np.testing.assert_array_equal(z["status"], got["status"])
+    assert_log(got["std"], z["std"], np.ones(len(pos), dtype=bool), "std")
     assert (got["status"] == 0).sum() > 100000
 
 
