@@ -172,6 +172,27 @@ int ss_xpehh(const ss_hapmat *a, const ss_hapmat *b, const ss_params *p,
              void *stream);
 
 /*
+ * ss_ihs_static -- ss_ihs for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same scan, the same kernels and the same results, with its
+ * scratch in a static device array of ss_static_scratch_bytes() bytes (32 MiB)
+ * that each GPU the library runs on holds until the process ends, instead of a
+ * caller's workspace.  The caller passes the inputs and outputs as for ss_ihs.
+ * It calls no allocating routine.  Every call on one GPU shares that GPU's
+ * array, and each call clears what it needs cleared: calls that overlap in
+ * time on one GPU (two streams, two threads) race and must be serialized by
+ * the caller.
+ * Errors: as ss_ihs; SS_EWS when the scan needs more scratch than the array
+ * holds (ss_workspace_bytes(SS_OP_IHS, ...) > ss_static_scratch_bytes()).
+ */
+int ss_ihs_static(const ss_hapmat *h, const ss_params *p, double *d_ihh1, double *d_ihh0,
+                  double *d_unstd, double *d_std, double *d_freq, int8_t *d_status,
+                  int32_t *d_steps, void *stream);
+
+/* Size of the static scratch array of ss_ihs_static, in bytes. */
+size_t ss_static_scratch_bytes(void);
+
+/*
  * ss_set_walk_kernel -- choose the EHH-walk kernel used by ss_ihs / ss_xpehh
  * (process-wide; results are identical, only speed differs):
  *   0 = automatic (bitmask kernel when it applies, else the persistent

@@ -90,6 +90,9 @@ def lib():
         L.ss_ehh.argtypes = [HM, i64, PR, i64, P, P, P, P, P, P, P, sz, P]
         L.ss_ihs.argtypes = [HM, PR, P, P, P, P, P, P, P, P, sz, P]
         L.ss_xpehh.argtypes = [HM, HM, PR, P, P, P, P, P, P, P, sz, P]
+        L.ss_ihs_static.argtypes = [HM, PR, P, P, P, P, P, P, P, P]
+        L.ss_static_scratch_bytes.argtypes = []
+        L.ss_static_scratch_bytes.restype = sz
         L.ss_set_walk_kernel.argtypes = [ctypes.c_int]
         L.ss_set_mask_lanes.argtypes = [ctypes.c_int]
         L.ss_timing_enable.argtypes = [ctypes.c_int]
@@ -109,7 +112,7 @@ def lib():
         L.ss_set_group_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
         L.ss_get_group_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32)]
-        for f in ("ss_pack", "ss_ehh", "ss_ihs", "ss_xpehh", "ss_set_walk_kernel", "ss_set_mask_lanes",
+        for f in ("ss_pack", "ss_ehh", "ss_ihs", "ss_ihs_static", "ss_xpehh", "ss_set_walk_kernel", "ss_set_mask_lanes",
                   "ss_timing_enable", "ss_timing_read", "ss_scan_batch", "ss_get_batch_config",
                   "ss_set_batch_config", "ss_autotune_batch", "ss_set_graph", "ss_graph_clear",
                   "ss_get_group_tuning", "ss_set_group_tuning"):
@@ -271,6 +274,35 @@ def ihs(h: HapMat, params: Optional[Params] = None, steps: bool = False, stream=
                         _ptr(out["status"]), _ptr(out.get("steps")), ctypes.c_void_p(base),
                         avail, _stream(stream)))
     return out
+
+
+def ihs_static(h: HapMat, params: Optional[Params] = None, steps: bool = False, stream=None,
+               out: Optional[dict] = None, validate: bool = True):
+    """The iHS scan of ``ihs`` through ss_ihs_static: no workspace, the
+    library's static device scratch instead (scans up to
+    ``static_scratch_bytes()`` of scratch).  Pass ``out`` to allocate nothing
+    here either."""
+    if validate:
+        h.validate()
+    d = h.desc()
+    M = h.n_sites
+    dev = h.bits.device
+    if out is None:
+        out = {k: torch.empty(M, dtype=torch.float64, device=dev)
+               for k in ("ihh1", "ihh0", "unstd", "std", "freq")}
+        out["status"] = torch.empty(M, dtype=torch.int8, device=dev)
+        if steps:
+            out["steps"] = torch.empty((M, 2, 2), dtype=torch.int32, device=dev)
+    cp = _cparams(params)
+    _check(lib().ss_ihs_static(ctypes.byref(d), ctypes.byref(cp), _ptr(out["ihh1"]),
+                               _ptr(out["ihh0"]), _ptr(out["unstd"]), _ptr(out["std"]),
+                               _ptr(out["freq"]), _ptr(out["status"]), _ptr(out.get("steps")),
+                               _stream(stream)))
+    return out
+
+
+def static_scratch_bytes() -> int:
+    return int(lib().ss_static_scratch_bytes())
 
 
 def xpehh(a: HapMat, b: HapMat, params: Optional[Params] = None, steps: bool = False,

@@ -876,6 +876,36 @@ std::string graph_key(const ss_scan_request *reqs, int32_t n, const ss_params *p
     return k;
 }
 
+// ---- static scratch of ss_ihs_static -----------------------------------------
+// For callers that cannot allocate device memory: the scan's workspace lives in
+// a file-scope device array instead of a caller's buffer.  Each device the
+// library runs on holds its own copy until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol): the device address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and is used everywhere instead.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+int static_scratch(void **out) {
+    int dev = -1;
+    SS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SS_EDEV, "device index out of range for the static scratch");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        SS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SS_EDEV, "hipGetSymbolAddress returned a null address for the static scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1003,6 +1033,34 @@ int ss_xpehh(const ss_hapmat *ha, const ss_hapmat *hb, const ss_params *p, doubl
     sc.steps = d_steps;
     return run_single(sc, p, d_ws, ws_bytes, (hipStream_t)stream);
 }
+
+int ss_ihs_static(const ss_hapmat *h, const ss_params *p, double *d_ihh1, double *d_ihh0,
+                  double *d_unstd, double *d_std, double *d_freq, int8_t *d_status,
+                  int32_t *d_steps, void *stream) {
+    g_err.clear();
+    SS_TRY(validate_scan(ss::MODE_CORE, h, nullptr, p, d_ihh1, d_ihh0, d_unstd, d_std, d_freq,
+                         d_status));
+    const size_t need = scan_bytes(ss::MODE_CORE, h, nullptr, p);
+    if (need > kStaticScratchBytes)
+        return fail(SS_EWS, "scan needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                                std::to_string(kStaticScratchBytes) + " (use ss_ihs with a workspace)");
+    void *ws = nullptr;
+    SS_TRY(static_scratch(&ws));
+    Scan sc{};
+    sc.mode = ss::MODE_CORE;
+    sc.a = h;
+    sc.b = nullptr;
+    sc.out_x = d_ihh1;
+    sc.out_y = d_ihh0;
+    sc.unstd = d_unstd;
+    sc.stdz = d_std;
+    sc.freq = d_freq;
+    sc.status = d_status;
+    sc.steps = d_steps;
+    return run_single(sc, p, ws, kStaticScratchBytes, (hipStream_t)stream);
+}
+
+size_t ss_static_scratch_bytes(void) { return kStaticScratchBytes; }
 
 size_t ss_batch_workspace_bytes(const ss_scan_request *reqs, int32_t n_reqs, const ss_params *p) {
     if (check_requests(reqs, n_reqs, p) != SS_OK) return 0;

@@ -220,3 +220,21 @@ def test_walk_kernel_choices(lib):
     ss.set_graph(True)
     ss.set_graph(False)
     ss.graph_clear()
+
+
+def test_static_scratch_entry_point_checks_before_the_device(lib):
+    """ss_ihs_static refuses, on the host, null outputs and scans needing more
+    scratch than its static array holds (1,000 x 300,000 here)."""
+    import paper_1403_6854_amd as ss
+    p = ss._cparams(None)
+    fake = ctypes.c_void_p(0x1000)
+    cap = lib.ss_static_scratch_bytes()
+    assert cap == 32 << 20
+    small = _desc(n_haps=204, n_sites=100, wps=4)
+    assert lib.ss_ihs_static(ctypes.byref(small), ctypes.byref(p), fake, None, fake, fake, fake,
+                             fake, None, None) == ss.SS_EARG
+    big = _desc(n_haps=1000, n_sites=300_000, wps=16)
+    assert lib.ss_workspace_bytes(ss.OP_IHS, ctypes.byref(big), None, ctypes.byref(p), 0) > cap
+    assert lib.ss_ihs_static(ctypes.byref(big), ctypes.byref(p), fake, fake, fake, fake, fake,
+                             fake, None, None) == ss.SS_EWS
+    assert b"static scratch" in lib.ss_last_error()
