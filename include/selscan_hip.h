@@ -69,6 +69,11 @@ typedef struct ss_params {
     int64_t gap_scale_bp;  /* gaps b > this scale g by gap_scale_bp / b, > 0 [20000] */
     int64_t max_gap_bp;    /* gaps b > this abort the locus, >= gap_scale  [200000] */
     double bin_width;      /* derived-allele-frequency bin width, (0, 1]   [0.025]  */
+    int32_t physical_map;  /* 0: integrate EHH over the genetic map, g = difference of
+                              gpos_cm [default]; 1: over the physical map, g = difference
+                              of pos_bp in base pairs (the rehh convention the paper
+                              compares against in Sec. 2.1); the gap rules apply to
+                              both in the same way                              [0]      */
 } ss_params;
 
 /* A bit-packed haplotype matrix with its physical and genetic map
@@ -191,6 +196,48 @@ int ss_ihs_static(const ss_hapmat *h, const ss_params *p, double *d_ihh1, double
 
 /* Size of the static scratch array of ss_ihs_static, in bytes. */
 size_t ss_static_scratch_bytes(void);
+
+/*
+ * Genome-wide standardization.  The paper standardizes iHS within
+ * derived-allele-frequency bins over the entire genome (Sec. 1.2, Eq. 6) and
+ * XPEHH over all loci (Sec. 1.3, Eq. 9).  ss_ihs, ss_xpehh and ss_scan_batch
+ * standardize each scan on its own; ss_genome_standardize re-standardizes the
+ * outputs of many scans -- the chromosomes of a genome, the regions of a
+ * batch -- together, as one sequence of loci (regions in the order given,
+ * sites in order within each): per bin, N and the mean of every scored score,
+ * then the N-1 standard deviation, then z = (u - mean) / sd, as the per-scan
+ * standardization does for one scan.
+ */
+typedef struct ss_std_region {
+    const double *d_unstd;   /* [n_sites] a scan's unstandardized scores (d_unstd output)   */
+    const double *d_freq;    /* [n_sites] iHS: the scan's derived frequencies (d_freq
+                                output), which give each site's bin; ignored for XPEHH   */
+    int8_t *d_status;        /* [n_sites] in/out: the scan's statuses.  Sites with OK or
+                                BIN are scored and come out OK, or BIN when their
+                                genome-wide bin has fewer than 2 loci or zero spread;
+                                other statuses are left unchanged                        */
+    double *d_std;           /* [n_sites] out: genome-wide standardized scores (NaN where
+                                the status is not OK)                                    */
+    int64_t n_sites;         /* >= 0                                                     */
+    int32_t n_haps;          /* iHS: haplotypes of the scan (2 .. 32767); ignored for XPEHH */
+    int32_t reserved;
+} ss_std_region;
+
+/* Workspace of ss_genome_standardize (0 for invalid arguments). */
+size_t ss_genome_workspace_bytes(const ss_std_region *regs, int32_t n_regs, int32_t op,
+                                 const ss_params *p);
+
+/*
+ * ss_genome_standardize -- standardize the regions' scores together.
+ *   op          SS_OP_IHS (bins of width p->bin_width) or SS_OP_XPEHH (one bin)
+ *   d_binstat   NULL, or [nbins][3] double out: N, mean and SD of each bin
+ * The regions' buffers must not overlap one another.  Results are the same
+ * from run to run (sums in a fixed order).
+ * Errors: SS_EARG, SS_EWS, SS_EDEV.
+ */
+int ss_genome_standardize(const ss_std_region *regs, int32_t n_regs, int32_t op,
+                          const ss_params *p, double *d_binstat, void *d_ws, size_t ws_bytes,
+                          void *stream);
 
 /*
  * ss_set_walk_kernel -- choose the EHH-walk kernel used by ss_ihs / ss_xpehh

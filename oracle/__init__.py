@@ -34,12 +34,13 @@ class Params:
     gap_scale_bp: int = 20_000
     max_gap_bp: int = 200_000
     bin_width: float = 0.025
+    physical_map: int = 0      # 1: integrate over physical distance (bp)
 
 
 class _CParams(ctypes.Structure):
     _fields_ = [("ehh_cutoff", ctypes.c_double), ("maf_cutoff", ctypes.c_double),
                 ("gap_scale_bp", ctypes.c_int64), ("max_gap_bp", ctypes.c_int64),
-                ("bin_width", ctypes.c_double)]
+                ("bin_width", ctypes.c_double), ("physical_map", ctypes.c_int32)]
 
 
 def build(force: bool = True) -> str:
@@ -85,7 +86,7 @@ def _ptr(a):
 
 def _cp(p: Params) -> _CParams:
     return _CParams(float(p.ehh_cutoff), float(p.maf_cutoff), int(p.gap_scale_bp),
-                    int(p.max_gap_bp), float(p.bin_width))
+                    int(p.max_gap_bp), float(p.bin_width), int(p.physical_map))
 
 
 def _prep(alleles, pos, gpos):
@@ -213,3 +214,24 @@ def standardize(u, status, bins, nbins: int):
     _load().or_standardize(_ptr(u), _ptr(st), _ptr(b), M, int(nbins), _ptr(z), _ptr(mean),
                            _ptr(sd), _ptr(cnt))
     return {"std": z, "status": st, "mean": mean, "sd": sd, "n": cnt}
+
+
+def genome_standardize(outs, nbins: int):
+    """Standardization over the whole genome (Eq. 6 for iHS with ``nbins``
+    frequency bins, Eq. 9 for XPEHH with one): the scored loci (status OK or
+    BIN) of several scans, concatenated in list order and site order, go
+    through ``or_standardize`` together.  ``outs`` are oracle scan outputs
+    (iHS scans carry their ``bin``).  Returns one {"std", "status"} per scan
+    and the bin statistics {"mean", "sd", "n"}."""
+    u = np.concatenate([np.asarray(o["unstd"], dtype=np.float64) for o in outs])
+    st = np.concatenate([np.where(np.asarray(o["status"]) == STATUS["BIN"], STATUS["OK"],
+                                  np.asarray(o["status"])).astype(np.int8) for o in outs])
+    b = np.concatenate([np.asarray(o["bin"], dtype=np.int32) if nbins > 1
+                        else np.zeros(len(o["unstd"]), dtype=np.int32) for o in outs])
+    r = standardize(u, st, b, nbins)
+    res, at = [], 0
+    for o in outs:
+        m = len(o["unstd"])
+        res.append({"std": r["std"][at:at + m], "status": r["status"][at:at + m]})
+        at += m
+    return res, {"mean": r["mean"], "sd": r["sd"], "n": r["n"]}

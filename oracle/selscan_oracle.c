@@ -50,7 +50,10 @@
  *       the score undefined;
  *   R15 iHH = (downstream sum) + (upstream sum), each accumulated from x0
  *       outward; the per-direction locus status is the downstream abort if
- *       any, else the upstream one.
+ *       any, else the upstream one;
+ *   R16 with the physical-map option the segment length g is the physical
+ *       distance b in base pairs, and the gap rules apply to it unchanged
+ *       (a scaled segment then counts gap_scale_bp base pairs).
  *
  * Build:  gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared
  */
@@ -68,6 +71,7 @@ typedef struct {
     int64_t gap_scale_bp;  /* gaps above this scale g; paper default 20 kb   */
     int64_t max_gap_bp;    /* gaps above this abort; paper default 200 kb    */
     double bin_width;      /* iHS frequency-bin width; 0.025 here            */
+    int32_t physical_map;  /* 1: integrate over physical distance in bp      */
 } or_params;
 
 enum { OR_OK = 0, OR_MAF = 1, OR_EDGE = 2, OR_GAP = 3, OR_UNDEF = 4,
@@ -151,15 +155,18 @@ static void pooled_row(const uint8_t *HA, int64_t nA, const uint8_t *HB, int64_t
     if (nB > 0) memcpy(row + nA, HB + k * nB, (size_t)nB);
 }
 
-/* Physical gap and (scaled) genetic length of the segment crossed when the
- * walk moves from marker k-dir to marker k.  Returns 0 to go on, or OR_GAP. */
+/* Physical gap and (scaled) length of the segment crossed when the walk
+ * moves from marker k-dir to marker k, on the genetic map or, with the
+ * physical-map option, in base pairs (the map rehh integrates over, which the
+ * paper's Sec. 2.1 compares against); the gap rules are the same for both.
+ * Returns 0 to go on, or OR_GAP. */
 static int segment(const int64_t *pos, const double *gpos, int64_t k, int dir,
                    const or_params *p, double *g_out) {
     int64_t lo = dir > 0 ? k - 1 : k;
     int64_t hi = lo + 1;
     int64_t b = pos[hi] - pos[lo];
     if (b > p->max_gap_bp) return OR_GAP;
-    double g = gpos[hi] - gpos[lo];
+    double g = p->physical_map ? (double)b : gpos[hi] - gpos[lo];
     if (b > p->gap_scale_bp) g = g * ((double)p->gap_scale_bp / (double)b);
     *g_out = g;
     return 0;

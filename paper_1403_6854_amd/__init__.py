@@ -10,8 +10,9 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import math
 import os
-from typing import Optional
+from typing import Optional, Sequence
 
 import torch
 
@@ -37,12 +38,13 @@ class Params:
     gap_scale_bp: int = 20_000
     max_gap_bp: int = 200_000
     bin_width: float = 0.025
+    physical_map: int = 0      # 1: integrate over pos_bp (g in bp) instead of gpos_cm
 
 
 class _Params(ctypes.Structure):
     _fields_ = [("ehh_cutoff", ctypes.c_double), ("maf_cutoff", ctypes.c_double),
                 ("gap_scale_bp", ctypes.c_int64), ("max_gap_bp", ctypes.c_int64),
-                ("bin_width", ctypes.c_double)]
+                ("bin_width", ctypes.c_double), ("physical_map", ctypes.c_int32)]
 
 
 class _HapMat(ctypes.Structure):
@@ -66,6 +68,13 @@ class _BatchConfig(ctypes.Structure):
                 ("kernel", ctypes.c_int32), ("small_pair_cap", ctypes.c_int32),
                 ("slots", ctypes.c_int32), ("class_cap", ctypes.c_int32),
                 ("counter_copies", ctypes.c_int32)]
+
+
+class _StdRegion(ctypes.Structure):
+    _fields_ = [("d_unstd", ctypes.c_void_p), ("d_freq", ctypes.c_void_p),
+                ("d_status", ctypes.c_void_p), ("d_std", ctypes.c_void_p),
+                ("n_sites", ctypes.c_int64), ("n_haps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -93,6 +102,10 @@ def lib():
         L.ss_ihs_static.argtypes = [HM, PR, P, P, P, P, P, P, P, P]
         L.ss_static_scratch_bytes.argtypes = []
         L.ss_static_scratch_bytes.restype = sz
+        SR = ctypes.POINTER(_StdRegion)
+        L.ss_genome_workspace_bytes.argtypes = [SR, ctypes.c_int32, ctypes.c_int32, PR]
+        L.ss_genome_workspace_bytes.restype = sz
+        L.ss_genome_standardize.argtypes = [SR, ctypes.c_int32, ctypes.c_int32, PR, P, P, sz, P]
         L.ss_set_walk_kernel.argtypes = [ctypes.c_int]
         L.ss_set_mask_lanes.argtypes = [ctypes.c_int]
         L.ss_timing_enable.argtypes = [ctypes.c_int]
@@ -112,7 +125,7 @@ def lib():
         L.ss_set_group_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
         L.ss_get_group_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32)]
-        for f in ("ss_pack", "ss_ehh", "ss_ihs", "ss_ihs_static", "ss_xpehh", "ss_set_walk_kernel", "ss_set_mask_lanes",
+        for f in ("ss_pack", "ss_ehh", "ss_ihs", "ss_ihs_static", "ss_genome_standardize", "ss_xpehh", "ss_set_walk_kernel", "ss_set_mask_lanes",
                   "ss_timing_enable", "ss_timing_read", "ss_scan_batch", "ss_get_batch_config",
                   "ss_set_batch_config", "ss_autotune_batch", "ss_set_graph", "ss_graph_clear",
                   "ss_get_group_tuning", "ss_set_group_tuning"):
@@ -139,7 +152,7 @@ def _stream(stream) -> ctypes.c_void_p:
 def _cparams(p: Optional[Params]) -> _Params:
     p = p or Params()
     return _Params(float(p.ehh_cutoff), float(p.maf_cutoff), int(p.gap_scale_bp),
-                   int(p.max_gap_bp), float(p.bin_width))
+                   int(p.max_gap_bp), float(p.bin_width), int(p.physical_map))
 
 
 def _need_cuda(*ts):
@@ -299,6 +312,47 @@ def ihs_static(h: HapMat, params: Optional[Params] = None, steps: bool = False, 
                                _ptr(out["freq"]), _ptr(out["status"]), _ptr(out.get("steps")),
                                _stream(stream)))
     return out
+
+
+def genome_standardize(outs: Sequence[dict], n_haps: Optional[Sequence[int]] = None,
+                       op: int = OP_IHS, params: Optional[Params] = None, stream=None,
+                       ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Standardize the scores of many scans together (Sec. 1.2 Eq. 6 and
+    Sec. 1.3 Eq. 9 over the whole genome), in place: ``outs`` are the output
+    dicts of ``ihs`` / ``xpehh`` / batch requests (their ``unstd``, ``freq``,
+    ``status`` and ``std``), taken as one sequence of loci in list order;
+    ``n_haps`` gives each iHS scan's haplotype count (its bins come from
+    ``freq``).  Returns the per-bin statistics [nbins, 3] = N, mean, SD."""
+    if not outs:
+        raise ValueError("no scans")
+    if op == OP_IHS and (n_haps is None or len(n_haps) != len(outs)):
+        raise ValueError("iHS scans need their haplotype counts")
+    arr = (_StdRegion * len(outs))()
+    dev = outs[0]["unstd"].device
+    for i, o in enumerate(outs):
+        M = int(o["unstd"].numel())
+        for k, dt in (("unstd", torch.float64), ("status", torch.int8), ("std", torch.float64)):
+            if o[k].dtype != dt or o[k].numel() != M or not o[k].is_contiguous():
+                raise ValueError("scan %d: %s must be a contiguous %s tensor of %d" % (i, k, dt, M))
+        fr = o.get("freq") if op == OP_IHS else None
+        if op == OP_IHS and (fr is None or fr.dtype != torch.float64 or fr.numel() != M):
+            raise ValueError("scan %d: iHS scans need their float64 freq" % i)
+        arr[i] = _StdRegion(o["unstd"].data_ptr(), fr.data_ptr() if fr is not None else None,
+                            o["status"].data_ptr(), o["std"].data_ptr(), M,
+                            int(n_haps[i]) if op == OP_IHS else 0, 0)
+    cp = _cparams(params)
+    nb = lib().ss_genome_workspace_bytes(arr, len(outs), op, ctypes.byref(cp))
+    if nb == 0:
+        raise SelscanError(SS_EARG, "invalid arguments for ss_genome_workspace_bytes: " +
+                           lib().ss_last_error().decode())
+    ws = _workspace(nb, dev, ws)
+    base = _aligned(ws)
+    nbins = int(math.floor(1.0 / (params or Params()).bin_width + 0.5)) if op == OP_IHS else 1
+    binstat = torch.empty((max(1, nbins), 3), dtype=torch.float64, device=dev)
+    _check(lib().ss_genome_standardize(arr, len(outs), op, ctypes.byref(cp), _ptr(binstat),
+                                       ctypes.c_void_p(base), ws.numel() - (base - ws.data_ptr()),
+                                       _stream(stream)))
+    return binstat
 
 
 def static_scratch_bytes() -> int:

@@ -58,6 +58,7 @@ int check_params(const ss_params *p) {
     if (!(p->bin_width > 0.0 && p->bin_width <= 1.0))
         return fail(SS_EARG, "bin_width must be in (0, 1]");
     if (nbins_of(p) > 100000) return fail(SS_EARG, "bin_width too small");
+    if (p->physical_map != 0 && p->physical_map != 1) return fail(SS_EARG, "physical_map must be 0 or 1");
     return SS_OK;
 }
 
@@ -380,6 +381,7 @@ ss::WalkArgs walk_args(const ss_hapmat *a, const ss_hapmat *b, const ss_params *
     w.cutoff = p->ehh_cutoff;
     w.gap_scale = p->gap_scale_bp;
     w.max_gap = p->max_gap_bp;
+    w.physical = p->physical_map;
     return w;
 }
 
@@ -479,8 +481,8 @@ int prepare_scan(const Scan &sc, const ss_params *p, hipStream_t s) {
     if (need_b)
         SS_HIP(ss::launch_transpose(a.bitsB, a.wpsB, a.nB, M, a.mwp,
                                     sc.w.hbits + (size_t)a.nA * (size_t)a.mwp, s));
-    SS_HIP(ss::launch_segments(M, a.pos, a.gpos, p->gap_scale_bp, p->max_gap_bp, sc.w.seg,
-                               sc.w.redo, s));
+    SS_HIP(ss::launch_segments(M, a.pos, a.gpos, p->gap_scale_bp, p->max_gap_bp, p->physical_map,
+                               sc.w.seg, sc.w.redo, s));
     return SS_OK;
 }
 
@@ -917,6 +919,7 @@ void ss_default_params(ss_params *p) {
     p->gap_scale_bp = 20000;
     p->max_gap_bp = 200000;
     p->bin_width = 0.025;
+    p->physical_map = 0;
 }
 
 const char *ss_version(void) { return "selscan-hip 0.2 (gfx950)"; }
@@ -1061,6 +1064,98 @@ int ss_ihs_static(const ss_hapmat *h, const ss_params *p, double *d_ihh1, double
 }
 
 size_t ss_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of ss_genome_standardize: the region table, the bin statistics
+// (unless the caller asks for them in d_binstat) and the per-tile sums.
+struct GenomeWs {
+    ss::GenomeRegion *table;
+    double *binstat;
+    double *part;
+    int64_t tiles;
+    size_t bytes;
+};
+
+int check_genome(const ss_std_region *regs, int32_t n, int32_t op, const ss_params *p) {
+    if (!regs || n < 1) return fail(SS_EARG, "no regions");
+    if (n > (1 << 20)) return fail(SS_EARG, "more than 2^20 regions");
+    if (op != SS_OP_IHS && op != SS_OP_XPEHH) return fail(SS_EARG, "op must be SS_OP_IHS or SS_OP_XPEHH");
+    SS_TRY(check_params(p));
+    for (int32_t i = 0; i < n; ++i) {
+        const ss_std_region &r = regs[i];
+        const std::string at = "region " + std::to_string(i) + ": ";
+        if (r.n_sites < 0 || r.n_sites > ((int64_t)1 << 31) - 1)
+            return fail(SS_EARG, at + "n_sites must be in [0, 2^31)");
+        if (r.n_sites > 0 && (!r.d_unstd || !r.d_status || !r.d_std))
+            return fail(SS_EARG, at + "null device pointer");
+        if (op == SS_OP_IHS && r.n_sites > 0) {
+            if (!r.d_freq) return fail(SS_EARG, at + "iHS regions need their derived frequencies");
+            if (r.n_haps < 2 || r.n_haps > kMaxHaps) return fail(SS_EARG, at + "n_haps must be in [2, 32767]");
+        }
+    }
+    return SS_OK;
+}
+
+GenomeWs carve_genome(void *base, const ss_std_region *regs, int32_t n, int nbins, bool own_binstat) {
+    GenomeWs w{};
+    int64_t tiles = 0;
+    for (int32_t i = 0; i < n; ++i) tiles += ss::genome_tiles(regs[i].n_sites);
+    w.tiles = tiles;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char *q = base ? (char *)base + off : nullptr;
+        off += align256(b);
+        return (void *)q;
+    };
+    w.table = (ss::GenomeRegion *)take(sizeof(ss::GenomeRegion) * (size_t)n);
+    w.binstat = own_binstat ? (double *)take(24 * (size_t)nbins) : nullptr;
+    w.part = (double *)take(8 * std::max<size_t>(1, ss::genome_scratch_doubles(tiles, nbins)));
+    w.bytes = off;
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ss_genome_workspace_bytes(const ss_std_region *regs, int32_t n_regs, int32_t op,
+                                 const ss_params *p) {
+    if (check_genome(regs, n_regs, op, p) != SS_OK) return 0;
+    const int nbins = op == SS_OP_IHS ? nbins_of(p) : 1;
+    return carve_genome(nullptr, regs, n_regs, nbins, true).bytes;
+}
+
+int ss_genome_standardize(const ss_std_region *regs, int32_t n_regs, int32_t op, const ss_params *p,
+                          double *d_binstat, void *d_ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    SS_TRY(check_genome(regs, n_regs, op, p));
+    const int nbins = op == SS_OP_IHS ? nbins_of(p) : 1;
+    const GenomeWs need = carve_genome(nullptr, regs, n_regs, nbins, d_binstat == nullptr);
+    if (!d_ws || ws_bytes < need.bytes) return fail(SS_EWS, "workspace smaller than ss_genome_workspace_bytes()");
+    GenomeWs w = carve_genome(d_ws, regs, n_regs, nbins, d_binstat == nullptr);
+    if (d_binstat) w.binstat = d_binstat;
+    std::vector<ss::GenomeRegion> host((size_t)n_regs);
+    int64_t t0 = 0;
+    for (int32_t i = 0; i < n_regs; ++i) {
+        const ss_std_region &r = regs[i];
+        ss::GenomeRegion &g = host[(size_t)i];
+        g.u = r.d_unstd;
+        g.freq = op == SS_OP_IHS ? r.d_freq : nullptr;
+        g.status = r.d_status;
+        g.z = r.d_std;
+        g.M = r.n_sites;
+        g.tile0 = t0;
+        g.n = r.n_haps;
+        g.pad = 0;
+        t0 += ss::genome_tiles(r.n_sites);
+    }
+    SS_HIP(ss::launch_genome_standardize(host.data(), n_regs, w.table, w.tiles, nbins, w.binstat, w.part,
+                                         (hipStream_t)stream));
+    return SS_OK;
+}
 
 size_t ss_batch_workspace_bytes(const ss_scan_request *reqs, int32_t n_reqs, const ss_params *p) {
     if (check_requests(reqs, n_reqs, p) != SS_OK) return 0;

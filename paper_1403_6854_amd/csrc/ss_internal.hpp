@@ -32,6 +32,7 @@ struct WalkArgs {
     double cutoff;
     int64_t gap_scale;
     int64_t max_gap;
+    int32_t physical;           // 1: segment length = physical distance in bp, else genetic
     const uint8_t *walk_flag;   // [M], nonzero = score this site; null = all sites
     const int32_t *sites;       // null: block x walks site site0 + blockIdx.x
     int64_t site0;
@@ -233,7 +234,8 @@ hipError_t launch_wide_walk(const Region *regs, int32_t nreg, int64_t total_item
 hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps,
                        uint64_t *bits, hipStream_t s);
 hipError_t launch_segments(int64_t M, const int64_t *pos, const double *gpos, int64_t gap_scale,
-                           int64_t max_gap, double *seg, int32_t *zero_me, hipStream_t s);
+                           int64_t max_gap, int32_t physical, double *seg, int32_t *zero_me,
+                           hipStream_t s);
 // Haplotype-major transposed matrix: [n][mwp] words, mwp = ceil(M/64) + 2.
 inline int64_t hap_major_words(int64_t M) { return (M + 63) / 64 + 2; }
 hipError_t launch_transpose(const uint64_t *bits, int64_t wps, int64_t n, int64_t M, int64_t mwp,
@@ -251,6 +253,23 @@ int64_t standardize_scratch_doubles(int64_t M, int32_t nbins);
 hipError_t launch_standardize(int64_t M, const double *unstd, int8_t *status,
                               const int32_t *bin, int32_t nbins, double *binstat,
                               double *scratch, double *z, hipStream_t s);
+// Genome-wide standardization over many scans' outputs (ss_genome.hip).  The
+// regions' 1,024-site tiles are numbered region by region: region r owns
+// tiles [tile0, tile0 + genome_tiles(M)).
+struct GenomeRegion {
+    const double *u;      // [M] unstandardized scores
+    const double *freq;   // [M] derived frequency (iHS bins), null: one bin
+    int8_t *status;       // [M] in: scan status; out: OK / BIN for scored sites
+    double *z;            // [M] standardized scores
+    int64_t M;
+    int64_t tile0;
+    int32_t n, pad;       // haplotypes of an iHS scan
+};
+int64_t genome_tiles(int64_t n_sites);
+size_t genome_scratch_doubles(int64_t total_tiles, int32_t nbins);
+hipError_t launch_genome_standardize(const GenomeRegion *host, int32_t nreg, GenomeRegion *dev,
+                                     int64_t total_tiles, int32_t nbins, double *binstat,
+                                     double *part, hipStream_t s);
 hipError_t launch_ehh_finish(int64_t n, int64_t cap, const uint64_t *S, const int64_t *len,
                              const double *dihh, const int32_t *dstatus, double *ehh,
                              double *ihh, int8_t *status, hipStream_t s);

@@ -80,15 +80,16 @@ __global__ void __launch_bounds__(kBlock) transpose_kernel(const uint64_t *__res
     }
 }
 
-// Genetic length of every segment between neighbouring sites, with the gap
-// rules of Sec. 1.2 applied once per scan instead of once per walk step:
-// seg[k] is the length of the segment from site k-1 to site k, scaled by
-// gap_scale / b when its physical length b exceeds gap_scale, or -1 when
-// b > max_gap (the walk aborts there).  seg[0] is unused.
+// Length of every segment between neighbouring sites on the map EHH is
+// integrated over (genetic, or physical in bp), with the gap rules of
+// Sec. 1.2 applied once per scan instead of once per walk step: seg[k] is the
+// length of the segment from site k-1 to site k, scaled by gap_scale / b when
+// its physical length b exceeds gap_scale, or -1 when b > max_gap (the walk
+// aborts there).  seg[0] is unused.
 __global__ void __launch_bounds__(kBlock) segment_kernel(int64_t M, const int64_t *__restrict__ pos,
                                                          const double *__restrict__ gpos,
                                                          int64_t gap_scale, int64_t max_gap,
-                                                         double *__restrict__ seg,
+                                                         int32_t physical, double *__restrict__ seg,
                                                          int32_t *__restrict__ zero_me) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k == 0 && zero_me) *zero_me = 0;   // the walk's overflow-list counter
@@ -100,7 +101,7 @@ __global__ void __launch_bounds__(kBlock) segment_kernel(int64_t M, const int64_
     const int64_t b = pos[k] - pos[k - 1];
     double g = -1.0;
     if (b <= max_gap) {
-        g = gpos[k] - gpos[k - 1];
+        g = physical ? (double)b : gpos[k] - gpos[k - 1];
         if (b > gap_scale) g = g * ((double)gap_scale / (double)b);
     }
     seg[k] = g;
@@ -551,10 +552,11 @@ hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps
 }
 
 hipError_t launch_segments(int64_t M, const int64_t *pos, const double *gpos, int64_t gap_scale,
-                           int64_t max_gap, double *seg, int32_t *zero_me, hipStream_t s) {
+                           int64_t max_gap, int32_t physical, double *seg, int32_t *zero_me,
+                           hipStream_t s) {
     const int64_t blocks = (M + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(segment_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, M, pos, gpos,
-                       gap_scale, max_gap, seg, zero_me);
+                       gap_scale, max_gap, physical, seg, zero_me);
     return hipGetLastError();
 }
 

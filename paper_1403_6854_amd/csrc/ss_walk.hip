@@ -223,7 +223,7 @@ __device__ void walk_one(const WalkArgs &a, int64_t j, int d) {
             if (b > a.max_gap) {
                 stl = ST_GAP;
             } else {
-                double g = a.gpos[lo + 1] - a.gpos[lo];
+                double g = a.physical ? (double)b : a.gpos[lo + 1] - a.gpos[lo];
                 if (b > a.gap_scale) g = g * ((double)a.gap_scale / (double)b);
                 gl = g;
             }

@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
             const int64_t b = a.pos[lo + 1] - a.pos[lo];
             double gg = -1.0;
             if (b <= a.max_gap) {
-                gg = a.gpos[lo + 1] - a.gpos[lo];
+                gg = a.physical ? (double)b : a.gpos[lo + 1] - a.gpos[lo];
                 if (b > a.gap_scale) gg = gg * ((double)a.gap_scale / (double)b);
             }
             sv = gg;

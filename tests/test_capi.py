@@ -41,8 +41,10 @@ def test_default_params_and_version(lib):
     import paper_1403_6854_amd as ss
     p = ss._Params()
     lib.ss_default_params(ctypes.byref(p))
-    assert (p.ehh_cutoff, p.maf_cutoff, p.gap_scale_bp, p.max_gap_bp, p.bin_width) == \
-        (0.05, 0.05, 20000, 200000, 0.025)
+    p.physical_map = 7
+    lib.ss_default_params(ctypes.byref(p))
+    assert (p.ehh_cutoff, p.maf_cutoff, p.gap_scale_bp, p.max_gap_bp, p.bin_width, p.physical_map) == \
+        (0.05, 0.05, 20000, 200000, 0.025, 0)
     assert "gfx950" in ss.version()
 
 
@@ -66,7 +68,8 @@ def test_workspace_bytes_is_host_only(lib):
 @pytest.mark.parametrize("field,value", [
     ("ehh_cutoff", 0.0), ("ehh_cutoff", 1.5), ("ehh_cutoff", float("nan")),
     ("maf_cutoff", -0.1), ("maf_cutoff", 0.6), ("gap_scale_bp", 0),
-    ("max_gap_bp", 100), ("bin_width", 0.0), ("bin_width", 2.0)])
+    ("max_gap_bp", 100), ("bin_width", 0.0), ("bin_width", 2.0), ("physical_map", 2),
+    ("physical_map", -1)])
 def test_bad_parameters_are_rejected(lib, field, value):
     import paper_1403_6854_amd as ss
     kw = {field: value}
@@ -238,3 +241,31 @@ def test_static_scratch_entry_point_checks_before_the_device(lib):
     assert lib.ss_ihs_static(ctypes.byref(big), ctypes.byref(p), fake, fake, fake, fake, fake,
                              fake, None, None) == ss.SS_EWS
     assert b"static scratch" in lib.ss_last_error()
+
+
+def test_genome_standardize_checks_arguments_on_the_host(lib):
+    import paper_1403_6854_amd as ss
+    p = ss._cparams(None)
+    x = 0x1000
+    good = ss._StdRegion(x, x, x, x, 1000, 204, 0)
+    arr = (ss._StdRegion * 2)(good, good)
+    nb = lib.ss_genome_workspace_bytes(arr, 2, ss.OP_IHS, ctypes.byref(p))
+    assert nb > 0
+    cases = [
+        ((ss._StdRegion * 1)(ss._StdRegion(x, None, x, x, 10, 204, 0)), ss.OP_IHS),   # iHS without freq
+        ((ss._StdRegion * 1)(ss._StdRegion(x, x, x, x, 10, 1, 0)), ss.OP_IHS),      # n_haps < 2
+        ((ss._StdRegion * 1)(ss._StdRegion(None, x, x, x, 10, 204, 0)), ss.OP_IHS),  # null scores
+        ((ss._StdRegion * 1)(ss._StdRegion(x, x, x, x, -1, 204, 0)), ss.OP_IHS),    # negative size
+        ((ss._StdRegion * 1)(good), ss.OP_EHH),                                       # not a scan op
+    ]
+    for regs, op in cases:
+        assert lib.ss_genome_workspace_bytes(regs, 1, op, ctypes.byref(p)) == 0
+        assert lib.ss_genome_standardize(regs, 1, op, ctypes.byref(p), None, ctypes.c_void_p(x),
+                                         1 << 30, None) == ss.SS_EARG
+    # XPEHH needs no frequencies or haplotype counts
+    xp = (ss._StdRegion * 1)(ss._StdRegion(x, None, x, x, 10, 0, 0))
+    assert lib.ss_genome_workspace_bytes(xp, 1, ss.OP_XPEHH, ctypes.byref(p)) > 0
+    assert lib.ss_genome_standardize(arr, 2, ss.OP_IHS, ctypes.byref(p), None, ctypes.c_void_p(x),
+                                     nb - 1, None) == ss.SS_EWS
+    assert lib.ss_genome_standardize(arr, 0, ss.OP_IHS, ctypes.byref(p), None, ctypes.c_void_p(x),
+                                     nb, None) == ss.SS_EARG

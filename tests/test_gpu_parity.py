@@ -468,3 +468,47 @@ def test_xpehh_pooled_9000_haplotypes(ss, walk, kind):
     ref = oracle.xpehh(A, B, pos, gpos, params)
     check_xpehh(got, ref, "xpehh 9000 %s" % kind)
     assert (ref["status"] == 0).sum() > 200
+
+
+# ---------------------------------------------------------------------------
+# Physical-map option: EHH integrated over base pairs, gap rules unchanged
+# ---------------------------------------------------------------------------
+def _gappy(n, m, seed):
+    d = hapgen.random_haplotypes(n, m, seed, n_founders=max(2, n // 12), switch_p=0.01)
+    rng = np.random.default_rng(seed)
+    steps = rng.integers(300, 9_000, size=m)
+    steps[rng.choice(m, m // 50, replace=False)] = rng.integers(20_001, 120_000, m // 50)
+    steps[rng.choice(m, 4, replace=False)] = 250_000
+    pos = np.cumsum(steps).astype(np.int64)
+    return d, pos, pos * 1e-6
+
+
+@pytest.mark.parametrize("kind", ["ihs", "xpehh"])
+def test_physical_map(ss, walk, kind):
+    params = oracle.Params(physical_map=1)
+    if kind == "ihs":
+        d = hapgen.config_input(1)
+        say("ss_ihs physical map 204 x 22147 walk=%s" % walk)
+        got = _np(ss.ihs(_hm(ss, d.alleles, d.pos_bp, d.gpos_cm), ss.Params(**vars(params)), steps=True))
+        check_ihs(got, oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm, params), "ihs physical")
+        d, pos, gpos = _gappy(300, 2000, 9)
+        got = _np(ss.ihs(_hm(ss, d.alleles, pos, gpos), ss.Params(**vars(params)), steps=True))
+        check_ihs(got, oracle.ihs(d.alleles, pos, gpos, params), "ihs physical gaps")
+    else:
+        a, b = hapgen.config_input(2)
+        say("ss_xpehh physical map 204+210 x 22147 walk=%s" % walk)
+        got = _np(ss.xpehh(_hm(ss, a.alleles, a.pos_bp, a.gpos_cm), _hm(ss, b.alleles, a.pos_bp, a.gpos_cm),
+                           ss.Params(**vars(params)), steps=True))
+        check_xpehh(got, oracle.xpehh(a.alleles, b.alleles, a.pos_bp, a.gpos_cm, params), "xpehh physical")
+        d, pos, gpos = _gappy(260, 1500, 10)
+        e = hapgen.random_haplotypes(700, 1500, 11, n_founders=50, switch_p=0.01)
+        got = _np(ss.xpehh(_hm(ss, d.alleles, pos, gpos), _hm(ss, e.alleles, pos, gpos),
+                           ss.Params(**vars(params)), steps=True))
+        check_xpehh(got, oracle.xpehh(d.alleles, e.alleles, pos, gpos, params), "xpehh physical gaps")
+
+
+def test_ehh_physical_map(ss):
+    d, pos, gpos = _gappy(200, 800, 12)
+    dd = hapgen.HapData(d.alleles, pos, gpos)
+    for core in (5, 400, 790):
+        _ehh_case(ss, dd, core, oracle.Params(physical_map=1), cap=1024)

@@ -51,6 +51,12 @@ MUTANTS = {
     # a pooled EHH exactly at the cutoff stops the XPEHH walk (reading R2)
     "pooled_tie_stops": ("if ((double)SP / PP < p->ehh_cutoff) return OR_OK;",
                          "if ((double)SP / PP <= p->ehh_cutoff) return OR_OK;"),
+    # the physical-map option ignored, or applied after the gap scaling (R16)
+    "physical_map_ignored": ("double g = p->physical_map ? (double)b : gpos[hi] - gpos[lo];",
+                             "double g = gpos[hi] - gpos[lo];"),
+    "physical_map_unscaled": (
+        "    double g = p->physical_map ? (double)b : gpos[hi] - gpos[lo];\n    if (b > p->gap_scale_bp) g = g * ((double)p->gap_scale_bp / (double)b);",
+        "    double g = gpos[hi] - gpos[lo];\n    if (b > p->gap_scale_bp) g = g * ((double)p->gap_scale_bp / (double)b);\n    if (p->physical_map) g = (double)b;"),
     "pooled_pairs_across_cores": ("SP += (uint64_t)choose2(pt->cntA[l] + pt->cntB[l]);\n        }\n        if (tr) {\n            tr->len",
                                   "SP += (uint64_t)choose2(pt->cntA[l] + pt->cntB[l]) + (uint64_t)(pt->cntA[l] * pt->cntB[l]);\n        }\n        if (tr) {\n            tr->len"),
 }

@@ -532,3 +532,123 @@ def test_xpehh_pooled_cutoff_tie_does_not_stop():
         assert abs(Fraction(out[key][core]) - want) <= Fraction(1, 10**15) * want
     tr = oracle.xpehh_trace(A, B, pos, gpos, core, P, cap=64)
     assert int(tr["S"][0, 19, 2]) == 15 and int(tr["S"][0, 20, 2]) == 10
+
+
+# ---------------------------------------------------------------------------
+# Physical-map option (reading R16): g = physical distance in bp, gap rules
+# unchanged
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("spacing,seg_bp", [(10_000, 10_000), (20_000, 20_000), (40_000, 20_000),
+                                            (160_000, 20_000)])
+def test_physical_map_constant_curve_closed_form(spacing, seg_bp):
+    # EHH = 1 over the window: iHH is the total scaled physical distance; a
+    # gap above 20 kb counts 20,000 bp (g = b * 20000 / b)
+    w = 5
+    H, pos, gpos, core = _two_core_block(2, w, spacing, killer=True)
+    out = oracle.ihs(H, pos, gpos, oracle.Params(maf_cutoff=0.0, physical_map=1))
+    assert out["status"][core] in (OK, BIN)
+    assert out["ihh1"][core] == 2 * w * seg_bp
+    assert out["ihh0"][core] == 2 * w * seg_bp
+
+
+def test_physical_map_peel_closed_form():
+    H, pos, gpos, core = _peel(14, 11, 7_000, 0.0625)
+    out = oracle.ihs(H, pos, gpos, oracle.Params(maf_cutoff=0.0, physical_map=1))
+    for c, k in ((1, 14), (0, 11)):
+        one_side, stop = _peel_ihh_exact(k, 0.05, Fraction(7_000))
+        got = out["ihh1" if c else "ihh0"][core]
+        assert abs(Fraction(got) - 2 * one_side) <= Fraction(1, 10**15) * 2 * one_side
+        assert out["steps"][core, 0, c] == stop
+
+
+@pytest.mark.parametrize("kind", ["ihs", "xpehh"])
+def test_physical_map_equals_a_constant_rate_genetic_map(kind):
+    # gpos = pos * 2^-20: every genetic segment is the physical one times a
+    # power of two, so every iHH scales by it exactly and the scores agree
+    # bit for bit (gaps above 20 kb and above 200 kb included)
+    d = random_haplotypes(80, 600, 17, n_founders=8, switch_p=0.02)
+    rng = np.random.default_rng(5)
+    steps = rng.integers(200, 9_000, size=600)
+    steps[rng.choice(600, 20, replace=False)] = rng.integers(20_001, 60_000, 20)
+    steps[rng.choice(600, 3, replace=False)] = 250_000
+    pos = np.cumsum(steps).astype(np.int64)
+    r = 2.0 ** -20
+    gpos = pos.astype(np.float64) * r
+    phys = oracle.Params(physical_map=1)
+    if kind == "ihs":
+        g = oracle.ihs(d.alleles, pos, gpos, P)
+        p = oracle.ihs(d.alleles, pos, gpos, phys)
+        keys = ("ihh1", "ihh0")
+    else:
+        e = random_haplotypes(70, 600, 18, n_founders=8, switch_p=0.02)
+        g = oracle.xpehh(d.alleles, e.alleles, pos, gpos, P)
+        p = oracle.xpehh(d.alleles, e.alleles, pos, gpos, phys)
+        keys = ("ihhA", "ihhB")
+    np.testing.assert_array_equal(g["status"], p["status"])
+    assert (g["status"] == OK).sum() > 100 and (g["status"] == GAP).sum() > 0
+    for k in keys:
+        np.testing.assert_array_equal(g[k], p[k] * r)
+    np.testing.assert_array_equal(g["unstd"], p["unstd"])
+    np.testing.assert_array_equal(g["std"], p["std"])
+
+
+# ---------------------------------------------------------------------------
+# Genome-wide standardization over several scans (Eq. 6 and Eq. 9 across the
+# entire genome)
+# ---------------------------------------------------------------------------
+def _scans_for_genome():
+    outs = []
+    for n, m, seed in ((90, 700, 31), (150, 900, 32), (40, 300, 33)):
+        d = random_haplotypes(n, m, seed, n_founders=max(3, n // 12), switch_p=0.02)
+        outs.append(oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm, P))
+    return outs
+
+
+def test_genome_standardization_matches_numpy_over_the_concatenation():
+    outs = _scans_for_genome()
+    res, stats = oracle.genome_standardize(outs, 40)
+    u = np.concatenate([o["unstd"] for o in outs])
+    scored = np.isin(np.concatenate([o["status"] for o in outs]), (OK, BIN))
+    bins = np.concatenate([o["bin"] for o in outs])
+    z = np.concatenate([r["std"] for r in res])
+    st = np.concatenate([r["status"] for r in res])
+    checked = 0
+    for b in range(40):
+        m = scored & (bins == b)
+        assert stats["n"][b] == m.sum()
+        if m.sum() < 2:
+            assert np.all(st[m] == BIN) and np.all(np.isnan(z[m]))
+            continue
+        v = u[m]
+        np.testing.assert_allclose(z[m], (v - v.mean()) / v.std(ddof=1), rtol=1e-12, atol=1e-12)
+        assert np.all(st[m] == OK)
+        checked += 1
+    assert checked > 10
+    assert np.all(np.isnan(z[~scored])) and np.array_equal(st[~scored],
+                                                          np.concatenate([o["status"] for o in outs])[~scored])
+
+
+@pytest.mark.parametrize("kind", ["ihs", "xpehh"])
+def test_genome_standardization_of_pieces_equals_the_whole(kind):
+    # one scan's scores cut into pieces, each standardized on its own (small
+    # pieces leave bins with fewer than 2 loci: status BIN), then standardized
+    # together, give exactly the standardization of the whole scan
+    d = random_haplotypes(120, 1500, 41, n_founders=10, switch_p=0.02)
+    if kind == "ihs":
+        whole = oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm, P)
+        nbins = 40
+    else:
+        e = random_haplotypes(100, 1500, 42, n_founders=9, switch_p=0.02)
+        whole = oracle.xpehh(d.alleles, e.alleles, d.pos_bp, d.gpos_cm, P)
+        whole["bin"] = np.zeros(1500, dtype=np.int32)
+        nbins = 1
+    pre = np.where(whole["status"] == BIN, OK, whole["status"]).astype(np.int8)
+    k = int(np.flatnonzero(pre[600:] == OK)[0]) + 600     # a one-locus piece: BIN on its own
+    pieces = []
+    for a, b in ((0, 37), (37, 600), (600, k), (k, k + 1), (k + 1, 1500)):
+        r = oracle.standardize(whole["unstd"][a:b], pre[a:b], whole["bin"][a:b], nbins)
+        pieces.append({"unstd": whole["unstd"][a:b], "status": r["status"], "bin": whole["bin"][a:b]})
+    assert any((p["status"] == BIN).any() for p in pieces)
+    res, _ = oracle.genome_standardize(pieces, nbins)
+    np.testing.assert_array_equal(np.concatenate([r["std"] for r in res]), whole["std"])
+    np.testing.assert_array_equal(np.concatenate([r["status"] for r in res]), whole["status"])
