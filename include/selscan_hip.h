@@ -375,6 +375,16 @@ int ss_set_graph(int on);
 int ss_graph_clear(void);
 
 /*
+ * ss_set_mask_skip -- tuning of the bitmask walk (process-wide): a batch of
+ * 64 markers that starts with at most max_classes live classes (0 .. 64;
+ * default 32) first tests every marker against every class at once, and
+ * refines only the markers that cut a class (the others change no class and
+ * no sum); 0 refines every marker.  Results are identical for every setting.
+ * Errors: SS_EARG outside [0, 64].
+ */
+int ss_set_mask_skip(int max_classes);
+
+/*
  * ss_set_mask_lanes -- tuning of the bitmask walk kernel (process-wide):
  * how many lanes of a wave hold one class (1, 2, 4 or 8; each lane holds
  * words_per_class / lanes of its mask), or 0 for the default.  More lanes per

@@ -108,6 +108,7 @@ def lib():
         L.ss_genome_standardize.argtypes = [SR, ctypes.c_int32, ctypes.c_int32, PR, P, P, sz, P]
         L.ss_set_walk_kernel.argtypes = [ctypes.c_int]
         L.ss_set_mask_lanes.argtypes = [ctypes.c_int]
+        L.ss_set_mask_skip.argtypes = [ctypes.c_int]
         L.ss_timing_enable.argtypes = [ctypes.c_int]
         L.ss_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                      ctypes.c_int]
@@ -125,7 +126,7 @@ def lib():
         L.ss_set_group_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
         L.ss_get_group_tuning.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32)]
-        for f in ("ss_pack", "ss_ehh", "ss_ihs", "ss_ihs_static", "ss_genome_standardize", "ss_xpehh", "ss_set_walk_kernel", "ss_set_mask_lanes",
+        for f in ("ss_pack", "ss_ehh", "ss_ihs", "ss_ihs_static", "ss_genome_standardize", "ss_xpehh", "ss_set_walk_kernel", "ss_set_mask_lanes", "ss_set_mask_skip",
                   "ss_timing_enable", "ss_timing_read", "ss_scan_batch", "ss_get_batch_config",
                   "ss_set_batch_config", "ss_autotune_batch", "ss_set_graph", "ss_graph_clear",
                   "ss_get_group_tuning", "ss_set_group_tuning"):
@@ -598,6 +599,12 @@ def graph_clear():
 def set_mask_lanes(lanes_per_class: int):
     """Lanes per class of the bitmask walk (1, 2, 4, 8; 0 = default)."""
     _check(lib().ss_set_mask_lanes(int(lanes_per_class)))
+
+
+def set_mask_skip(max_classes: int):
+    """Bitmask walk: batches with at most ``max_classes`` live classes refine
+    only the markers that cut a class (0 .. 64; 0 refines every marker)."""
+    _check(lib().ss_set_mask_skip(int(max_classes)))
 
 
 def timing_enable(on: bool = True):

@@ -184,6 +184,7 @@ hipEvent_t take_event() {
 
 int g_walk_kind = ss::WALK_AUTO;
 int g_mask_lpc = 0;   // lanes per class of the bitmask walk; 0 = default
+int g_mask_skip = 32;       // bitmask walk: most class slots for which markers that cut none are skipped
 ss_batch_config g_bcfg = {64, 4096, 1, 0, 0, 1, 0, 1024, 16, 1024, 0};
 bool g_graph_on = false;
 bool g_capturing = false;   // timing events are not recorded into graphs
@@ -490,7 +491,9 @@ int prepare_scan(const Scan &sc, const ss_params *p, hipStream_t s) {
 int walk_direct(const Scan &sc, hipStream_t s) {
     const ss::WalkArgs &a = sc.args;
     if (sc.route == RT_MASK) {
-        SS_HIP(ss::launch_mask_walk(a, sc.mode, g_mask_lpc, a.M, s));
+        ss::WalkArgs m = a;
+        m.skip_classes = g_mask_skip;
+        SS_HIP(ss::launch_mask_walk(m, sc.mode, g_mask_lpc, a.M, s));
         SS_HIP(ss::launch_walk_list(a, sc.mode, kRedoBlocks, s));
     } else {
         SS_HIP(ss::launch_walk(a, sc.mode, false, a.M, s));
@@ -866,8 +869,32 @@ std::string graph_key(const ss_scan_request *reqs, int32_t n, const ss_params *p
     (void)hipGetDevice(&dev);
     put(k, dev);
     put(k, n);
-    k.append((const char *)reqs, sizeof(ss_scan_request) * (size_t)n);
-    put(k, *p);
+    // field by field: the structs' padding bytes are not part of the key
+    for (int32_t i = 0; i < n; ++i) {
+        const ss_scan_request &r = reqs[i];
+        put(k, r.op);
+        for (const ss_hapmat *h : {&r.a, &r.b}) {
+            put(k, h->bits);
+            put(k, h->n_haps);
+            put(k, h->n_sites);
+            put(k, h->words_per_site);
+            put(k, h->pos_bp);
+            put(k, h->gpos_cm);
+        }
+        put(k, r.d_ihh_x);
+        put(k, r.d_ihh_y);
+        put(k, r.d_unstd);
+        put(k, r.d_std);
+        put(k, r.d_freq);
+        put(k, r.d_status);
+        put(k, r.d_steps);
+    }
+    put(k, p->ehh_cutoff);
+    put(k, p->maf_cutoff);
+    put(k, p->gap_scale_bp);
+    put(k, p->max_gap_bp);
+    put(k, p->bin_width);
+    put(k, p->physical_map);
     put(k, d_ws);
     put(k, ws_bytes);
     put(k, stream);
@@ -875,6 +902,7 @@ std::string graph_key(const ss_scan_request *reqs, int32_t n, const ss_params *p
     put(k, g_gtune);
     put(k, g_walk_kind);
     put(k, g_mask_lpc);
+    put(k, g_mask_skip);
     return k;
 }
 
@@ -1468,6 +1496,12 @@ int ss_graph_clear(void) {
 int ss_set_walk_kernel(int kind) {
     if (kind < ss::WALK_AUTO || kind > ss::WALK_WIDE) return fail(SS_EARG, "unknown walk kernel");
     g_walk_kind = kind;
+    return SS_OK;
+}
+
+int ss_set_mask_skip(int max_classes) {
+    if (max_classes < 0 || max_classes > 64) return fail(SS_EARG, "max_classes must be in [0, 64]");
+    g_mask_skip = max_classes;
     return SS_OK;
 }
 

@@ -55,6 +55,9 @@ struct WalkArgs {
     // registers): entries 2 * site + direction, redone by the class-id walk
     int32_t *redo_list;         // [2 M]
     int32_t *redo_count;        // [1], zeroed by the segment pass
+    // bitmask walk: batches with at most this many class slots test all their
+    // markers at once and refine only those that cut a class
+    int32_t skip_classes;
 };
 
 struct WalkShape {

@@ -104,13 +104,15 @@ __device__ __forceinline__ uint32_t stop_threshold(uint32_t P, double cutoff, in
     return (uint32_t)__builtin_amdgcn_readlane((uint32_t)s, top);
 }
 
-// Waves per SIMD the compiler is held to: 4-word iHS walks (129-256
-// haplotypes) take 72 VGPRs bounded to 7 waves per SIMD, without spills (5
-// waves unbounded); the 204-haplotype walk runs 0.306 ms against 0.337 ms
-// unbounded.  Wider masks spill heavily under a bound, and the pooled walks
-// were not measured bounded: they keep the default.
+// Waves per SIMD the compiler is held to, the most that fit without spills:
+// 4-word iHS walks (129-256 haplotypes) 6 waves in 80 VGPRs (bounded to 7
+// they spill 24-44 bytes a lane and run slower: the 204-haplotype walk takes
+// 0.265 against 0.270 ms), 8-word iHS walks 4 waves in 128 VGPRs (3
+// unbounded); the pooled walks fit 4 or more waves unbounded.
 template <int MODE, int W>
-constexpr int mask_waves_per_eu() { return MODE == MODE_CORE && W == 4 ? 7 : 1; }
+constexpr int mask_waves_per_eu() {
+    return MODE == MODE_CORE && W == 4 ? 6 : (MODE == MODE_CORE && W == 8 ? 4 : 1);
+}
 
 // W: mask words per class (pooled: A's words, then B's); LPC: lanes per
 // class; NR: rows of 64 / LPC classes (capacity NR * 64 / LPC classes).
@@ -126,19 +128,24 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
     constexpr int kUnionWords = kStageWords > PCAP / 2 ? kStageWords : PCAP / 2;
     uint64_t *rowbuf = lds64;                  // [64][W] rows of the staged markers
     uint64_t *keys = rowbuf;                   // [64 W] 64-marker keys (pairwise phase)
-    uint16_t *mem = (uint16_t *)rowbuf;        // [64 W] members of one class (pair-list build)
     uint64_t *stage = rowbuf + 64 * W;         // [NR * CPR][W + 1] class records
-    uint32_t *pairs = (uint32_t *)stage;       // [PCAP] a | b << 16 (pairwise phase)
+    uint32_t *pairs = (uint32_t *)stage;       // [PCAP] a | b << 16, member indices (pairwise phase)
     uint32_t *hist = (uint32_t *)(stage + kUnionWords);   // [64] splits per marker
+    uint16_t *memb = (uint16_t *)(hist + 64);  // [64 W] haplotypes of the pair list's members
 
     const int lane = threadIdx.x;
     const int q = lane / LPC;     // class slot within a row
     const int g = lane % LPC;     // word group within the class
     const bool leader = g == 0;
-    const int d = blockIdx.y;
+    // one workgroup per (site, direction[, core]), site-major: the walks of a
+    // site are neighbours in the grid, so they start together and share the
+    // site's rows in cache, and a run of long walks in the middle of a region
+    // (a sweep) starts in the middle of the launch, not in its last quarter
+    constexpr int kPerSite = MODE == MODE_CORE ? 4 : 2;
+    const int d = (int)(blockIdx.x % 2u);
     const int dir = d == 0 ? 1 : -1;
-    const int core = blockIdx.z;  // CORE mode: the allele whose carriers this wave walks
-    const int64_t j = a.site0 + (int64_t)blockIdx.x;
+    const int core = MODE == MODE_CORE ? (int)((blockIdx.x / 2u) % 2u) : 0;   // CORE: the allele this wave walks
+    const int64_t j = a.site0 + (int64_t)(blockIdx.x / (unsigned)kPerSite);
     if (j >= a.M) return;
     if (a.walk_flag && !a.walk_flag[j]) return;
     const int Wused = MODE == MODE_CORE ? a.WA : a.WA + a.WB;
@@ -202,20 +209,9 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
         inr = kb >= 0 && kb < a.M;
 #pragma unroll
         for (int w = 0; w < W; ++w) rv[w] = (rows && inr) ? rowword(w, kb) : 0ull;
-        if (!inr) {
-            sv = 0.0;
-        } else if (a.seg) {
-            sv = a.seg[dir > 0 ? kb : kb + 1];
-        } else {
-            const int64_t lo = dir > 0 ? kb - 1 : kb;
-            const int64_t b = a.pos[lo + 1] - a.pos[lo];
-            double gg = -1.0;
-            if (b <= a.max_gap) {
-                gg = a.physical ? (double)b : a.gpos[lo + 1] - a.gpos[lo];
-                if (b > a.gap_scale) gg = gg * ((double)a.gap_scale / (double)b);
-            }
-            sv = gg;
-        }
+        // segment lengths with the gap rules applied come from the scan's
+        // segment pass (a.seg is always set for this kernel)
+        sv = inr ? a.seg[dir > 0 ? kb : kb + 1] : 0.0;
     };
     uint64_t pf_rows[W];
     double pf_seg;
@@ -252,6 +248,17 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
     int32_t steps = 0;
     int32_t status = ST_OK;
     int step = 0;
+    // The sums after the last marker refined (S, or S_A | S_B << 16 and S_B
+    // when they do not fit): a marker that cuts no live class leaves them as
+    // they are.
+    uint32_t curS = 0u, curSB = 0u;
+    if (MODE == MODE_CORE) {
+        curS = act ? choose2(core ? n1a : n0a) : 0u;
+    } else {
+        const uint32_t sa0 = choose2(n0a) + choose2(n1a), sb0 = choose2(n0b) + choose2(n1b);
+        curS = pack16 ? (sa0 | (sb0 << 16)) : sa0;
+        curSB = pack16 ? 0u : sb0;
+    }
 
     // Dense re-indexing of the live classes through LDS, with the second
     // child of every split appended after them.
@@ -312,6 +319,7 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
     bool pmode = false;
     bool overflow = false;   // the classes outgrew the wave: the walk is redone elsewhere
     int npairs = 0;
+    int nmem = 0;            // members of the pair list (memb), the haplotypes whose keys a pass reads
     uint32_t s_now = 0;   // S after the last marker processed
     if (MODE == MODE_CORE) s_now = choose2(core ? n1a : n0a);
     const bool can_pair = PCAP > 0 && a.hbits != nullptr;
@@ -320,6 +328,7 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
     // masks are read from the registers of the lanes holding them.
     auto build_pairs = [&]() {
         npairs = 0;
+        nmem = 0;
         for (int c = 0; c < kend; ++c) {
             const int rr = c / CPR, qq = c % CPR;
             uint32_t cnt = 0;
@@ -335,35 +344,49 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
                 for (int r = 0; r < NR; ++r)
                     if (r == rr) mw = readlane64(m[r][w % WPL], qq * LPC + w / WPL);
                 const uint64_t below = lane ? (mw & ((1ull << lane) - 1ull)) : 0ull;
-                if ((mw >> lane) & 1ull) mem[sz + __popcll(below)] = (uint16_t)(64 * w + lane);
+                if ((mw >> lane) & 1ull) memb[nmem + sz + __popcll(below)] = (uint16_t)(64 * w + lane);
                 sz += __popcll(mw);
             }
-            __syncthreads();
+            // the class's members are entries nmem .. nmem + sz - 1 of the
+            // member list; its pairs refer to them by entry
             for (int y = 1; y < sz; ++y) {
-                const uint32_t my = mem[y];
+                const uint32_t my = (uint32_t)(nmem + y);
                 const int base = npairs + y * (y - 1) / 2;
                 for (int x0 = 0; x0 < y; x0 += 64) {
                     const int x = x0 + lane;
-                    if (x < y) pairs[base + x] = (uint32_t)mem[x] | (my << 16);
+                    if (x < y) pairs[base + x] = (uint32_t)(nmem + x) | (my << 16);
                 }
             }
             npairs += sz * (sz - 1) / 2;
+            nmem += sz;
             __syncthreads();
         }
     };
 
     // Alleles of haplotype h at the 64 markers from k0 onwards in the walk's
-    // direction, bit i = marker k0 + dir * i.
-    auto key_of = [&](int h, int64_t k0) -> uint64_t {
+    // direction, bit i = marker k0 + dir * i: the two words of the
+    // haplotype-major row that hold them (zero outside the row) ...
+    auto key_words = [&](int h, int64_t k0, uint64_t &lo, uint64_t &hi) {
         const uint64_t *row = a.hbits + (size_t)h * a.mwp;
         const int64_t b = dir > 0 ? k0 + 64 : k0 + 1;   // padded index of the lowest marker
-        const int64_t wi = b >> 6;
+        const int64_t wi = b >> 6;                       // (floor division)
+        lo = wi >= 0 && wi < a.mwp ? row[wi] : 0ull;
+        hi = wi + 1 >= 0 && wi + 1 < a.mwp ? row[wi + 1] : 0ull;
+    };
+    // ... and the key cut from them
+    auto key_join = [&](int64_t k0, uint64_t lo, uint64_t hi) -> uint64_t {
+        const int64_t b = dir > 0 ? k0 + 64 : k0 + 1;
         const int sh = (int)(b & 63);
-        const uint64_t lo = wi < a.mwp ? row[wi] : 0ull;
-        const uint64_t hi = wi + 1 < a.mwp ? row[wi + 1] : 0ull;
         const uint64_t x = sh ? ((lo >> sh) | (hi << (64 - sh))) : lo;
         return dir > 0 ? x : __builtin_bitreverse64(x);
     };
+    auto key_of = [&](int h, int64_t k0) -> uint64_t {
+        uint64_t lo, hi;
+        key_words(h, k0, lo, hi);
+        return key_join(k0, lo, hi);
+    };
+    uint64_t pk_lo = 0ull, pk_hi = 0ull;   // member `lane`'s words for the next pass
+    int pk_step = -1;                      // the pass they were loaded for
 
     if (can_pair && act && s_now <= (uint32_t)PCAP) {
         build_pairs();
@@ -398,12 +421,56 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
         const int32_t abort_st = abort_mask ? (int32_t)__builtin_amdgcn_readlane(stl, nb) : ST_OK;
         __syncthreads();
 
+        // ---- markers that cut no class: with at most a.skip_classes classes
+        // alive, lane i tests marker i against every class (a class is cut
+        // when some but not all of its members carry allele 1); markers that
+        // cut none leave the partition and the sums unchanged and are not
+        // refined.  A marker that cuts no class of the batch's first partition
+        // cuts none of its refinements either.
+        // (The pooled walks of XPEHH end within a few markers of the first
+        // splits, so they refine every marker: the test's registers cost
+        // them a wave per SIMD and gain nothing.)
+        uint64_t cutm = ~0ull;
+        if (MODE == MODE_CORE && kend <= a.skip_classes) {
+            bool cut = false;
+            for (int c = 0; c < kend; ++c) {
+                const int rr = c / CPR, qq = c % CPR;
+                // a class is cut when it has members with allele 1 and members
+                // with allele 0 (an empty slot has neither)
+                bool one = false, zero = false;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    uint64_t mw = 0;
+#pragma unroll
+                    for (int r = 0; r < NR; ++r)
+                        if (r == rr) mw = readlane64(m[r][w % WPL], qq * LPC + w / WPL);
+                    const uint64_t rw = rowbuf[lane * W + w];
+                    one = one || (mw & rw) != 0ull;
+                    zero = zero || (mw & ~rw) != 0ull;
+                }
+                cut = cut || (one && zero);
+            }
+            cutm = __ballot(cut);
+        }
+
         uint32_t sb = 0, sbB = 0;   // lane i: step i's S (A|B packed, or A) and S_B
         int nterm = 0;              // trapezoid terms of this batch
         int i = 0;
         bool to_pairs = false;
         for (; i < 64 && act; ++i) {
             if (i == nb) { status = abort_st; break; }
+            if (!((cutm >> i) & 1ull)) {
+                // markers i .. nxt-1 cut no class: the sums stay (above the
+                // cutoff and the pair capacity) and each adds its term
+                const uint64_t rest = cutm >> i;
+                int nxt = rest ? i + (int)__builtin_ctzll(rest) : 64;
+                if (nxt > nb) nxt = nb;
+                if (lane >= i && lane < nxt) { sb = curS; sbB = curSB; }
+                steps += nxt - i;
+                nterm = nxt;
+                i = nxt - 1;
+                continue;
+            }
             // the marker's row words, read from LDS where they are used: a
             // copy of the next marker's words held in registers cost more
             // (spills at 4 words, fewer waves at 8) than the LDS latency
@@ -485,6 +552,8 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
 
             // ---- record the step's sums and apply the stop rule -----------
             if (lane == i) { sb = S; sbB = SB; }
+            curS = S;
+            curSB = SB;
             steps += 1;
             const uint32_t Sst = MODE == MODE_CORE ? S : SP;
             if (Sst <= thr) act = false; else nterm = i + 1;
@@ -566,8 +635,16 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
         int i = 0;
         {
             // ---- one pass over the pair list covers the next 64 markers ----
+            // keys of the pair list's members only; member `lane`'s words were
+            // loaded during the previous pass
             const int64_t k0 = j + (int64_t)dir * (int64_t)(step + 1);
-            for (int h = lane; h < a.nA; h += 64) keys[h] = key_of(h, k0);
+            if (lane < nmem) {
+                if (pk_step != step) key_words((int)memb[lane], k0, pk_lo, pk_hi);
+                keys[lane] = key_join(k0, pk_lo, pk_hi);
+            }
+            for (int h = lane + 64; h < nmem; h += 64) keys[h] = key_of((int)memb[h], k0);
+            if (lane < nmem) key_words((int)memb[lane], k0 + (int64_t)dir * 64, pk_lo, pk_hi);
+            pk_step = step + 64;
             hist[lane] = 0u;
             __syncthreads();
             int wpos = 0;
@@ -664,7 +741,9 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
 
 template <int MODE, int W, int LPC>
 hipError_t launch_nr(const WalkArgs &a, int nr, size_t lds, int64_t n_blocks, hipStream_t s) {
-    dim3 grid((unsigned)n_blocks, 2u, MODE == MODE_CORE ? 2u : 1u);
+    const int64_t blocks = n_blocks * (MODE == MODE_CORE ? 4 : 2);
+    if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks);
     // one register row of classes (mask_walk_shape); walks that need more
     // are listed for the class-id walk
     if (nr != 1) return hipErrorInvalidValue;
@@ -712,7 +791,8 @@ MaskShape mask_walk_shape(int32_t nA, int32_t nB, int mode, int lpc) {
     const size_t stage_words = (size_t)sh.rows * cpr * (sh.words + 1);
     const size_t union_words = stage_words > (size_t)sh.pair_cap / 2 ? stage_words
                                                                       : (size_t)sh.pair_cap / 2;
-    sh.lds = ((size_t)64 * sh.words + union_words) * sizeof(uint64_t) + 64 * sizeof(uint32_t);
+    sh.lds = ((size_t)64 * sh.words + union_words) * sizeof(uint64_t) + 64 * sizeof(uint32_t) +
+             (size_t)64 * sh.words * sizeof(uint16_t);   // member list of the pair list
     sh.ok = true;
     return sh;
 }
@@ -723,7 +803,7 @@ bool mask_walk_supported(int32_t nA, int32_t nB, int mode) {
 
 hipError_t launch_mask_walk(const WalkArgs &a, int mode, int lpc, int64_t n_blocks, hipStream_t s) {
     const MaskShape sh = mask_walk_shape(a.nA, a.nB, mode, lpc);
-    if (!sh.ok) return hipErrorInvalidValue;
+    if (!sh.ok || !a.seg) return hipErrorInvalidValue;
     if (n_blocks <= 0) return hipSuccess;
     const bool core = mode == MODE_CORE;
     switch (sh.words) {

@@ -512,3 +512,34 @@ def test_ehh_physical_map(ss):
     dd = hapgen.HapData(d.alleles, pos, gpos)
     for core in (5, 400, 790):
         _ehh_case(ss, dd, core, oracle.Params(physical_map=1), cap=1024)
+
+
+@pytest.mark.parametrize("lpc", [1, 4])
+def test_mask_skip_changes_no_result(ss, lpc):
+    """Batches of the bitmask walk that refine only the markers cutting a
+    class give the same results as refining every marker (iHS with the
+    chromosome-22 sweep, a 400-haplotype scan, and XPEHH)."""
+    d = hapgen.config_input(1)
+    e = hapgen.random_haplotypes(400, 2500, 77, n_founders=30, switch_p=0.004)
+    a, b = hapgen.config_input(2)
+    say("mask skip on/off, lanes %d" % lpc)
+    hd, he = _hm(ss, d.alleles, d.pos_bp, d.gpos_cm), _hm(ss, e.alleles, e.pos_bp, e.gpos_cm)
+    hb = _hm(ss, b.alleles, a.pos_bp, a.gpos_cm)
+    ss.set_walk_kernel(2)
+    ss.set_mask_lanes(lpc)
+    got = {}
+    try:
+        for skip in (0, 8, 32, 64):
+            ss.set_mask_skip(skip)
+            got[skip] = [_np(ss.ihs(hd, steps=True)), _np(ss.ihs(he, steps=True)),
+                         _np(ss.xpehh(hd, hb, steps=True))]
+    finally:
+        ss.set_mask_skip(32)
+        ss.set_mask_lanes(0)
+        ss.set_walk_kernel(0)
+    for skip in (8, 32, 64):
+        for x, y in zip(got[skip], got[0]):
+            for k in y:
+                np.testing.assert_array_equal(x[k], y[k], err_msg="skip %d %s" % (skip, k))
+    check_ihs(got[32][0], oracle.ihs(d.alleles, d.pos_bp, d.gpos_cm), "skip chr22")
+    check_xpehh(got[32][2], oracle.xpehh(a.alleles, b.alleles, a.pos_bp, a.gpos_cm), "skip xpehh")
