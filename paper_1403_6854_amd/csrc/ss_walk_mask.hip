@@ -80,14 +80,31 @@ __host__ __device__ constexpr int mask_pair_cap(int W) {
     return W >= 8 ? 1024 : (W == 4 ? 256 : 512);
 }
 
-// Inclusive prefix sum over the 64 lanes (once per 64-marker pass).
-__device__ __forceinline__ uint32_t wave_prefix(uint32_t v, int lane) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t t = __shfl_up(v, off, 64);
-        if (lane >= off) v += t;
-    }
+// Inclusive prefix sum over the 64 lanes (once per 64-marker pass), in DPP
+// register moves instead of LDS permutes: within each row of 16 lanes by
+// shifts of 1, 2, 4 and 8 (lanes shifted in from outside the row read 0), then
+// row 0's total broadcast into row 1 and row 2's into row 3, then the total
+// of rows 0-1 into rows 2-3.
+__device__ __forceinline__ uint32_t wave_prefix(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
     return v;
+}
+
+// The value of lane - 1 (lane 0 gets `first`): a DPP wave shift instead of an
+// LDS permute.
+__device__ __forceinline__ double lane_before(double v, double first) {
+    const uint64_t x = __builtin_bit_cast(uint64_t, v);
+    const uint64_t f = __builtin_bit_cast(uint64_t, first);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)f, (int)(uint32_t)x, 0x138,
+                                                              0xF, 0xF, false);   // wave_shr:1
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(f >> 32), (int)(uint32_t)(x >> 32),
+                                                              0x138, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 // Largest S in [0, P] with (double)S / (double)P < cutoff (P >= 1), found by
@@ -572,8 +589,7 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
             const double g64 = gl;
             if (MODE == MODE_CORE) {
                 const double e = (double)sb / PA;
-                double prev = __shfl_up(e, 1, 64);
-                if (lane == 0) prev = epA;
+                const double prev = lane_before(e, epA);
                 const double term = 0.5 * (prev + e) * g64;
                 for (int t = 0; t < nterm; ++t) ihhA += readlane_f64(term, t);
                 epA = readlane_f64(e, nterm - 1);
@@ -582,9 +598,8 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
                 const uint32_t sB = pack16 ? (sb >> 16) : sbB;
                 const double eA = (double)sA / PA;
                 const double eB = (double)sB / PB;
-                double pA = __shfl_up(eA, 1, 64);
-                double pB = __shfl_up(eB, 1, 64);
-                if (lane == 0) { pA = epA; pB = epB; }
+                const double pA = lane_before(eA, epA);
+                const double pB = lane_before(eB, epB);
                 const double tA = 0.5 * (pA + eA) * g64;
                 const double tB = 0.5 * (pB + eB) * g64;
                 for (int t = 0; t < nterm; ++t) {
@@ -662,7 +677,7 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
                 wpos += __popcll(sm);
             }
             __syncthreads();
-            const uint32_t si = s_now - wave_prefix(hist[lane], lane);   // S after step `lane`
+            const uint32_t si = s_now - wave_prefix(hist[lane]);   // S after step `lane`
             const uint64_t valid = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
             const uint64_t stopm = __ballot(si <= thr) & valid;
             if (stopm) {
@@ -690,8 +705,7 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
             const double g64 = gl;
             if (MODE == MODE_CORE) {
                 const double e = (double)sb / PA;
-                double prev = __shfl_up(e, 1, 64);
-                if (lane == 0) prev = epA;
+                const double prev = lane_before(e, epA);
                 const double term = 0.5 * (prev + e) * g64;
                 for (int t = 0; t < nterm; ++t) ihhA += readlane_f64(term, t);
                 epA = readlane_f64(e, nterm - 1);
@@ -700,9 +714,8 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
                 const uint32_t sB = pack16 ? (sb >> 16) : sbB;
                 const double eA = (double)sA / PA;
                 const double eB = (double)sB / PB;
-                double pA = __shfl_up(eA, 1, 64);
-                double pB = __shfl_up(eB, 1, 64);
-                if (lane == 0) { pA = epA; pB = epB; }
+                const double pA = lane_before(eA, epA);
+                const double pB = lane_before(eB, epB);
                 const double tA = 0.5 * (pA + eA) * g64;
                 const double tB = 0.5 * (pB + eB) * g64;
                 for (int t = 0; t < nterm; ++t) {
