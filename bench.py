@@ -41,6 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 int32 lanes/clk x 2.4 GHz
+PROXY_OPS_PER_CELL = 51.0 / 256.0           # int32 lane-ops per haplotype-cell of the refinement
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_traffic.json")
 WALK_SRC = os.path.join(ROOT, "paper_1403_6854_amd", "csrc", "ss_walk_mask.hip")
@@ -171,6 +172,80 @@ def bench_batched(ss, torch, dev, autotune: bool = True, reps: int = 3):
     return res
 
 
+# The paper's runtime data sets (Sec. 2.1, Table 1; Sec. 2.2, Table 2): haplotypes
+# and SNPs over a 4 Mbp region.  Stand-ins from the copying model: 40 founders,
+# the per-bp switch rate of the chromosome-22 workload (0.003 per SNP at 1.58 kb
+# per SNP), so that a walk's length in markers grows with the SNP density.
+SCALING_IHS = [("IHS250", 250, 9625), ("IHS500", 500, 10646), ("IHS1000", 1000, 11655),
+               ("IHS2000", 2000, 12724)]
+SCALING_XP = [("XP250", 125, 12920), ("XP500", 250, 14989), ("XP1000", 500, 17142),
+              ("XP2000", 1000, 19567)]
+SCALING_DENSITY = [2500, 5000, 10000, 20000, 40000]   # SNPs over 4 Mbp at 500 haplotypes
+SCALING_BP = 4_000_000
+SWITCH_PER_BP = 0.003 / 1580.0
+
+
+def bench_scaling(ss, torch, dev, reps: int = 10):
+    """GPU time of whole scans against haplotypes N and SNP density D at the
+    paper's runtime shapes, with the least-squares exponents of
+    time ~ N^b D^c (the paper states O(N D^2), Sec. 3)."""
+    import hapgen
+
+    def region(n, m, seed, nb=0):
+        s = min(0.5, SWITCH_PER_BP * SCALING_BP / m)
+        a = hapgen.copying_model(n, m, SCALING_BP, 40, s, seed)
+        b = None
+        if nb:
+            rng = np.random.default_rng(seed + 1)
+            b = hapgen.copy_haplotypes(rng, hapgen.derive_founders(rng, a.founders, 0.8), nb, s, 0.001)
+        return a, b
+
+    def run(name, n, m, seed, nb=0):
+        a, b = region(n, m, seed, nb)
+        pos = torch.from_numpy(a.pos_bp).to(dev)
+        gpos = torch.from_numpy(a.gpos_cm).to(dev)
+        ha = ss.hapmat(torch.from_numpy(a.alleles).to(dev), pos, gpos)
+        hb = ss.hapmat(torch.from_numpy(b).to(dev), pos, gpos) if nb else None
+        op = ss.OP_XPEHH if nb else ss.OP_IHS
+        ws = torch.empty(ss.workspace_bytes(op, ha, hb) + 256, dtype=torch.uint8, device=dev)
+        scan = (lambda out: ss.xpehh(ha, hb, steps=True, ws=ws, out=out, validate=False)) if nb else \
+               (lambda out: ss.ihs(ha, steps=True, ws=ws, out=out, validate=False))
+        out = scan(None)
+        el, walk_ms, _ = time_scan(lambda: scan(out), 2, reps, ss, torch)
+        st = out["status"].cpu().numpy()
+        stp = out["steps"].cpu().numpy().astype(np.int64)
+        if nb:
+            loci = int(st.size)
+            w = int(stp.sum()) * (n + nb)
+        else:
+            loci = int((st != 1).sum())
+            n1 = a.alleles.sum(axis=1).astype(np.int64)
+            nc = np.stack([n - n1, n1], axis=1)[:, None, :]
+            w = int((stp * nc).sum())
+        ms = el / reps * 1e3
+        return {"shape": name, "n_haps": n + nb, "n_sites": m, "snps_per_kb": round(m / 4000.0, 3),
+                "scan_ms": round(ms, 4), "walk_ms": round(walk_ms, 4), "core_loci": loci,
+                "core_loci_per_s": round(loci / (ms * 1e-3), 1), "work_cells": w,
+                "mean_markers_per_walk": round(float(stp.sum()) / max(1, (stp > 0).sum()), 1)}
+
+    log("scaling: paper shapes and a density sweep")
+    ihs = [run(nm, n, m, 3000 + i) for i, (nm, n, m) in enumerate(SCALING_IHS)]
+    xp = [run(nm, n, m, 3100 + i, nb=n) for i, (nm, n, m) in enumerate(SCALING_XP)]
+    dens = [run("D%d" % m, 500, m, 3200 + i) for i, m in enumerate(SCALING_DENSITY)]
+    pts = ihs + dens
+    X = np.stack([np.ones(len(pts)), np.log([p["n_haps"] for p in pts]),
+                  np.log([p["snps_per_kb"] for p in pts])], axis=1)
+    fit = {}
+    for key in ("scan_ms", "walk_ms"):
+        coef, *_ = np.linalg.lstsq(X, np.log([p[key] for p in pts]), rcond=None)
+        fit[key] = {"exponent_N": round(float(coef[1]), 3), "exponent_D": round(float(coef[2]), 3)}
+    cw, *_ = np.linalg.lstsq(X, np.log([p["work_cells"] for p in pts]), rcond=None)
+    fit["work_cells"] = {"exponent_N": round(float(cw[1]), 3), "exponent_D": round(float(cw[2]), 3)}
+    return {"region_bp": SCALING_BP, "founders": 40, "switch_per_bp": SWITCH_PER_BP,
+            "ihs": ihs, "xpehh": xp, "density_n500": dens,
+            "fit_ihs": fit, "paper_claim": "O(N D^2) (Sec. 3)"}
+
+
 def bench_served(ss, torch, dev, args):
     """The served request stream: continuous batching vs back to back."""
     import hapgen
@@ -270,6 +345,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-scaling", action="store_true")
+    ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
     ap.add_argument("--serve-streams", type=int, default=4)
@@ -278,6 +355,8 @@ def main():
                          "from the batch's first by more than this factor (0: off)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default persistent-walk configuration (profiling runs)")
+    ap.add_argument("--micro-only", action="store_true",
+                    help="only run the measurement kernels (achievable peaks) and print them")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -289,6 +368,13 @@ def main():
             torch.mul(x, 1, out=y)       # reads and writes calibrate_copy_mb MiB each
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8}))
+        return
+    if args.micro_only:
+        import torch
+        import hapgen
+        import paper_1403_6854_amd as ss
+        d = hapgen.config_input(1)
+        print(json.dumps(ss.micro(ss.pack(torch.from_numpy(d.alleles).cuda()))))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
@@ -352,16 +438,34 @@ def main():
     value_x = M / (elx / args.steps)
 
     # --- roofline of the dominant kernel (the iHS walk) ----------------------
-    achieved = W / (walk_ms * 1e-3) / 1e12
+    # Algorithmic work is W haplotype-cells (markers walked x core haplotypes);
+    # the operations a cell needs are those of the cell-update proxy, whose
+    # compiled loop refines 256 cells per lane and row with 51 int32 VALU
+    # instructions (gfx950; the profile of the measurement kernels checks it).
+    micro = None
+    if not args.no_micro:
+        log("measurement kernels")
+        micro = ss.micro(ss.pack(A))
+    ops_per_cell = PROXY_OPS_PER_CELL
+    achieved = W * ops_per_cell / (walk_ms * 1e-3) / 1e12
     traffic = measured_traffic("ihs_chr22_204x22147")
-    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_INT32_TOPS, 3),
-                "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 5),
+    cells_s = W / (walk_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": round(achieved, 5), "peak": round(PEAK_INT32_TOPS, 3),
+                "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 6),
                 "traffic": traffic,
                 "kernel": "mask_walk_kernel<CORE,4,1,1> (+ walk_list_kernel overflow pass)",
                 "kernel_ms": round(walk_ms, 5),
-                "work_cells": W, "ops_per_cell": 1,
+                "work_cells": W, "ops_per_cell": round(ops_per_cell, 5),
+                "ops_per_cell_source": "cell-update proxy: 51 VALU lane-ops per 256 cells",
+                "achieved_Gcells": round(cells_s / 1e9, 2),
                 "algorithmic_bytes": W // 8,
                 "algorithmic_GBps": round(W / 8 / (walk_ms * 1e-3) / 1e9, 3)}
+    if micro:
+        roofline.update({
+            "measured": micro,
+            "frac_of_measured_valu": round(achieved / micro["valu_int32_TOPs"], 6),
+            "frac_of_cell_proxy": round(cells_s / 1e9 / micro["cell_proxy_Gcells"], 6),
+            "frac_of_measured_hbm": round(W / 8 / (walk_ms * 1e-3) / 1e9 / micro["hbm_copy_GBps"], 6)})
 
     # --- CPU baseline: the oracle on this host's cores ------------------------
     cpu = None
@@ -374,11 +478,20 @@ def main():
             ref = oracle.ihs(a.alleles, a.pos_bp, a.gpos_cm, threads=threads)
         t_cpu = (time.perf_counter() - t0) / args.cpu_reps
         assert np.array_equal(ref["status"], status)
+        # one thread, for the paper's single-thread column (Table 1)
+        log("timing the CPU oracle on 1 thread")
+        t0 = time.perf_counter()
+        ref1 = oracle.ihs(a.alleles, a.pos_bp, a.gpos_cm, threads=1)
+        t_one = time.perf_counter() - t0
+        assert np.array_equal(ref1["status"], status)
         cpu = {"value": round(core_loci / t_cpu, 1), "unit": "core loci/s", "cores": threads,
                "kind": "oracle",
                "sample": "%d full iHS scans of the 204 x 22,147 workload (%d core loci each), "
-                         "%.2f s per scan" % (args.cpu_reps, core_loci, t_cpu)}
+                         "%.2f s per scan" % (args.cpu_reps, core_loci, t_cpu),
+               "one_thread": {"value": round(core_loci / t_one, 1), "unit": "core loci/s", "cores": 1,
+                              "sample": "1 full iHS scan of the same workload, %.2f s" % t_one}}
 
+    scaling = None if args.no_scaling else bench_scaling(ss, torch, dev)
     batched = None if args.no_batched else bench_batched(ss, torch, dev, not args.no_autotune)
     served = None if args.no_served else bench_served(ss, torch, dev, args)
 
@@ -403,6 +516,7 @@ def main():
                   "unit": "core loci/s", "ms_per_step": round(elx / args.steps * 1e3, 5),
                   "walk_kernel_ms": round(walk_ms_x, 5), "work_cells": Wx,
                   "achieved_TOPs": round(Wx / (walk_ms_x * 1e-3) / 1e12, 4)},
+        "scaling": scaling,
         "batched": batched,
         "served": served,
         "context": {"paper_cpu_loci_per_s": {"ihs_ceu22_1thread": 62.7, "ihs_ceu22_16threads": 671,

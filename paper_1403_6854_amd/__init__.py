@@ -102,6 +102,15 @@ def lib():
         L.ss_ihs_static.argtypes = [HM, PR, P, P, P, P, P, P, P, P]
         L.ss_static_scratch_bytes.argtypes = []
         L.ss_static_scratch_bytes.restype = sz
+        D = ctypes.POINTER(ctypes.c_double)
+        L.ss_micro_out_words.argtypes = []
+        L.ss_micro_copy.argtypes = [P, P, sz, ctypes.c_int, P, D]
+        L.ss_micro_valu.argtypes = [P, ctypes.c_int, ctypes.c_int, P, D, D]
+        L.ss_micro_lds_atomic.argtypes = [P, ctypes.c_int, ctypes.c_int, P, D, D]
+        L.ss_micro_cell.argtypes = [P, i64, P, ctypes.c_int, ctypes.c_int, P, D, D]
+        for f in ("ss_micro_out_words", "ss_micro_copy", "ss_micro_valu", "ss_micro_lds_atomic",
+                  "ss_micro_cell"):
+            getattr(L, f).restype = ctypes.c_int
         SR = ctypes.POINTER(_StdRegion)
         L.ss_genome_workspace_bytes.argtypes = [SR, ctypes.c_int32, ctypes.c_int32, PR]
         L.ss_genome_workspace_bytes.restype = sz
@@ -354,6 +363,36 @@ def genome_standardize(outs: Sequence[dict], n_haps: Optional[Sequence[int]] = N
                                        ctypes.c_void_p(base), ws.numel() - (base - ws.data_ptr()),
                                        _stream(stream)))
     return binstat
+
+
+# ---- measurement kernels (include/selscan_micro.h) ------------------------------
+
+def micro(rows: torch.Tensor, copy_bytes: int = 1 << 30, stream=None) -> dict:
+    """Achievable rates of the GPU resources the walks use, measured on the
+    current device: HBM stream copy (GB/s), int32 VALU (T lane-ops/s), LDS
+    atomics (G ops/s) and the cell-update proxy (G cells/s) over ``rows``
+    (device uint64 [n_rows, 4], e.g. a packed 204-haplotype matrix)."""
+    L = lib()
+    dev = rows.device
+    if rows.dtype != torch.int64 or rows.dim() != 2 or rows.shape[1] != 4 or not rows.is_contiguous():
+        raise ValueError("rows must be a contiguous int64 tensor [n_rows, 4]")
+    out = torch.zeros(L.ss_micro_out_words(), dtype=torch.int32, device=dev)
+    ms, x = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    src = torch.empty(copy_bytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty(copy_bytes, dtype=torch.uint8, device=dev)
+    st = _stream(stream)
+    _check(L.ss_micro_copy(_ptr(src), _ptr(dst), copy_bytes, 10, st, ctypes.byref(ms)))
+    res = {"hbm_copy_GBps": round(2.0 * copy_bytes / (ms.value * 1e-3) / 1e9, 1),
+           "hbm_copy_bytes": copy_bytes}
+    del src, dst
+    _check(L.ss_micro_valu(_ptr(out), 4096, 10, st, ctypes.byref(ms), ctypes.byref(x)))
+    res["valu_int32_TOPs"] = round(x.value / (ms.value * 1e-3) / 1e12, 3)
+    _check(L.ss_micro_lds_atomic(_ptr(out), 4096, 10, st, ctypes.byref(ms), ctypes.byref(x)))
+    res["lds_atomic_Gops"] = round(x.value / (ms.value * 1e-3) / 1e9, 1)
+    _check(L.ss_micro_cell(_ptr(rows), rows.shape[0], _ptr(out), 2048, 10, st, ctypes.byref(ms),
+                           ctypes.byref(x)))
+    res["cell_proxy_Gcells"] = round(x.value / (ms.value * 1e-3) / 1e9, 1)
+    return res
 
 
 def static_scratch_bytes() -> int:

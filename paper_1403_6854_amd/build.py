@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libselscan_hip.so")
 SOURCES = ["ss_walk.hip", "ss_walk_mask.hip", "ss_walk_wide.hip", "ss_walk_batch.hip", "ss_sites.hip",
-           "ss_genome.hip", "ss_capi.hip"]
+           "ss_genome.hip", "ss_micro.hip", "ss_capi.hip"]
 ARCH = os.environ.get("SS_OFFLOAD_ARCH", "gfx950")
 
 

@@ -7,11 +7,11 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "selscan_hip.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("selscan_hip.h", "selscan_micro.h")]
 
 
 def _declared():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"\b(ss_[a-z_]+)\s*\(", text)
     return sorted(set(names))
@@ -269,3 +269,17 @@ def test_genome_standardize_checks_arguments_on_the_host(lib):
                                      nb - 1, None) == ss.SS_EWS
     assert lib.ss_genome_standardize(arr, 0, ss.OP_IHS, ctypes.byref(p), None, ctypes.c_void_p(x),
                                      nb, None) == ss.SS_EARG
+
+
+def test_measurement_kernels_check_arguments_on_the_host(lib):
+    import paper_1403_6854_amd as ss
+    d = ctypes.c_double(0.0)
+    x = ctypes.c_void_p(0x1000)
+    assert lib.ss_micro_copy(None, x, 4096, 1, None, ctypes.byref(d)) == ss.SS_EARG
+    assert lib.ss_micro_copy(x, x, 4097, 1, None, ctypes.byref(d)) == ss.SS_EARG      # not a multiple of 16
+    assert lib.ss_micro_copy(ctypes.c_void_p(0x1008), x, 4096, 1, None, ctypes.byref(d)) == ss.SS_EARG
+    assert lib.ss_micro_valu(None, 16, 1, None, ctypes.byref(d), ctypes.byref(d)) == ss.SS_EARG
+    assert lib.ss_micro_valu(x, 0, 1, None, ctypes.byref(d), ctypes.byref(d)) == ss.SS_EARG
+    assert lib.ss_micro_lds_atomic(x, 16, 1, None, ctypes.byref(d), None) == ss.SS_EARG
+    assert lib.ss_micro_cell(x, 0, x, 16, 1, None, ctypes.byref(d), ctypes.byref(d)) == ss.SS_EARG
+    assert lib.ss_micro_cell(x, 10, x, 0, 1, None, ctypes.byref(d), ctypes.byref(d)) == ss.SS_EARG
