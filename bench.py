@@ -271,6 +271,8 @@ def bench_served(ss, torch, dev, args):
         kinds = {s.rid: s for s in sp}
         tot = 0
         for c in done:
+            if c.out is None:    # a request that failed every attempt
+                continue
             st = c.out["status"]
             tot += int((st != 1).sum().item()) if kinds[c.rid].kind == "ihs" else int(st.numel())
         return tot
@@ -297,24 +299,7 @@ def bench_served(ss, torch, dev, args):
     serve.Server(serve.TorchBackend(args.serve_streams), budget).run(reqs_of(warm))
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    log("served: %d requests, continuous batching" % len(specs))
-    srv = serve.Server(serve.TorchBackend(args.serve_streams), budget, max_batch=64,
-                       work_ratio=args.serve_work_ratio)
-    done = srv.run(reqs_of(specs))
-    torch.cuda.synchronize()
-    s1 = serve.summarize(done)
-    s1["core_loci_per_s"] = round(loci_of(done, specs) / s1["makespan_s"], 1)
-    s1.update({"batches": srv.batches, "mean_batch": round(float(np.mean(srv.batch_sizes)), 2),
-               "peak_admitted_GB": round(srv.peak_bytes / 2**30, 2),
-               "streams": args.serve_streams, "budget_GB": args.serve_budget_gb,
-               "work_ratio": args.serve_work_ratio,
-               "config": dataclasses.asdict(cfg), "group_tuning": ss.group_tuning()})
-    del done
-    torch.cuda.empty_cache()
-
-    log("served: %d requests back to back (plain scans)" % len(specs))
     stream = torch.cuda.Stream()
-    ss.set_walk_kernel(2)    # bitmask kernel when it applies, else the plain class-id kernel
 
     def run_one(r):
         with torch.cuda.stream(stream):
@@ -323,17 +308,46 @@ def bench_served(ss, torch, dev, args):
         stream.synchronize()
         return {"status": out["status"]}
 
-    seq = serve.run_back_to_back(reqs_of(specs), run_one)
-    ss.set_walk_kernel(0)
-    s2 = serve.summarize(seq)
-    s2["core_loci_per_s"] = round(loci_of(seq, specs) / s2["makespan_s"], 1)
-    del seq
-    torch.cuda.empty_cache()
-    return {"workload": "served_mixed_4096", "requests": len(specs),
-            "arrivals_per_s": hapgen.SERVE["rate_per_s"],
-            "continuous_batching": s1, "back_to_back": s2,
-            "throughput_ratio": round(s1["requests_per_s"] / s2["requests_per_s"], 3),
-            "p99_ratio": round(s2["p99_ms"] / s1["p99_ms"], 3)}
+    def both(sp, label):
+        log("served: %d requests at %g/s, continuous batching" % (len(sp), label))
+        srv = serve.Server(serve.TorchBackend(args.serve_streams), budget, max_batch=64,
+                           work_ratio=args.serve_work_ratio)
+        done = srv.run(reqs_of(sp))
+        torch.cuda.synchronize()
+        s1 = serve.summarize(done)
+        s1["core_loci_per_s"] = round(loci_of(done, sp) / s1["makespan_s"], 1)
+        s1.update({"batches": srv.batches, "mean_batch": round(float(np.mean(srv.batch_sizes)), 2),
+                   "peak_admitted_GB": round(srv.peak_bytes / 2**30, 2), "failed_batches": srv.failures,
+                   "errors": sum(1 for c in done if c.error)})
+        del done
+        torch.cuda.empty_cache()
+        log("served: %d requests at %g/s, back to back (plain scans)" % (len(sp), label))
+        ss.set_walk_kernel(2)    # bitmask kernel when it applies, else the plain class-id kernel
+        seq = serve.run_back_to_back(reqs_of(sp), run_one)
+        ss.set_walk_kernel(0)
+        s2 = serve.summarize(seq)
+        s2["core_loci_per_s"] = round(loci_of(seq, sp) / s2["makespan_s"], 1)
+        del seq
+        torch.cuda.empty_cache()
+        return s1, s2
+
+    s1, s2 = both(specs, hapgen.SERVE["rate_per_s"])
+    s1.update({"streams": args.serve_streams, "budget_GB": args.serve_budget_gb,
+               "work_ratio": args.serve_work_ratio, "config": dataclasses.asdict(cfg),
+               "group_tuning": ss.group_tuning()})
+    res = {"workload": "served_mixed_4096", "requests": len(specs),
+           "arrivals_per_s": hapgen.SERVE["rate_per_s"],
+           "continuous_batching": s1, "back_to_back": s2,
+           "throughput_ratio": round(s1["requests_per_s"] / s2["requests_per_s"], 3),
+           "p99_ratio": round(s2["p99_ms"] / s1["p99_ms"], 3)}
+    if args.serve_low_rate > 0:
+        low = hapgen.request_stream(args.serve_low_requests, args.serve_low_rate)
+        l1, l2 = both(low, args.serve_low_rate)
+        res["below_saturation"] = {"requests": len(low), "arrivals_per_s": args.serve_low_rate,
+                                   "continuous_batching": l1, "back_to_back": l2,
+                                   "p50_ratio": round(l2["p50_ms"] / l1["p50_ms"], 3),
+                                   "p99_ratio": round(l2["p99_ms"] / l1["p99_ms"], 3)}
+    return res
 
 
 def main():
@@ -350,7 +364,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
     ap.add_argument("--serve-streams", type=int, default=4)
-    ap.add_argument("--serve-work-ratio", type=float, default=0.0,
+    ap.add_argument("--serve-low-rate", type=float, default=150.0,
+                    help="also serve a stream arriving at this rate (below saturation); 0: skip")
+    ap.add_argument("--serve-low-requests", type=int, default=2048)
+    ap.add_argument("--serve-work-ratio", type=float, default=4.0,
                     help="close a served batch at a request whose estimated work differs "
                          "from the batch's first by more than this factor (0: off)")
     ap.add_argument("--no-autotune", action="store_true",

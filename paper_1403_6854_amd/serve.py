@@ -12,7 +12,16 @@ one region -- arrive over time.  The server
   * keeps one batch per stream of the backend on the device at once, so
     requests that arrive while others run are admitted as soon as a stream
     and memory free up, and their work overlaps on the GPU;
-  * retires a batch when its completion event has fired, releasing its memory.
+  * completes each request as soon as its own results are ready: the torch
+    backend enqueues a batch as up to two ss_scan_batch calls, the requests
+    walked by the register-bitmask kernel (512 haplotypes or fewer in the
+    walk) first, each followed by an event, so that small requests do not wait
+    for the longest walk of a large one; the batch's memory and stream are
+    released when its last event has fired;
+  * survives backend failures: a batch whose launch or completion raises is
+    dropped, its memory released, and its unfinished requests queued again at
+    the front to run alone; a request that fails ``max_attempts`` times
+    completes with an error entry (``Completion.error``) instead of results.
 
 Latency of a request is completion time minus arrival time.  The per-request
 results are exactly those of the request run alone (every walk kernel gives the
@@ -50,6 +59,7 @@ class Completion:
     finish_s: float
     batch: int
     out: Optional[dict] = None
+    error: Optional[str] = None   # set when the request failed every attempt
 
     @property
     def latency_s(self) -> float:
@@ -81,8 +91,16 @@ def request_work(kind: str, n_a: int, n_b: int, n_sites: int) -> float:
     return float(n_sites) * float(n_a + (n_b if kind == "xpehh" else 0))
 
 
+# Haplotypes in a walk up to which the register-bitmask kernel takes a request.
+SMALL_WALK_HAPS = 512
+
+
 class TorchBackend:
-    """Runs batches through ss_scan_batch on a pool of streams."""
+    """Runs batches through ss_scan_batch on a pool of streams.  A batch is
+    enqueued as one ss_scan_batch call for the requests of at most 512
+    haplotypes in the walk (the bitmask kernel, one launch per scan), then one
+    for the others (one persistent launch), each followed by an event; the
+    requests of a call are complete when its event has fired."""
 
     def __init__(self, n_streams: int = 2, params=None, keep=("status",), steps: bool = False):
         import torch
@@ -102,36 +120,69 @@ class TorchBackend:
         torch, ss = self.torch, self.ss
         si = self.free.pop()
         s = self.streams[si]
-        with torch.cuda.stream(s):
-            srs = []
-            for r in reqs:
-                a, b = r.make()
-                sr = ss.ScanRequest(a, b)
-                ss.alloc_outputs(sr, steps=self.steps)
-                srs.append(sr)
-            ss.scan_batch(srs, self.params, stream=s, validate=False)
-            ev = torch.cuda.Event()
-            ev.record(s)
-        return (si, ev, srs)
+        try:
+            with torch.cuda.stream(s):
+                srs = []
+                for r in reqs:
+                    a, b = r.make()
+                    sr = ss.ScanRequest(a, b)
+                    ss.alloc_outputs(sr, steps=self.steps)
+                    srs.append(sr)
+                small = [i for i, sr in enumerate(srs)
+                         if sr.a.n_haps + (sr.b.n_haps if sr.b is not None else 0) <= SMALL_WALK_HAPS]
+                in_small = set(small)
+                large = [i for i in range(len(srs)) if i not in in_small]
+                groups = []
+                for pos in (small, large):
+                    if not pos:
+                        continue
+                    ss.scan_batch([srs[i] for i in pos], self.params, stream=s, validate=False)
+                    ev = torch.cuda.Event()
+                    ev.record(s)
+                    groups.append([pos, ev, False])
+        except Exception:
+            self.free.append(si)
+            raise
+        return (si, groups, srs)
+
+    def _out(self, sr) -> dict:
+        return {k: v for k, v in sr.out.items() if self.keep is None or k in self.keep}
+
+    def partial(self, handle):
+        """Members whose call's event has fired since the last query:
+        [(position in the batch, outputs)]."""
+        _, groups, srs = handle
+        got = []
+        for g in groups:
+            if not g[2] and g[1].query():
+                g[2] = True
+                got.extend((i, self._out(srs[i])) for i in g[0])
+        return got
 
     def done(self, handle) -> bool:
-        return handle[1].query()
+        return handle[1][-1][1].query()
 
     def retire(self, handle) -> List[dict]:
-        si, ev, srs = handle
+        si, _, srs = handle
         self.free.append(si)
-        outs = []
-        for sr in srs:
-            outs.append({k: v for k, v in sr.out.items() if self.keep is None or k in self.keep})
-        return outs
+        return [self._out(sr) for sr in srs]
+
+    def release(self, handle):
+        """Gives back the stream of a batch the server abandons."""
+        if handle[1]:
+            handle[1][-1][1].synchronize()   # its work may still be running
+        self.free.append(handle[0])
 
 
 class Server:
     """Admission by memory budget, continuous batching, completion polling.
 
     ``backend`` provides slots() (free streams), launch(list) -> handle,
-    done(handle) -> bool and retire(handle) -> per-request outputs; ``clock``
-    and ``sleep`` are injectable so the policy can be exercised off the GPU.
+    done(handle) -> bool and retire(handle) -> per-request outputs, and
+    optionally partial(handle) -> [(position, outputs)] for members complete
+    before the whole batch, and release(handle) to give back the stream of a
+    batch dropped after an error; ``clock`` and ``sleep`` are injectable so the
+    policy can be exercised off the GPU.
 
     ``work_ratio`` > 0 closes a batch at the first waiting request whose
     estimated work differs from the batch's first request's by more than
@@ -143,9 +194,12 @@ class Server:
     def __init__(self, backend, budget_bytes: int, max_batch: int = 64,
                  clock: Callable[[], float] = time.perf_counter,
                  sleep: Callable[[float], None] = time.sleep, poll_s: float = 1e-4,
-                 work_ratio: float = 0.0):
-        if budget_bytes <= 0 or max_batch < 1:
-            raise ValueError("budget_bytes and max_batch must be positive")
+                 work_ratio: float = 0.0, max_attempts: int = 2):
+        if budget_bytes <= 0 or max_batch < 1 or max_attempts < 1:
+            raise ValueError("budget_bytes, max_batch and max_attempts must be positive")
+        self.max_attempts = int(max_attempts)
+        self.failures = 0                 # batches dropped after a backend error
+        self.errors: List[str] = []
         if work_ratio < 0.0 or (0.0 < work_ratio < 1.0):
             raise ValueError("work_ratio must be 0 or at least 1")
         self.work_ratio = float(work_ratio)
@@ -169,31 +223,77 @@ class Server:
         reqs = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
         t0 = self.clock()
         nxt = 0
-        pending = collections.deque()
-        inflight = []          # (handle, [(req, admit_s)], bytes, batch id)
+        pending = collections.deque()   # (request, alone): alone after a failed attempt
+        attempts = collections.Counter()
+        inflight = []          # [handle, [(req, admit_s)], bytes, batch id, set of positions done]
         used = 0
         done: List[Completion] = []
+        partial = getattr(self.backend, "partial", None)
+
+        def requeue(members, bid, err):
+            # a failed attempt: each unfinished request goes back to the front
+            # of the queue, to run alone, or completes with the error once it
+            # has failed max_attempts times
+            self.failures += 1
+            self.errors.append(err)
+            now_s = self.clock() - t0
+            for r, adm in reversed(members):
+                attempts[r.rid] += 1
+                if attempts[r.rid] >= self.max_attempts:
+                    done.append(Completion(r.rid, r.arrival_s, adm, now_s, bid, None, err))
+                else:
+                    pending.appendleft((r, True))
+
+        def drop(item, err):
+            # the batch failed after its launch: release its memory and stream
+            nonlocal used
+            handle, members, nbytes, bid, got = item
+            inflight.remove(item)
+            used -= nbytes
+            release = getattr(self.backend, "release", None)
+            if release is not None:
+                try:
+                    release(handle)
+                except Exception as e:   # the stream is lost; keep serving on the others
+                    self.errors.append("release: %r" % (e,))
+            requeue([m for pos, m in enumerate(members) if pos not in got], bid, err)
+
         while nxt < len(reqs) or pending or inflight:
             now = self.clock() - t0
             while nxt < len(reqs) and reqs[nxt].arrival_s <= now:
-                pending.append(reqs[nxt])
+                pending.append((reqs[nxt], False))
                 nxt += 1
             progressed = False
             for item in list(inflight):
-                handle, members, nbytes, bid = item
-                if self.backend.done(handle):
-                    fin = self.clock() - t0
-                    outs = self.backend.retire(handle)
-                    for (r, adm), o in zip(members, outs):
-                        done.append(Completion(r.rid, r.arrival_s, adm, fin, bid, o))
-                    used -= nbytes
-                    inflight.remove(item)
+                handle, members, nbytes, bid, got = item
+                try:
+                    if partial is not None:
+                        early = partial(handle)
+                        if early:
+                            fin = self.clock() - t0
+                            for pos, o in early:
+                                if pos not in got:
+                                    got.add(pos)
+                                    r, adm = members[pos]
+                                    done.append(Completion(r.rid, r.arrival_s, adm, fin, bid, o))
+                            progressed = True
+                    if self.backend.done(handle):
+                        fin = self.clock() - t0
+                        outs = self.backend.retire(handle)
+                        for pos, ((r, adm), o) in enumerate(zip(members, outs)):
+                            if pos not in got:
+                                done.append(Completion(r.rid, r.arrival_s, adm, fin, bid, o))
+                        used -= nbytes
+                        inflight.remove(item)
+                        progressed = True
+                except Exception as e:
+                    drop(item, "batch %d: %r" % (bid, e))
                     progressed = True
             if pending and self.backend.slots() > 0:
                 batch, nbytes = [], 0
                 while pending and len(batch) < self.max_batch:
-                    r = pending[0]
-                    if batch and self._apart(batch[0], r):
+                    r, alone = pending[0]
+                    if batch and (alone or batch[0][1] or self._apart(batch[0][0], r)):
                         break
                     if used + nbytes + r.nbytes > self.budget:
                         # a request larger than the whole budget runs alone
@@ -203,13 +303,18 @@ class Server:
                     nbytes += r.nbytes
                 if batch:
                     adm = self.clock() - t0
-                    handle = self.backend.launch(batch)
-                    used += nbytes
-                    self.peak_bytes = max(self.peak_bytes, used)
-                    inflight.append((handle, [(r, adm) for r in batch], nbytes, self.batches))
+                    bid = self.batches
                     self.batch_sizes.append(len(batch))
                     self.batches += 1
                     progressed = True
+                    try:
+                        handle = self.backend.launch([r for r, _ in batch])
+                    except Exception as e:   # nothing was admitted
+                        requeue([(r, adm) for r, _ in batch], bid, "batch %d launch: %r" % (bid, e))
+                    else:
+                        used += nbytes
+                        self.peak_bytes = max(self.peak_bytes, used)
+                        inflight.append([handle, [(r, adm) for r, _ in batch], nbytes, bid, set()])
             if not progressed:
                 if not inflight and not pending and nxt < len(reqs):
                     wait = reqs[nxt].arrival_s - (self.clock() - t0)

@@ -168,3 +168,99 @@ def test_work_ratio_keeps_dissimilar_requests_apart_in_arrival_order():
                for _, rids in be0.launches)
     with pytest.raises(ValueError):
         serve.Server(be, 10, work_ratio=0.5)
+
+
+class FlakyBackend(FakeBackend):
+    """A FakeBackend whose launch raises the first time a batch holds a
+    request of `bad_launch`, and whose completion check raises for every
+    batch holding a request of `poison`."""
+
+    def __init__(self, clock, bad_launch=(), poison=(), **kw):
+        super().__init__(clock, **kw)
+        self.bad_launch = set(bad_launch)
+        self.poison = set(poison)
+        self.released = 0
+
+    def launch(self, reqs):
+        bad = [r.rid for r in reqs if r.rid in self.bad_launch]
+        if bad:
+            self.bad_launch -= set(bad)
+            raise RuntimeError("launch failed")
+        return super().launch(reqs)
+
+    def done(self, h):
+        if any(r.rid in self.poison for r in h[2]):
+            raise RuntimeError("device error")
+        return super().done(h)
+
+    def release(self, h):
+        self.released += 1
+        self.free.append(h[0])
+        self.active_bytes -= h[3]
+
+
+def _run_flaky(reqs, **kw):
+    clk = FakeClock()
+    be = FlakyBackend(clk, n_streams=2, **kw)
+    srv = serve.Server(be, 10**9, max_batch=8, clock=clk, sleep=clk.sleep, poll_s=1e-4)
+    return srv.run(reqs), be, srv
+
+
+def test_a_failed_launch_is_retried_and_every_request_completes():
+    reqs = _reqs(120, rate=2000.0)
+    done, be, srv = _run_flaky(reqs, bad_launch={7, 50})
+    assert sorted(c.rid for c in done) == list(range(120))
+    assert all(c.error is None and c.out == {"rid": c.rid} for c in done)
+    assert 1 <= srv.failures <= 2        # 7 and 50 in one batch, or in two
+    # the requests of a failed batch were retried alone
+    alone = [rids for _, rids in be.launches if 7 in rids or 50 in rids]
+    assert all(len(r) == 1 for r in alone)
+
+
+def test_a_request_that_keeps_failing_ends_with_an_error_and_the_rest_complete():
+    reqs = _reqs(80, rate=2000.0)
+    done, be, srv = _run_flaky(reqs, poison={33})
+    assert sorted(c.rid for c in done) == list(range(80))
+    bad = [c for c in done if c.rid == 33]
+    assert len(bad) == 1 and bad[0].error and bad[0].out is None
+    assert all(c.error is None and c.out == {"rid": c.rid} for c in done if c.rid != 33)
+    # streams and memory of dropped batches were given back
+    assert be.released == srv.failures and be.active_bytes == 0 and len(be.free) == 2
+
+
+class PartialBackend(FakeBackend):
+    """Members of a batch complete at their own times (small requests first)."""
+
+    def launch(self, reqs):
+        h = super().launch(reqs)
+        t = self.clock()
+        return h + ([t + 0.001 * (1 + (r.rid % 2) * 20) for r in reqs], set())
+
+    def partial(self, h):
+        got = []
+        for i, t in enumerate(h[4]):
+            if i not in h[5] and self.clock() >= t:
+                h[5].add(i)
+                got.append((i, {"rid": h[2][i].rid}))
+        return got
+
+    def done(self, h):
+        return self.clock() >= max(h[4])
+
+
+def test_requests_complete_when_their_own_results_are_ready():
+    clk = FakeClock()
+    be = PartialBackend(clk, n_streams=1)
+    srv = serve.Server(be, 10**9, max_batch=16, clock=clk, sleep=clk.sleep, poll_s=1e-4)
+    reqs = _reqs(40, rate=5000.0)
+    done = srv.run(reqs)
+    assert sorted(c.rid for c in done) == list(range(40))
+    by = {c.rid: c for c in done}
+    for c in done:
+        assert c.out == {"rid": c.rid}
+    # in each batch the even requests (1 ms) finish before the odd ones (21 ms)
+    for b in {c.batch for c in done}:
+        ev = [by[r].finish_s for r in by if by[r].batch == b and r % 2 == 0]
+        od = [by[r].finish_s for r in by if by[r].batch == b and r % 2 == 1]
+        if ev and od:
+            assert max(ev) < min(od)
