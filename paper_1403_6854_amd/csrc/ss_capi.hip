@@ -107,9 +107,7 @@ constexpr int kGroupCtrWords = 2 * ss::kQueueWords + ss::kCtrStride;
 struct ScanWs {
     uint8_t *walk_flag;   // [M]
     int32_t *bin;         // [M]
-    double *dihh;         // [M][2][2]
-    int32_t *dstatus;     // [M][2][2]
-    int32_t *dsteps;      // [M][2][2]
+    ss::WalkRec *rec;     // [M][2][2] walk results
     double *binstat;      // [nbins][3]
     double *binpart;      // per-tile partial sums of the bin statistics
     uint64_t *hbits;      // [nA (+ nB)][mwp] haplotype-major copies
@@ -131,9 +129,7 @@ ScanWs carve_scan(void *base, int64_t M, int nbins, int64_t n_hapmajor) {
     };
     w.walk_flag = (uint8_t *)take((size_t)M);
     w.bin = (int32_t *)take(4 * (size_t)M);
-    w.dihh = (double *)take(32 * (size_t)M);
-    w.dstatus = (int32_t *)take(16 * (size_t)M);
-    w.dsteps = (int32_t *)take(16 * (size_t)M);
+    w.rec = (ss::WalkRec *)take(sizeof(ss::WalkRec) * 4 * (size_t)M);
     w.binstat = (double *)take(24 * (size_t)nbins);
     w.binpart = (double *)take(8 * (size_t)ss::standardize_scratch_doubles(M, nbins));
     w.hbits = (uint64_t *)take(8 * (size_t)n_hapmajor * (size_t)ss::hap_major_words(M));
@@ -147,16 +143,14 @@ ScanWs carve_scan(void *base, int64_t M, int nbins, int64_t n_hapmajor) {
 }
 
 struct EhhWs {
-    double *dihh;      // [2][2]
-    int32_t *dstatus;  // [2]
+    ss::WalkRec *rec;  // [2 dirs][2 cores]
     size_t bytes;
 };
 
 EhhWs carve_ehh(void *base) {
     EhhWs w;
-    w.dihh = (double *)base;
-    w.dstatus = base ? (int32_t *)((char *)base + 256) : nullptr;
-    w.bytes = 512;
+    w.rec = (ss::WalkRec *)base;
+    w.bytes = 256;
     return w;
 }
 
@@ -434,9 +428,7 @@ void init_scan(Scan &sc, void *base, const ss_params *p) {
     a.walk_flag = sc.mode == ss::MODE_CORE ? sc.w.walk_flag : nullptr;
     a.site0 = 0;
     a.kmax = (int32_t)(list_len(a.nA, a.nB, sc.mode) / 2 + 2);
-    a.ihh = sc.w.dihh;
-    a.dstatus = sc.w.dstatus;
-    a.steps = sc.w.dsteps;
+    a.rec = sc.w.rec;
     a.mwp = ss::hap_major_words(a.M);
     a.hbits = sc.mode == ss::MODE_CORE ? sc.w.hbits : nullptr;
     a.seg = sc.w.seg;
@@ -453,9 +445,7 @@ ss::Region region_of(const Scan &sc) {
     r.hbitsB = sc.mode == ss::MODE_POOLED ? sc.w.hbits + (size_t)a.nA * (size_t)a.mwp : nullptr;
     r.seg = sc.w.seg;
     r.walk_flag = a.walk_flag;
-    r.ihh = sc.w.dihh;
-    r.dstatus = sc.w.dstatus;
-    r.steps = sc.w.dsteps;
+    r.rec = sc.w.rec;
     r.wpsA = a.wpsA;
     r.wpsB = a.wpsB;
     r.M = a.M;
@@ -504,7 +494,7 @@ int walk_direct(const Scan &sc, hipStream_t s) {
 int finish_scan(const Scan &sc, hipStream_t s) {
     const int64_t M = sc.args.M;
     SS_HIP(ss::launch_combine(sc.mode, M, sc.mode == ss::MODE_CORE ? sc.w.walk_flag : nullptr,
-                              sc.w.dihh, sc.w.dstatus, sc.w.dsteps, sc.out_x, sc.out_y, sc.unstd,
+                              sc.w.rec, sc.out_x, sc.out_y, sc.unstd,
                               sc.status, sc.steps, s));
     if (sc.mode == ss::MODE_CORE)
         SS_HIP(ss::launch_standardize(M, sc.unstd, sc.status, sc.w.bin, sc.nbins, sc.w.binstat,
@@ -999,14 +989,13 @@ int ss_ehh(const ss_hapmat *h, int64_t core, const ss_params *p, int64_t cap, ui
     ss::WalkArgs a = walk_args(h, nullptr, p);
     a.site0 = core;
     a.kmax = (int32_t)(h->n_haps / 2 + 2);
-    a.ihh = w.dihh;
-    a.dstatus = w.dstatus;
+    a.rec = w.rec;
     a.trS = d_S;
     a.trSizes = d_class_sizes;
     a.trLen = d_len;
     a.cap = cap;
     SS_HIP(ss::launch_walk(a, ss::MODE_CORE, true, 1, s));
-    SS_HIP(ss::launch_ehh_finish(h->n_haps, cap, d_S, d_len, w.dihh, w.dstatus, d_ehh, d_ihh,
+    SS_HIP(ss::launch_ehh_finish(h->n_haps, cap, d_S, d_len, w.rec, d_ehh, d_ihh,
                                  d_status, s));
     return SS_OK;
 }

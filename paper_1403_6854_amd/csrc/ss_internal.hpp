@@ -16,6 +16,22 @@ enum : int32_t {
 
 enum WalkMode : int { MODE_CORE = 0, MODE_POOLED = 1 };
 
+// Result of one walk -- iHH, abort status and markers walked -- as one 16-byte
+// record per (site, direction, slot), the slot being the core allele (iHS) or
+// the population (XPEHH), written with one vector store: three separate
+// arrays took three partial-line writes per walk.
+struct WalkRec {
+    double ihh;
+    int32_t status;
+    int32_t steps;
+};
+static_assert(sizeof(WalkRec) == 16, "one 16-byte store per walk");
+
+__device__ __forceinline__ void put_rec(WalkRec *r, double ihh, int32_t status, int32_t steps) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, ihh);
+    *(uint4 *)r = make_uint4((uint32_t)b, (uint32_t)(b >> 32), (uint32_t)status, (uint32_t)steps);
+}
+
 // Everything one launch of the EHH walk needs.  The pooled haplotype index
 // space places population A in words [0, WA) and population B in words
 // [WA, WA + WB), so that every 64-haplotype word belongs to one population.
@@ -37,9 +53,7 @@ struct WalkArgs {
     const int32_t *sites;       // null: block x walks site site0 + blockIdx.x
     int64_t site0;
     int32_t kmax;               // class-table capacity in LDS
-    double *ihh;                // [M][2 dirs][2]
-    int32_t *dstatus;           // [M][2 dirs][2] (per core for iHS walks split by core)
-    int32_t *steps;             // [M][2 dirs][2]
+    WalkRec *rec;               // [M][2 dirs][2 slots] walk results (ss_ehh: [2 dirs][2])
     // ss_ehh trace outputs (one site only)
     uint64_t *trS;              // [2][cap+1][2]
     uint32_t *trSizes;          // [2][cap+1][n] or null
@@ -103,9 +117,7 @@ struct Region {
     const uint64_t *hbitsB;     // [nB][mwp] (XPEHH)
     const double *seg;          // [M]
     const uint8_t *walk_flag;   // [M] or null (every site)
-    double *ihh;                // [M][2][2]
-    int32_t *dstatus;           // [M][2][2]
-    int32_t *steps;             // [M][2][2]
+    WalkRec *rec;               // [M][2][2]
     int64_t wpsA, wpsB, M, mwp;
     int64_t item0;
     double cutoff;
@@ -248,8 +260,7 @@ hipError_t launch_site_stats(const uint64_t *bits, int64_t wps, int64_t n, int64
                              int32_t *bin, uint8_t *walk_flag, int8_t *status,
                              hipStream_t s);
 hipError_t launch_combine(int mode, int64_t M, const uint8_t *walk_flag,
-                          const double *dihh, const int32_t *dstatus,
-                          const int32_t *dsteps, double *out_a, double *out_b,
+                          const WalkRec *rec, double *out_a, double *out_b,
                           double *unstd, int8_t *status, int32_t *steps_out,
                           hipStream_t s);
 int64_t standardize_scratch_doubles(int64_t M, int32_t nbins);
@@ -274,7 +285,7 @@ hipError_t launch_genome_standardize(const GenomeRegion *host, int32_t nreg, Gen
                                      int64_t total_tiles, int32_t nbins, double *binstat,
                                      double *part, hipStream_t s);
 hipError_t launch_ehh_finish(int64_t n, int64_t cap, const uint64_t *S, const int64_t *len,
-                             const double *dihh, const int32_t *dstatus, double *ehh,
+                             const WalkRec *rec, double *ehh,
                              double *ihh, int8_t *status, hipStream_t s);
 
 }  // namespace ss

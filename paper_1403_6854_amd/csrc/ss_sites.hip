@@ -149,8 +149,7 @@ __global__ void __launch_bounds__(kBlock) site_stats_kernel(
 // downstream abort if any, else the upstream one; then the log-ratio
 // (Eq. 5 / Eq. 8).
 __global__ void __launch_bounds__(kBlock) combine_kernel(
-    int64_t M, const uint8_t *__restrict__ walk_flag, const double *__restrict__ dihh,
-    const int32_t *__restrict__ dstatus, const int32_t *__restrict__ dsteps,
+    int64_t M, const uint8_t *__restrict__ walk_flag, const WalkRec *__restrict__ rec,
     double *__restrict__ out_a, double *__restrict__ out_b, double *__restrict__ unstd,
     int8_t *__restrict__ status, int32_t *__restrict__ steps_out, int pooled) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -169,13 +168,14 @@ __global__ void __launch_bounds__(kBlock) combine_kernel(
     }
     // a direction aborts if the walk of either core aborted (iHS walks may be
     // split by core; joint walks write the same status to both slots)
-    const int32_t sd = dstatus[4 * j + 0] != ST_OK ? dstatus[4 * j + 0] : dstatus[4 * j + 1];
-    const int32_t su = dstatus[4 * j + 2] != ST_OK ? dstatus[4 * j + 2] : dstatus[4 * j + 3];
+    const WalkRec r0 = rec[4 * j + 0], r1 = rec[4 * j + 1], r2 = rec[4 * j + 2], r3 = rec[4 * j + 3];
+    const int32_t sd = r0.status != ST_OK ? r0.status : r1.status;
+    const int32_t su = r2.status != ST_OK ? r2.status : r3.status;
     int32_t st = sd != ST_OK ? sd : su;
     // slot 0 of a direction holds core 0 (iHS) or population A (XPEHH),
     // slot 1 holds core 1 or population B
-    const double x0 = dihh[4 * j + 0] + dihh[4 * j + 2];
-    const double x1 = dihh[4 * j + 1] + dihh[4 * j + 3];
+    const double x0 = r0.ihh + r2.ihh;
+    const double x1 = r1.ihh + r3.ihh;
     double a = nan, b = nan, u = nan;
     if (st == ST_OK) {
         if (!(x0 > 0.0) || !(x1 > 0.0)) {
@@ -196,10 +196,13 @@ __global__ void __launch_bounds__(kBlock) combine_kernel(
     status[j] = (int8_t)st;
     if (steps_out) {
         if (pooled) {
-            steps_out[2 * j] = dsteps[4 * j + 0];
-            steps_out[2 * j + 1] = dsteps[4 * j + 2];
+            steps_out[2 * j] = r0.steps;
+            steps_out[2 * j + 1] = r2.steps;
         } else {
-            for (int q = 0; q < 4; ++q) steps_out[4 * j + q] = dsteps[4 * j + q];
+            steps_out[4 * j + 0] = r0.steps;
+            steps_out[4 * j + 1] = r1.steps;
+            steps_out[4 * j + 2] = r2.steps;
+            steps_out[4 * j + 3] = r3.steps;
         }
     }
 }
@@ -494,8 +497,7 @@ __global__ void __launch_bounds__(kFusedBlock) bin_fused_kernel(int64_t M,
 // C(n_c, 2), the denominator of Eq. 3), iHH = downstream + upstream, status.
 __global__ void ehh_finish_kernel(int64_t n, int64_t cap, const uint64_t *__restrict__ S,
                                   const int64_t *__restrict__ len,
-                                  const double *__restrict__ dihh,
-                                  const int32_t *__restrict__ dstatus, double *__restrict__ ehh,
+                                  const WalkRec *__restrict__ rec, double *__restrict__ ehh,
                                   double *__restrict__ ihh, int8_t *__restrict__ status) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const double nan = __builtin_nan("");
@@ -514,13 +516,13 @@ __global__ void ehh_finish_kernel(int64_t n, int64_t cap, const uint64_t *__rest
         }
     }
     if (t == 0) {
-        int32_t st = dstatus[0] != ST_OK ? dstatus[0] : dstatus[1];
+        int32_t st = rec[0].status != ST_OK ? rec[0].status : rec[2].status;   // downstream, upstream
         const bool small = S[0] == 0 || S[1] == 0;   // C(n_c, 2) = 0: n_c < 2
         if (st == ST_OK && small) st = ST_UNDEF;
         double i0 = nan, i1 = nan;
         if (st == ST_OK) {
-            i0 = dihh[0] + dihh[2];
-            i1 = dihh[1] + dihh[3];
+            i0 = rec[0].ihh + rec[2].ihh;
+            i1 = rec[1].ihh + rec[3].ihh;
             if (!(i0 > 0.0) || !(i1 > 0.0)) {
                 st = ST_UNDEF;
                 i0 = i1 = nan;
@@ -577,13 +579,13 @@ hipError_t launch_site_stats(const uint64_t *bits, int64_t wps, int64_t n, int64
     return hipGetLastError();
 }
 
-hipError_t launch_combine(int mode, int64_t M, const uint8_t *walk_flag, const double *dihh,
-                          const int32_t *dstatus, const int32_t *dsteps, double *out_a,
+hipError_t launch_combine(int mode, int64_t M, const uint8_t *walk_flag, const WalkRec *rec,
+                          double *out_a,
                           double *out_b, double *unstd, int8_t *status, int32_t *steps_out,
                           hipStream_t s) {
     const int64_t blocks = (M + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, M, walk_flag,
-                       dihh, dstatus, dsteps, out_a, out_b, unstd, status, steps_out,
+                       rec, out_a, out_b, unstd, status, steps_out,
                        mode == MODE_POOLED ? 1 : 0);
     return hipGetLastError();
 }
@@ -632,12 +634,12 @@ hipError_t launch_standardize(int64_t M, const double *unstd, int8_t *status, co
 }
 
 hipError_t launch_ehh_finish(int64_t n, int64_t cap, const uint64_t *S, const int64_t *len,
-                             const double *dihh, const int32_t *dstatus, double *ehh,
+                             const WalkRec *rec, double *ehh,
                              double *ihh, int8_t *status, hipStream_t s) {
     const int64_t items = 2 * (cap + 1);
     const int64_t blocks = (items + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(ehh_finish_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, n, cap, S,
-                       len, dihh, dstatus, ehh, ihh, status);
+                       len, rec, ehh, ihh, status);
     return hipGetLastError();
 }
 

@@ -394,16 +394,11 @@ done:
     if (tid == 0) {
         const size_t o = (size_t)j * 2 + d;
         if (!TRACE) {
-            a.ihh[o * 2 + 0] = ihh0;
-            a.ihh[o * 2 + 1] = ihh1;
-            a.dstatus[o * 2 + 0] = status;
-            a.dstatus[o * 2 + 1] = status;
-            a.steps[o * 2 + 0] = steps0;
-            a.steps[o * 2 + 1] = steps1;
+            put_rec(a.rec + o * 2 + 0, ihh0, status, steps0);
+            put_rec(a.rec + o * 2 + 1, ihh1, status, steps1);
         } else {
-            a.ihh[d * 2 + 0] = ihh0;
-            a.ihh[d * 2 + 1] = ihh1;
-            a.dstatus[d] = status;
+            put_rec(a.rec + d * 2 + 0, ihh0, status, step);
+            put_rec(a.rec + d * 2 + 1, ihh1, status, step);
             a.trLen[d] = step;
         }
     }

@@ -690,12 +690,8 @@ done:
     (void)pmode;
     if (tid == 0) {
         const size_t o = (size_t)j * 2 + d;
-        G.ihh[o * 2 + 0] = ihh0;
-        G.ihh[o * 2 + 1] = ihh1;
-        G.dstatus[o * 2 + 0] = status;
-        G.dstatus[o * 2 + 1] = status;
-        G.steps[o * 2 + 0] = steps0;
-        G.steps[o * 2 + 1] = MODE == MODE_CORE ? steps1 : 0;
+        put_rec(G.rec + o * 2 + 0, ihh0, status, steps0);
+        put_rec(G.rec + o * 2 + 1, ihh1, status, MODE == MODE_CORE ? steps1 : 0);
     }
     return;
 overflowed:

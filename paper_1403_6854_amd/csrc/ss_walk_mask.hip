@@ -738,16 +738,10 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
     if (lane == 0) {
         const size_t o = (size_t)j * 2 + d;
         if (MODE == MODE_CORE) {
-            a.ihh[o * 2 + core] = ihhA;
-            a.dstatus[o * 2 + core] = status;
-            a.steps[o * 2 + core] = steps;
+            put_rec(a.rec + o * 2 + core, ihhA, status, steps);
         } else {
-            a.ihh[o * 2 + 0] = ihhA;
-            a.ihh[o * 2 + 1] = ihhB;
-            a.dstatus[o * 2 + 0] = status;
-            a.dstatus[o * 2 + 1] = status;
-            a.steps[o * 2 + 0] = steps;
-            a.steps[o * 2 + 1] = 0;
+            put_rec(a.rec + o * 2 + 0, ihhA, status, steps);
+            put_rec(a.rec + o * 2 + 1, ihhB, status, 0);
         }
     }
 }

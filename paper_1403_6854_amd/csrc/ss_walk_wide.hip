@@ -663,16 +663,10 @@ __device__ void wide_walk_one(const Region &R, int64_t j, int d, int core, char 
     if (tid == 0) {
         const size_t o = (size_t)j * 2 + d;
         if (!pooled) {
-            R.ihh[o * 2 + core] = ihhA;
-            R.dstatus[o * 2 + core] = status;
-            R.steps[o * 2 + core] = steps;
+            put_rec(R.rec + o * 2 + core, ihhA, status, steps);
         } else {
-            R.ihh[o * 2 + 0] = ihhA;
-            R.ihh[o * 2 + 1] = ihhB;
-            R.dstatus[o * 2 + 0] = status;
-            R.dstatus[o * 2 + 1] = status;
-            R.steps[o * 2 + 0] = steps;
-            R.steps[o * 2 + 1] = 0;
+            put_rec(R.rec + o * 2 + 0, ihhA, status, steps);
+            put_rec(R.rec + o * 2 + 1, ihhB, status, 0);
         }
     }
 }
