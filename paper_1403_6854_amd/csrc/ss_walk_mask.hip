@@ -107,6 +107,41 @@ __device__ __forceinline__ double lane_before(double v, double first) {
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// Adds the first n of the wave's per-lane terms (lane t: the term of step t
+// of a 64-marker batch) to each running iHH sum, one after another in step
+// order -- the definition's rounding, identical to adding them one by one.
+// The terms are staged in LDS (64 doubles per sum at buf, a region no lane
+// reads meanwhile); lanes t >= n stage +0.0, which leaves a non-negative sum
+// as it is, so the adds run several at a time from broadcast LDS reads
+// instead of two lane reads, a scalar loop step and an add per term.
+template <int NS>
+__device__ __forceinline__ void add_terms(double (&acc)[NS], const double (&term)[NS], int n,
+                                          double *buf) {
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) buf[s * 64 + lane] = lane < n ? term[s] : 0.0;
+    __syncthreads();
+    // K terms of each sum per iteration, the loop kept rolled: unrolled, its
+    // loads in flight took up to 128 VGPRs
+    constexpr int K = 8 / NS;
+    const double2 *b2 = (const double2 *)buf;
+#pragma unroll 1
+    for (int b = 0; b < n; b += K) {
+        double2 v[NS][K / 2];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int k = 0; k < K / 2; ++k) v[s][k] = b2[s * 32 + (b >> 1) + k];
+#pragma unroll
+        for (int k = 0; k < K / 2; ++k)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                acc[s] += v[s][k].x;
+                acc[s] += v[s][k].y;
+            }
+    }
+}
+
 // Largest S in [0, P] with (double)S / (double)P < cutoff (P >= 1), found by
 // testing 64 consecutive candidates around cutoff * P, one per lane.
 __device__ __forceinline__ uint32_t stop_threshold(uint32_t P, double cutoff, int lane) {
@@ -149,6 +184,12 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
     uint32_t *pairs = (uint32_t *)stage;       // [PCAP] a | b << 16, member indices (pairwise phase)
     uint32_t *hist = (uint32_t *)(stage + kUnionWords);   // [64] splits per marker
     uint16_t *memb = (uint16_t *)(hist + 64);  // [64 W] haplotypes of the pair list's members
+    // [1 or 2][64] trapezoid terms of a batch, staged once the batch's rows
+    // (per-marker phase) or keys (pairwise phase) are no longer read; the
+    // pooled walks' second 64 may reach into the class staging area, which is
+    // idle between markers
+    double *tbuf = (double *)rowbuf;
+    static_assert(64 * W + kStageWords >= (MODE == MODE_CORE ? 64 : 128), "room for the terms");
 
     const int lane = threadIdx.x;
     const int q = lane / LPC;     // class slot within a row
@@ -590,8 +631,10 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
             if (MODE == MODE_CORE) {
                 const double e = (double)sb / PA;
                 const double prev = lane_before(e, epA);
-                const double term = 0.5 * (prev + e) * g64;
-                for (int t = 0; t < nterm; ++t) ihhA += readlane_f64(term, t);
+                double acc[1] = {ihhA};
+                const double term[1] = {0.5 * (prev + e) * g64};
+                add_terms<1>(acc, term, nterm, tbuf);
+                ihhA = acc[0];
                 epA = readlane_f64(e, nterm - 1);
             } else {
                 const uint32_t sA = pack16 ? (sb & 0xFFFFu) : sb;
@@ -600,12 +643,11 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
                 const double eB = (double)sB / PB;
                 const double pA = lane_before(eA, epA);
                 const double pB = lane_before(eB, epB);
-                const double tA = 0.5 * (pA + eA) * g64;
-                const double tB = 0.5 * (pB + eB) * g64;
-                for (int t = 0; t < nterm; ++t) {
-                    ihhA += readlane_f64(tA, t);
-                    ihhB += readlane_f64(tB, t);
-                }
+                double acc[2] = {ihhA, ihhB};
+                const double term[2] = {0.5 * (pA + eA) * g64, 0.5 * (pB + eB) * g64};
+                add_terms<2>(acc, term, nterm, tbuf);
+                ihhA = acc[0];
+                ihhB = acc[1];
                 epA = readlane_f64(eA, nterm - 1);
                 epB = readlane_f64(eB, nterm - 1);
             }
@@ -706,8 +748,10 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
             if (MODE == MODE_CORE) {
                 const double e = (double)sb / PA;
                 const double prev = lane_before(e, epA);
-                const double term = 0.5 * (prev + e) * g64;
-                for (int t = 0; t < nterm; ++t) ihhA += readlane_f64(term, t);
+                double acc[1] = {ihhA};
+                const double term[1] = {0.5 * (prev + e) * g64};
+                add_terms<1>(acc, term, nterm, tbuf);
+                ihhA = acc[0];
                 epA = readlane_f64(e, nterm - 1);
             } else {
                 const uint32_t sA = pack16 ? (sb & 0xFFFFu) : sb;
@@ -716,12 +760,11 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
                 const double eB = (double)sB / PB;
                 const double pA = lane_before(eA, epA);
                 const double pB = lane_before(eB, epB);
-                const double tA = 0.5 * (pA + eA) * g64;
-                const double tB = 0.5 * (pB + eB) * g64;
-                for (int t = 0; t < nterm; ++t) {
-                    ihhA += readlane_f64(tA, t);
-                    ihhB += readlane_f64(tB, t);
-                }
+                double acc[2] = {ihhA, ihhB};
+                const double term[2] = {0.5 * (pA + eA) * g64, 0.5 * (pB + eB) * g64};
+                add_terms<2>(acc, term, nterm, tbuf);
+                ihhA = acc[0];
+                ihhB = acc[1];
                 epA = readlane_f64(eA, nterm - 1);
                 epB = readlane_f64(eB, nterm - 1);
             }
