@@ -171,8 +171,10 @@ hipEvent_t take_event() {
         g_timing.pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fences (with them, each record held the
+    // stream for about 3 us more)
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
@@ -461,19 +463,33 @@ ss::Region region_of(const Scan &sc) {
 // Per-site passes before the walk.
 int prepare_scan(const Scan &sc, const ss_params *p, hipStream_t s) {
     const ss::WalkArgs &a = sc.args;
-    const int64_t M = a.M;
-    if (sc.mode == ss::MODE_CORE)
-        SS_HIP(ss::launch_site_stats(a.bitsA, a.wpsA, a.nA, M, p->maf_cutoff, nbins_of(p), sc.freq,
-                                     sc.w.bin, sc.w.walk_flag, sc.status, s));
+    ss::SitePass sp{};
+    sp.M = a.M;
+    if (sc.mode == ss::MODE_CORE) {
+        sp.bits = a.bitsA;
+        sp.wps = a.wpsA;
+        sp.n = a.nA;
+        sp.maf_cutoff = p->maf_cutoff;
+        sp.nbins = nbins_of(p);
+        sp.freq = sc.freq;
+        sp.bin = sc.w.bin;
+        sp.walk_flag = sc.w.walk_flag;
+        sp.status = sc.status;
+    }
+    sp.pos = a.pos;
+    sp.gpos = a.gpos;
+    sp.gap_scale = p->gap_scale_bp;
+    sp.max_gap = p->max_gap_bp;
+    sp.physical = p->physical_map;
+    sp.seg = sc.w.seg;
+    sp.zero_me = sc.w.redo;
     // haplotype-major copies feed the pairwise phases
-    const bool need_a = sc.route == RT_WIDE || (sc.route == RT_MASK && sc.mode == ss::MODE_CORE);
-    const bool need_b = sc.route == RT_WIDE && sc.mode == ss::MODE_POOLED;
-    if (need_a) SS_HIP(ss::launch_transpose(a.bitsA, a.wpsA, a.nA, M, a.mwp, sc.w.hbits, s));
-    if (need_b)
-        SS_HIP(ss::launch_transpose(a.bitsB, a.wpsB, a.nB, M, a.mwp,
-                                    sc.w.hbits + (size_t)a.nA * (size_t)a.mwp, s));
-    SS_HIP(ss::launch_segments(M, a.pos, a.gpos, p->gap_scale_bp, p->max_gap_bp, p->physical_map,
-                               sc.w.seg, sc.w.redo, s));
+    sp.mwp = a.mwp;
+    if (sc.route == RT_WIDE || (sc.route == RT_MASK && sc.mode == ss::MODE_CORE))
+        sp.tr[0] = {a.bitsA, a.wpsA, a.nA, sc.w.hbits};
+    if (sc.route == RT_WIDE && sc.mode == ss::MODE_POOLED)
+        sp.tr[1] = {a.bitsB, a.wpsB, a.nB, sc.w.hbits + (size_t)a.nA * (size_t)a.mwp};
+    SS_HIP(ss::launch_site_pass(sp, s));
     return SS_OK;
 }
 

@@ -74,6 +74,7 @@ struct WalkArgs {
     int32_t skip_classes;
 };
 
+
 struct WalkShape {
     int threads;      // workgroup size, multiple of 64
     int slots;        // 64-haplotype words handled per wave and step
@@ -248,17 +249,40 @@ hipError_t launch_wide_walk(const Region *regs, int32_t nreg, int64_t total_item
 // Site-level kernels.
 hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps,
                        uint64_t *bits, hipStream_t s);
-hipError_t launch_segments(int64_t M, const int64_t *pos, const double *gpos, int64_t gap_scale,
-                           int64_t max_gap, int32_t physical, double *seg, int32_t *zero_me,
-                           hipStream_t s);
 // Haplotype-major transposed matrix: [n][mwp] words, mwp = ceil(M/64) + 2.
 inline int64_t hap_major_words(int64_t M) { return (M + 63) / 64 + 2; }
-hipError_t launch_transpose(const uint64_t *bits, int64_t wps, int64_t n, int64_t M, int64_t mwp,
-                            uint64_t *hbits, hipStream_t s);
-hipError_t launch_site_stats(const uint64_t *bits, int64_t wps, int64_t n, int64_t M,
-                             double maf_cutoff, int32_t nbins, double *freq,
-                             int32_t *bin, uint8_t *walk_flag, int8_t *status,
-                             hipStream_t s);
+// The per-site passes of a scan before its walk, in one launch: site
+// statistics (iHS; skipped when bits is null), segment lengths (always), and
+// up to two haplotype-major copies (those with a non-null hbits).
+struct SitePass {
+    int64_t M;
+    // site statistics
+    const uint64_t *bits;
+    int64_t wps, n;
+    double maf_cutoff;
+    int32_t nbins;
+    double *freq;
+    int32_t *bin;
+    uint8_t *walk_flag;
+    int8_t *status;
+    // segments
+    const int64_t *pos;
+    const double *gpos;
+    int64_t gap_scale, max_gap;
+    int32_t physical;
+    double *seg;
+    int32_t *zero_me;   // a counter cleared on the way (or null)
+    // haplotype-major copies
+    int64_t mwp;
+    struct Copy {
+        const uint64_t *bits;
+        int64_t wps, n;
+        uint64_t *hbits;
+    } tr[2];
+    // workgroups of each part (set by the launcher)
+    int64_t b_stats, b_seg, b_tr[2];
+};
+hipError_t launch_site_pass(SitePass p, hipStream_t s);
 hipError_t launch_combine(int mode, int64_t M, const uint8_t *walk_flag,
                           const WalkRec *rec, double *out_a, double *out_b,
                           double *unstd, int8_t *status, int32_t *steps_out,

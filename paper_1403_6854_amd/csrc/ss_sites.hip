@@ -51,20 +51,25 @@ __global__ void __launch_bounds__(kBlock) pack_kernel(const uint8_t *__restrict_
     }
 }
 
+// The per-site passes before a walk -- site statistics, the haplotype-major
+// copies and the segment lengths -- read different inputs and write
+// different outputs, so they run as parts of one launch, each in its own
+// range of workgroups; each part is a handful of latency-bound load rounds,
+// and in one launch they overlap instead of queueing one after another.
+
 // Haplotype-major copy of the bit matrix for the pairwise phase of the walk:
 // row h holds haplotype h's alleles at every site, 64 sites per word, with
 // one zero word of padding on each side (word w covers sites 64(w-1) ..
 // 64(w-1)+63), so that any 64 consecutive sites are two neighbouring words.
 // One wave per (64-site block, 64-haplotype word): lane i loads the word of
 // site i of the block, and 64 ballots transpose the 64 x 64 bit block.
-__global__ void __launch_bounds__(kBlock) transpose_kernel(const uint64_t *__restrict__ bits,
-                                                           int64_t wps, int64_t n, int64_t M,
-                                                           int64_t mwp,
-                                                           uint64_t *__restrict__ hbits) {
+__device__ void transpose_part(int64_t blk, int64_t nblk, const uint64_t *__restrict__ bits,
+                               int64_t wps, int64_t n, int64_t M, int64_t mwp,
+                               uint64_t *__restrict__ hbits) {
     const int lane = threadIdx.x & 63;
     const int64_t words = (n + 63) / 64;
-    const int64_t stride = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); item < mwp * words;
+    const int64_t stride = nblk * (kBlock / 64);
+    for (int64_t item = blk * (kBlock / 64) + (threadIdx.x >> 6); item < mwp * words;
          item += stride) {
         const int64_t wp = item / words;          // padded block of 64 sites
         const int64_t w = item - wp * words;      // word of 64 haplotypes
@@ -85,13 +90,12 @@ __global__ void __launch_bounds__(kBlock) transpose_kernel(const uint64_t *__res
 // Sec. 1.2 applied once per scan instead of once per walk step: seg[k] is the
 // length of the segment from site k-1 to site k, scaled by gap_scale / b when
 // its physical length b exceeds gap_scale, or -1 when b > max_gap (the walk
-// aborts there).  seg[0] is unused.
-__global__ void __launch_bounds__(kBlock) segment_kernel(int64_t M, const int64_t *__restrict__ pos,
-                                                         const double *__restrict__ gpos,
-                                                         int64_t gap_scale, int64_t max_gap,
-                                                         int32_t physical, double *__restrict__ seg,
-                                                         int32_t *__restrict__ zero_me) {
-    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+// aborts there).  seg[0] is unused.  One lane per site.
+__device__ void segment_part(int64_t blk, int64_t M, const int64_t *__restrict__ pos,
+                             const double *__restrict__ gpos, int64_t gap_scale, int64_t max_gap,
+                             int32_t physical, double *__restrict__ seg,
+                             int32_t *__restrict__ zero_me) {
+    const int64_t k = blk * kBlock + threadIdx.x;
     if (k == 0 && zero_me) *zero_me = 0;   // the walk's overflow-list counter
     if (k >= M) return;
     if (k == 0) {
@@ -110,16 +114,52 @@ __global__ void __launch_bounds__(kBlock) segment_kernel(int64_t M, const int64_
 // Per-site derived count n1, derived frequency, frequency bin, MAF filter
 // (Sec. 1.2: sites with MAF < cutoff are not scored) and the cores' sizes
 // (a core with fewer than two haplotypes leaves the score undefined).
-// One wave per site.
-__global__ void __launch_bounds__(kBlock) site_stats_kernel(
-    const uint64_t *__restrict__ bits, int64_t wps, int64_t n, int64_t M, double maf_cutoff,
-    int32_t nbins, double *__restrict__ freq, int32_t *__restrict__ bin,
-    uint8_t *__restrict__ walk_flag, int8_t *__restrict__ status) {
+__device__ void site_outputs(int64_t site, int64_t n, int64_t n1, double maf_cutoff, int32_t nbins,
+                             double *__restrict__ freq, int32_t *__restrict__ bin,
+                             uint8_t *__restrict__ walk_flag, int8_t *__restrict__ status) {
+    const int64_t n0 = n - n1;
+    freq[site] = (double)n1 / (double)n;
+    int64_t b = ((int64_t)nbins * n1) / n;
+    if (b > nbins - 1) b = nbins - 1;
+    bin[site] = (int32_t)b;
+    const double maf = (double)(n0 < n1 ? n0 : n1) / (double)n;
+    int8_t st = ST_OK;
+    if (maf < maf_cutoff) st = ST_MAF;
+    else if (n0 < 2 || n1 < 2) st = ST_UNDEF;
+    status[site] = st;
+    walk_flag[site] = st == ST_OK ? 1 : 0;
+}
+
+// Rows of up to kLaneRowWords words are counted one site per lane (neighbouring
+// lanes read neighbouring rows); longer rows one site per wave, a word per lane.
+constexpr int64_t kLaneRowWords = 4;
+
+__host__ __device__ inline int64_t site_stats_items(int64_t n, int64_t M) {
+    return (n + 63) / 64 <= kLaneRowWords ? (M + 63) / 64 : M;   // waves' worth of work
+}
+
+__device__ void site_stats_part(int64_t blk, int64_t nblk, const uint64_t *__restrict__ bits,
+                                int64_t wps, int64_t n, int64_t M, double maf_cutoff,
+                                int32_t nbins, double *__restrict__ freq,
+                                int32_t *__restrict__ bin, uint8_t *__restrict__ walk_flag,
+                                int8_t *__restrict__ status) {
     const int lane = threadIdx.x & 63;
     const int64_t words = (n + 63) / 64;
-    const int64_t stride = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t site = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); site < M;
-         site += stride) {
+    if (words <= kLaneRowWords) {
+        for (int64_t site = blk * kBlock + threadIdx.x; site < M; site += nblk * kBlock) {
+            uint32_t c = 0;
+            for (int64_t w = 0; w < words; ++w) {
+                uint64_t x = bits[site * wps + w];
+                const int64_t valid = n - w * 64;
+                if (valid < 64) x &= (1ull << valid) - 1ull;
+                c += (uint32_t)__popcll(x);
+            }
+            site_outputs(site, n, c, maf_cutoff, nbins, freq, bin, walk_flag, status);
+        }
+        return;
+    }
+    const int64_t stride = nblk * (kBlock / 64);
+    for (int64_t site = blk * (kBlock / 64) + (threadIdx.x >> 6); site < M; site += stride) {
         uint32_t c = 0;
         for (int64_t w = lane; w < words; w += 64) {
             uint64_t x = bits[site * wps + w];
@@ -129,19 +169,34 @@ __global__ void __launch_bounds__(kBlock) site_stats_kernel(
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-        if (lane == 0) {
-            const int64_t n1 = c, n0 = n - n1;
-            freq[site] = (double)n1 / (double)n;
-            int64_t b = ((int64_t)nbins * n1) / n;
-            if (b > nbins - 1) b = nbins - 1;
-            bin[site] = (int32_t)b;
-            const double maf = (double)(n0 < n1 ? n0 : n1) / (double)n;
-            int8_t st = ST_OK;
-            if (maf < maf_cutoff) st = ST_MAF;
-            else if (n0 < 2 || n1 < 2) st = ST_UNDEF;
-            status[site] = st;
-            walk_flag[site] = st == ST_OK ? 1 : 0;
+        if (lane == 0) site_outputs(site, n, c, maf_cutoff, nbins, freq, bin, walk_flag, status);
+    }
+}
+
+// Workgroups [0, b_stats) count sites, [b_stats, b_seg) compute segments,
+// then one range per haplotype-major copy.
+__global__ void __launch_bounds__(kBlock) site_pass_kernel(SitePass p) {
+    int64_t blk = blockIdx.x;
+    if (blk < p.b_stats) {
+        site_stats_part(blk, p.b_stats, p.bits, p.wps, p.n, p.M, p.maf_cutoff, p.nbins, p.freq,
+                        p.bin, p.walk_flag, p.status);
+        return;
+    }
+    blk -= p.b_stats;
+    if (blk < p.b_seg) {
+        segment_part(blk, p.M, p.pos, p.gpos, p.gap_scale, p.max_gap, p.physical, p.seg,
+                     p.zero_me);
+        return;
+    }
+    blk -= p.b_seg;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        if (blk < p.b_tr[t]) {
+            transpose_part(blk, p.b_tr[t], p.tr[t].bits, p.tr[t].wps, p.tr[t].n, p.M, p.mwp,
+                           p.tr[t].hbits);
+            return;
         }
+        blk -= p.b_tr[t];
     }
 }
 
@@ -553,29 +608,15 @@ hipError_t launch_pack(const uint8_t *alleles, int64_t n, int64_t M, int64_t wps
     return hipGetLastError();
 }
 
-hipError_t launch_segments(int64_t M, const int64_t *pos, const double *gpos, int64_t gap_scale,
-                           int64_t max_gap, int32_t physical, double *seg, int32_t *zero_me,
-                           hipStream_t s) {
-    const int64_t blocks = (M + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(segment_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, M, pos, gpos,
-                       gap_scale, max_gap, physical, seg, zero_me);
-    return hipGetLastError();
-}
-
-hipError_t launch_transpose(const uint64_t *bits, int64_t wps, int64_t n, int64_t M, int64_t mwp,
-                            uint64_t *hbits, hipStream_t s) {
-    const int64_t blocks = wave_blocks(mwp * ((n + 63) / 64));
-    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, bits, wps, n, M,
-                       mwp, hbits);
-    return hipGetLastError();
-}
-
-hipError_t launch_site_stats(const uint64_t *bits, int64_t wps, int64_t n, int64_t M,
-                             double maf_cutoff, int32_t nbins, double *freq, int32_t *bin,
-                             uint8_t *walk_flag, int8_t *status, hipStream_t s) {
-    const int64_t blocks = wave_blocks(M);
-    hipLaunchKernelGGL(site_stats_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, bits, wps,
-                       n, M, maf_cutoff, nbins, freq, bin, walk_flag, status);
+hipError_t launch_site_pass(SitePass p, hipStream_t s) {
+    p.b_stats = p.bits ? wave_blocks(site_stats_items(p.n, p.M)) : 0;
+    p.b_seg = (p.M + kBlock - 1) / kBlock;
+    for (int t = 0; t < 2; ++t)
+        p.b_tr[t] = p.tr[t].hbits ? wave_blocks(p.mwp * ((p.tr[t].n + 63) / 64)) : 0;
+    const int64_t blocks = p.b_stats + p.b_seg + p.b_tr[0] + p.b_tr[1];
+    if (blocks <= 0) return hipSuccess;
+    if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(site_pass_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, p);
     return hipGetLastError();
 }
 
