@@ -112,7 +112,6 @@ struct ScanWs {
     double *binpart;      // per-tile partial sums of the bin statistics
     uint64_t *hbits;      // [nA (+ nB)][mwp] haplotype-major copies
     double *seg;          // [M] segment lengths with the gap rules applied
-    int32_t *redo;        // [1 + 2M] overflow count, then the walks to redo
     ss::Region *region;   // [1] descriptor for the persistent walk
     unsigned long long *counter;   // [kGroupCtrWords] work queues of the two launches, redo count
     int64_t *wredo;       // [2M] walks the capped class table could not hold
@@ -134,7 +133,6 @@ ScanWs carve_scan(void *base, int64_t M, int nbins, int64_t n_hapmajor) {
     w.binpart = (double *)take(8 * (size_t)ss::standardize_scratch_doubles(M, nbins));
     w.hbits = (uint64_t *)take(8 * (size_t)n_hapmajor * (size_t)ss::hap_major_words(M));
     w.seg = (double *)take(8 * (size_t)M);
-    w.redo = (int32_t *)take(4 * (1 + 2 * (size_t)M));
     w.region = (ss::Region *)take(sizeof(ss::Region));
     w.counter = (unsigned long long *)take(kGroupCtrWords * sizeof(unsigned long long));
     w.wredo = (int64_t *)take(8 * 2 * (size_t)M);
@@ -333,10 +331,6 @@ size_t route_lds(Route r, int32_t nA, int32_t nB, int mode) {
     return 0;   // checked by make_wide_cfg
 }
 
-// Workgroups of the pass that redoes, with the class-id walk, the walks the
-// bitmask kernel could not hold; it exits at once when there are none.
-constexpr int kRedoBlocks = 256;
-
 // Events around a walk launch while timing is enabled.
 struct TimedRegion {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -434,8 +428,6 @@ void init_scan(Scan &sc, void *base, const ss_params *p) {
     a.mwp = ss::hap_major_words(a.M);
     a.hbits = sc.mode == ss::MODE_CORE ? sc.w.hbits : nullptr;
     a.seg = sc.w.seg;
-    a.redo_count = sc.w.redo;
-    a.redo_list = sc.w.redo + 1;
 }
 
 ss::Region region_of(const Scan &sc) {
@@ -482,7 +474,6 @@ int prepare_scan(const Scan &sc, const ss_params *p, hipStream_t s) {
     sp.max_gap = p->max_gap_bp;
     sp.physical = p->physical_map;
     sp.seg = sc.w.seg;
-    sp.zero_me = sc.w.redo;
     // haplotype-major copies feed the pairwise phases
     sp.mwp = a.mwp;
     if (sc.route == RT_WIDE || (sc.route == RT_MASK && sc.mode == ss::MODE_CORE))
@@ -500,7 +491,6 @@ int walk_direct(const Scan &sc, hipStream_t s) {
         ss::WalkArgs m = a;
         m.skip_classes = g_mask_skip;
         SS_HIP(ss::launch_mask_walk(m, sc.mode, g_mask_lpc, a.M, s));
-        SS_HIP(ss::launch_walk_list(a, sc.mode, kRedoBlocks, s));
     } else {
         SS_HIP(ss::launch_walk(a, sc.mode, false, a.M, s));
     }

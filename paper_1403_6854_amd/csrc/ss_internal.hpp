@@ -65,10 +65,6 @@ struct WalkArgs {
     // per-segment genetic lengths with the gap rules applied (segment k-1 -> k
     // at index k; -1 marks an abort gap); null: walks compute them
     const double *seg;
-    // walks the bitmask kernel could not hold (more live classes than its
-    // registers): entries 2 * site + direction, redone by the class-id walk
-    int32_t *redo_list;         // [2 M]
-    int32_t *redo_count;        // [1], zeroed by the segment pass
     // bitmask walk: batches with at most this many class slots test all their
     // markers at once and refine only those that cut a class
     int32_t skip_classes;
@@ -102,7 +98,6 @@ bool mask_walk_supported(int32_t nA, int32_t nB, int mode);
 hipError_t launch_mask_walk(const WalkArgs &a, int mode, int lpc, int64_t n_blocks, hipStream_t s);
 hipError_t launch_walk(const WalkArgs &a, int mode, bool trace, int64_t n_blocks,
                        hipStream_t s);
-hipError_t launch_walk_list(const WalkArgs &a, int mode, int blocks, hipStream_t s);
 
 // ---- batched walks over many regions (ss_walk_wide.hip) ----------------------
 // One region of a batch: a haplotype matrix (iHS) or a pair of them (XPEHH),
@@ -271,7 +266,6 @@ struct SitePass {
     int64_t gap_scale, max_gap;
     int32_t physical;
     double *seg;
-    int32_t *zero_me;   // a counter cleared on the way (or null)
     // haplotype-major copies
     int64_t mwp;
     struct Copy {

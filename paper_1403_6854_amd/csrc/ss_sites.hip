@@ -93,10 +93,8 @@ __device__ void transpose_part(int64_t blk, int64_t nblk, const uint64_t *__rest
 // aborts there).  seg[0] is unused.  One lane per site.
 __device__ void segment_part(int64_t blk, int64_t M, const int64_t *__restrict__ pos,
                              const double *__restrict__ gpos, int64_t gap_scale, int64_t max_gap,
-                             int32_t physical, double *__restrict__ seg,
-                             int32_t *__restrict__ zero_me) {
+                             int32_t physical, double *__restrict__ seg) {
     const int64_t k = blk * kBlock + threadIdx.x;
-    if (k == 0 && zero_me) *zero_me = 0;   // the walk's overflow-list counter
     if (k >= M) return;
     if (k == 0) {
         seg[0] = -1.0;
@@ -184,8 +182,7 @@ __global__ void __launch_bounds__(kBlock) site_pass_kernel(SitePass p) {
     }
     blk -= p.b_stats;
     if (blk < p.b_seg) {
-        segment_part(blk, p.M, p.pos, p.gpos, p.gap_scale, p.max_gap, p.physical, p.seg,
-                     p.zero_me);
+        segment_part(blk, p.M, p.pos, p.gpos, p.gap_scale, p.max_gap, p.physical, p.seg);
         return;
     }
     blk -= p.b_seg;

@@ -37,25 +37,11 @@
 //     gives S at each of the 64 markers, and the surviving pairs are compacted
 //     in place.  Long walks then cost a few instructions per pair per 64
 //     markers instead of a full refinement per marker.
-#include "ss_internal.hpp"
+#include "ss_walk_ids.hpp"   // walk_one, choose2, wave_sum, readlane64, readlane_f64
 
 namespace ss {
 
 namespace {
-
-__device__ __forceinline__ uint32_t choose2(uint32_t x) { return (x * (x - 1u)) >> 1; }
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return __ockl_wfred_add_u32(v); }
-
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, int i) {
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, i);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), i);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int i) {
-    return __builtin_bit_cast(double, readlane64(__builtin_bit_cast(uint64_t, v), i));
-}
 
 // Sum of v over the LPC consecutive lanes of a class (LPC = 1, 2, 4 or 8).
 template <int LPC>
@@ -774,8 +760,13 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
     }
 
     if (overflow) {
-        // the class-id walk redoes this site and direction for both cores
-        if (lane == 0) a.redo_list[atomicAdd(a.redo_count, 1)] = (int32_t)(j * 2 + d);
+        // More live classes than the wave holds: this wave walks the site and
+        // direction again from x0 with the class-id walk (class ids in
+        // registers, counters in this workgroup's LDS), which writes the
+        // records of both cores; the other core's wave, if it did not
+        // overflow, writes the same values for its own.
+        __syncthreads();
+        walk_one<MODE, false, W>(a, j, d);
         return;
     }
     if (lane == 0) {
@@ -830,11 +821,9 @@ MaskShape mask_walk_shape(int32_t nA, int32_t nB, int mode, int lpc) {
     if (lpc > sh.words || (lpc & (lpc - 1))) return MaskShape{};
     sh.lpc = lpc;
     const int cpr = 64 / lpc;
-    const int kmax = n / 2 + 2;   // classes with >= 2 members, plus the two at x0
-    // Walks keep one row of classes in registers; walks that would need more
-    // (rare: more than 64 / lpc multi-member classes at once) are listed for
-    // the class-id walk.
-    (void)kmax;
+    // Walks keep one row of classes in registers; a walk that would need more
+    // (rare: more than 64 / lpc multi-member classes at once) is walked again
+    // by the class-id walk in the same workgroup, with this LDS.
     sh.rows = 1;
     if (sh.rows > 16) return MaskShape{};
     sh.pair_cap = mode == MODE_CORE ? mask_pair_cap(sh.words) : 0;
@@ -843,6 +832,9 @@ MaskShape mask_walk_shape(int32_t nA, int32_t nB, int mode, int lpc) {
                                                                       : (size_t)sh.pair_cap / 2;
     sh.lds = ((size_t)64 * sh.words + union_words) * sizeof(uint64_t) + 64 * sizeof(uint32_t) +
              (size_t)64 * sh.words * sizeof(uint16_t);   // member list of the pair list
+    const WalkShape ids = walk_shape(nA, nB, mode);      // the class-id walk's, for overflows
+    if (ids.threads != 64 || ids.slots > sh.words) return MaskShape{};
+    if (ids.lds > sh.lds) sh.lds = ids.lds;
     sh.ok = true;
     return sh;
 }

@@ -276,31 +276,35 @@ def test_xpehh_mask_lanes(ss, lpc):
     check_xpehh(got, ref, "xpehh lpc=%d" % lpc)
 
 
-def _many_classes(seed):
+def _many_classes(seed, n1=340, n_same=200):
     """A core whose walk holds more than 64 multi-member classes at once while
-    its EHH is still high: 200 identical carriers plus 70 distinct identical
-    pairs, told apart by a 7-marker code right after the core."""
+    its EHH is still high: n_same identical carriers plus (n1 - n_same) / 2
+    distinct identical pairs (70 by default), told apart by a 7-marker code
+    right after the core."""
     rng = np.random.default_rng(seed)
-    n1, n0, M, core = 340, 24, 160, 60
+    n0, M, core = 24, 160, 60
     n = n1 + n0
+    npairs = (n1 - n_same) // 2
     H = (rng.random((M, n)) < 0.5).astype(np.uint8)
     H[core, :n1] = 1
     H[core, n1:] = 0
     group = np.zeros(n1, dtype=np.int64)
-    group[200:] = 1 + (np.arange(n1 - 200) // 2)          # 70 pairs, codes 1..70
+    group[n_same:] = 1 + (np.arange(n1 - n_same) // 2)    # the pairs, codes 1..npairs
     for direction in (+1, -1):
         for b in range(7):
             H[core + direction * (b + 1), :n1] = (group >> b) & 1
         for t in range(8, 30):                            # identical within groups for a while
-            col = rng.integers(0, 2, size=71)
+            col = rng.integers(0, 2, size=npairs + 1)
             H[core + direction * t, :n1] = col[group]
     pos = (np.arange(M, dtype=np.int64) + 1) * 1000
     return H, pos, pos * 1e-6, core
 
 
-def test_ihs_more_classes_than_a_wave_row(ss, walk):
-    H, pos, gpos, core = _many_classes(3)
-    say("ss_ihs many classes walk=%s" % walk)
+@pytest.mark.parametrize("n1,n_same", [(340, 200), (230, 98)])
+def test_ihs_more_classes_than_a_wave_row(ss, walk, n1, n_same):
+    # 364 haplotypes: 8-word masks, 71 classes; 254: 4-word masks, 67 classes
+    H, pos, gpos, core = _many_classes(3, n1, n_same)
+    say("ss_ihs many classes n1=%d walk=%s" % (n1, walk))
     h = _hm(ss, H, pos, gpos)
     params = oracle.Params(maf_cutoff=0.0)
     got = _np(ss.ihs(h, ss.Params(**vars(params)), steps=True))
@@ -308,6 +312,21 @@ def test_ihs_more_classes_than_a_wave_row(ss, walk):
     check_ihs(got, ref, "many classes")
     assert ref["status"][core] in (0, 5)
     assert ref["steps"][core, 0, 1] > 8
+
+
+def test_xpehh_more_classes_than_a_wave_row(ss, walk):
+    # the two halves of the many-classes sample as populations A and B: the
+    # pooled walk holds more than 64 classes at once
+    H, pos, gpos, core = _many_classes(4)
+    A = np.ascontiguousarray(H[:, 0::2])
+    B = np.ascontiguousarray(H[:, 1::2])
+    say("ss_xpehh many classes walk=%s" % walk)
+    ha = _hm(ss, A, pos, gpos)
+    hb = _hm(ss, B, pos, gpos)
+    got = _np(ss.xpehh(ha, hb, steps=True))
+    ref = oracle.xpehh(A, B, pos, gpos)
+    check_xpehh(got, ref, "many classes")
+    assert ref["steps"][core].max() > 8
 
 
 def test_ihs_is_deterministic(ss, walk):
