@@ -473,7 +473,7 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 5), "peak": round(PEAK_INT32_TOPS, 3),
                 "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 6),
                 "traffic": traffic,
-                "kernel": "mask_walk_kernel<CORE,4,1,1> (+ walk_list_kernel overflow pass)",
+                "kernel": "mask_walk_kernel<CORE,4,1,1>",
                 "kernel_ms": round(walk_ms, 5),
                 "work_cells": W, "ops_per_cell": round(ops_per_cell, 5),
                 "ops_per_cell_source": "cell-update proxy: 51 VALU lane-ops per 256 cells",
