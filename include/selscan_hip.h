@@ -246,8 +246,8 @@ int ss_genome_standardize(const ss_std_region *regs, int32_t n_regs, int32_t op,
  *       walk of ss_scan_batch, else class ids),
  *   1 = class ids in LDS (any haplotype count): the plain kernel, one
  *       workgroup per (site, direction), launched over every site,
- *   2 = class bitmasks in registers (up to 512 haplotypes in the walk,
- *       pooled for XPEHH; larger inputs use class ids),
+ *   2 = class bitmasks in registers (iHS up to 1,024 haplotypes, XPEHH up
+ *       to 512 pooled; larger inputs use class ids),
  *   3 = the persistent walk of ss_scan_batch with its current configuration
  *       (ss_set_batch_config); inputs it cannot take use class ids.
  * Errors: SS_EARG for any other value.
@@ -305,8 +305,9 @@ typedef struct ss_batch_config {
     int32_t chunk;          /* work items taken per grab of the counter, >= 1            */
     int32_t blocks_per_cu;  /* persistent workgroups per CU; 0 = as many as fit          */
     int32_t order;          /* 0: regions in the order given; 1: most haplotypes first   */
-    int32_t small_kernel;   /* 1: regions of <= 512 haplotypes in the walk use the
-                               bitmask kernel; 0: the persistent launch takes them too  */
+    int32_t small_kernel;   /* 1: regions the bitmask kernel takes (iHS up to 1,024
+                               haplotypes, XPEHH up to 512 pooled) use it; 0: the
+                               persistent launch takes them too                          */
     int32_t kernel;         /* 0: class ids per haplotype with a pairwise tail, one item
                                per (site, direction) [default]; 1: per-core walks over
                                sorted member lists, one item per (site, direction, core) */
@@ -387,9 +388,12 @@ int ss_set_mask_skip(int max_classes);
 /*
  * ss_set_mask_lanes -- tuning of the bitmask walk kernel (process-wide):
  * how many lanes of a wave hold one class (1, 2, 4 or 8; each lane holds
- * words_per_class / lanes of its mask), or 0 for the default.  More lanes per
- * class cut the per-marker work when few classes are alive; fewer lanes fit
- * more classes in one row.  Results are identical for every setting.
+ * words_per_class / lanes of its mask), or 0 for the default (1 lane up to
+ * 8 words a class, 2 lanes for the 16-word masks of 513-1,024 haplotypes,
+ * which take 2 or 4).  More lanes per class cut the per-marker work when few
+ * classes are alive; fewer lanes fit more classes in one row; inputs a
+ * setting does not fit use class ids.  Results are identical for every
+ * setting.
  * Errors: SS_EARG for any other value.
  */
 int ss_set_mask_lanes(int lanes_per_class);

@@ -158,6 +158,10 @@ template <int MODE, int W, int LPC, int NR>
 __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_kernel(WalkArgs a) {
     constexpr int WPL = W / LPC;    // words per lane
     constexpr int CPR = 64 / LPC;   // classes per row
+    // the next batch's rows are loaded during the current one for masks of up
+    // to 8 words; wider masks would hold 2 W registers a lane across the
+    // whole batch for it, so they load their rows when the batch starts
+    constexpr bool kPrefetchRows = W <= 8;
     constexpr int PCAP = MODE == MODE_CORE ? mask_pair_cap(W) : 0;
     extern __shared__ uint64_t lds64[];
     // LDS regions; the pairwise phase stages no rows and compacts no classes,
@@ -448,12 +452,12 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
         // ---- lane i holds step i of the next 64: its row words go to LDS,
         // its segment (end of data, abort gap, or scaled genetic length)
         // stays in registers for the FP64 pass
-        if (pf_step != step) fetch(step, true, pf_rows, pf_seg, pf_inr);
+        if (pf_step != step || !kPrefetchRows) fetch(step, true, pf_rows, pf_seg, pf_inr);
 #pragma unroll
         for (int w = 0; w < W; ++w) rowbuf[lane * W + w] = pf_rows[w];
         const bool inr = pf_inr;
         const double segv = pf_seg;
-        fetch(step + 64, true, pf_rows, pf_seg, pf_inr);   // next batch, if the walk goes on
+        fetch(step + 64, kPrefetchRows, pf_rows, pf_seg, pf_inr);   // next batch, if the walk goes on
         pf_step = step + 64;
         int32_t stl = ST_OK;
         double gl = 0.0;
@@ -803,6 +807,16 @@ hipError_t launch_lpc(const WalkArgs &a, const MaskShape &sh, int64_t n_blocks, 
     }
 }
 
+// 16-word masks: two or four lanes a class
+template <int MODE>
+hipError_t launch_wide(const WalkArgs &a, const MaskShape &sh, int64_t n_blocks, hipStream_t s) {
+    switch (sh.lpc) {
+        case 2: return launch_nr<MODE, 16, 2>(a, sh.rows, sh.lds, n_blocks, s);
+        case 4: return launch_nr<MODE, 16, 4>(a, sh.rows, sh.lds, n_blocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 int pow2_at_least(int x) {
     int p = 1;
     while (p < x) p *= 2;
@@ -815,10 +829,17 @@ MaskShape mask_walk_shape(int32_t nA, int32_t nB, int mode, int lpc) {
     MaskShape sh{};
     const int words = (nA + 63) / 64 + (mode == MODE_POOLED ? (nB + 63) / 64 : 0);
     const int n = nA + (mode == MODE_POOLED ? nB : 0);
-    if (words > 8 || n > 512) return sh;
-    sh.words = pow2_at_least(words);   // 1, 2, 4 or 8
-    if (lpc <= 0) lpc = 1;   // default: one class per lane (64 classes per row)
+    // 16-word masks for iHS only: pooled walks of 513-1,024 haplotypes took
+    // longer in them than in the persistent class-id walk (0.70 against
+    // 0.56 ms on 500 + 500 x 17,142), iHS walks less (2.53 against 3.33 ms
+    // on 1,000 x 11,655)
+    if (words > (mode == MODE_CORE ? 16 : 8) || n > (mode == MODE_CORE ? 1024 : 512)) return sh;
+    sh.words = pow2_at_least(words);   // 1, 2, 4, 8 or 16
+    // default: one class per lane (64 classes per row) up to 8 words; 16-word
+    // masks take two lanes a class (32 classes per row, 8 words a lane)
+    if (lpc <= 0) lpc = sh.words == 16 ? 2 : 1;
     if (lpc > sh.words || (lpc & (lpc - 1))) return MaskShape{};
+    if (sh.words == 16 && lpc != 2 && lpc != 4) return MaskShape{};
     sh.lpc = lpc;
     const int cpr = 64 / lpc;
     // Walks keep one row of classes in registers; a walk that would need more
@@ -857,6 +878,7 @@ hipError_t launch_mask_walk(const WalkArgs &a, int mode, int lpc, int64_t n_bloc
                             : launch_lpc<MODE_POOLED, 4>(a, sh, n_blocks, s);
         case 8: return core ? launch_lpc<MODE_CORE, 8>(a, sh, n_blocks, s)
                             : launch_lpc<MODE_POOLED, 8>(a, sh, n_blocks, s);
+        case 16: return core ? launch_wide<MODE_CORE>(a, sh, n_blocks, s) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

@@ -229,7 +229,7 @@ def test_ihs_edge_cases(ss, walk, case):
     check_ihs(got, ref, case)
 
 
-@pytest.mark.parametrize("n", [3, 63, 64, 65, 128, 129, 256, 257, 400, 511, 512, 513])
+@pytest.mark.parametrize("n", [3, 63, 64, 65, 128, 129, 256, 257, 400, 511, 512, 513, 700, 1024, 1025])
 def test_ihs_ragged_haplotype_counts(ss, walk, n):
     d = hapgen.random_haplotypes(n, 700, 40 + n, n_founders=max(2, n // 12), switch_p=0.01)
     say("ss_ihs %d x 700 walk=%s" % (n, walk))
@@ -240,8 +240,8 @@ def test_ihs_ragged_haplotype_counts(ss, walk, n):
     check_ihs(got, ref, "n=%d" % n)
 
 
-@pytest.mark.parametrize("lpc", [1, 2, 4, 8])
-@pytest.mark.parametrize("n", [65, 204, 300, 510])
+@pytest.mark.parametrize("lpc,n", [(lpc, n) for lpc in (1, 2, 4, 8) for n in (65, 204, 300, 510)]
+                         + [(2, 700), (4, 700), (2, 1000), (4, 1000)])
 def test_ihs_mask_lanes(ss, lpc, n):
     # every lanes-per-class setting of the bitmask walk gives the same answer
     d = hapgen.random_haplotypes(n, 900, 70 + n, n_founders=max(2, n // 10), switch_p=0.006)
@@ -300,9 +300,10 @@ def _many_classes(seed, n1=340, n_same=200):
     return H, pos, pos * 1e-6, core
 
 
-@pytest.mark.parametrize("n1,n_same", [(340, 200), (230, 98)])
+@pytest.mark.parametrize("n1,n_same", [(340, 200), (230, 98), (700, 560)])
 def test_ihs_more_classes_than_a_wave_row(ss, walk, n1, n_same):
-    # 364 haplotypes: 8-word masks, 71 classes; 254: 4-word masks, 67 classes
+    # 364 haplotypes: 8-word masks, 71 classes; 254: 4-word masks, 67 classes;
+    # 724: 16-word masks two lanes a class (32 a row), 71 classes
     H, pos, gpos, core = _many_classes(3, n1, n_same)
     say("ss_ihs many classes n1=%d walk=%s" % (n1, walk))
     h = _hm(ss, H, pos, gpos)
