@@ -246,8 +246,8 @@ int ss_genome_standardize(const ss_std_region *regs, int32_t n_regs, int32_t op,
  *       walk of ss_scan_batch, else class ids),
  *   1 = class ids in LDS (any haplotype count): the plain kernel, one
  *       workgroup per (site, direction), launched over every site,
- *   2 = class bitmasks in registers (iHS up to 1,024 haplotypes, XPEHH up
- *       to 512 pooled; larger inputs use class ids),
+ *   2 = class bitmasks in registers (up to 1,024 haplotypes in the walk,
+ *       pooled for XPEHH; larger inputs use class ids),
  *   3 = the persistent walk of ss_scan_batch with its current configuration
  *       (ss_set_batch_config); inputs it cannot take use class ids.
  * Errors: SS_EARG for any other value.
@@ -305,9 +305,8 @@ typedef struct ss_batch_config {
     int32_t chunk;          /* work items taken per grab of the counter, >= 1            */
     int32_t blocks_per_cu;  /* persistent workgroups per CU; 0 = as many as fit          */
     int32_t order;          /* 0: regions in the order given; 1: most haplotypes first   */
-    int32_t small_kernel;   /* 1: regions the bitmask kernel takes (iHS up to 1,024
-                               haplotypes, XPEHH up to 512 pooled) use it; 0: the
-                               persistent launch takes them too                          */
+    int32_t small_kernel;   /* 1: regions of <= 1,024 haplotypes in the walk use the
+                               bitmask kernel; 0: the persistent launch takes them too  */
     int32_t kernel;         /* 0: class ids per haplotype with a pairwise tail, one item
                                per (site, direction) [default]; 1: per-core walks over
                                sorted member lists, one item per (site, direction, core) */

@@ -789,10 +789,15 @@ hipError_t launch_nr(const WalkArgs &a, int nr, size_t lds, int64_t n_blocks, hi
     const int64_t blocks = n_blocks * (MODE == MODE_CORE ? 4 : 2);
     if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks);
-    // one register row of classes (mask_walk_shape); walks that need more
-    // are listed for the class-id walk
-    if (nr != 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 1>), grid, dim3(64), lds, s, a);
+    // one register row of classes, two for 16-word masks (mask_walk_shape);
+    // walks that need more are walked again by the class-id walk
+    if (nr == 1) {
+        hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 1>), grid, dim3(64), lds, s, a);
+    } else if (nr == 2 && W == 16) {
+        hipLaunchKernelGGL((mask_walk_kernel<MODE, W, LPC, 2>), grid, dim3(64), lds, s, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -829,11 +834,7 @@ MaskShape mask_walk_shape(int32_t nA, int32_t nB, int mode, int lpc) {
     MaskShape sh{};
     const int words = (nA + 63) / 64 + (mode == MODE_POOLED ? (nB + 63) / 64 : 0);
     const int n = nA + (mode == MODE_POOLED ? nB : 0);
-    // 16-word masks for iHS only: pooled walks of 513-1,024 haplotypes took
-    // longer in them than in the persistent class-id walk (0.70 against
-    // 0.56 ms on 500 + 500 x 17,142), iHS walks less (2.53 against 3.33 ms
-    // on 1,000 x 11,655)
-    if (words > (mode == MODE_CORE ? 16 : 8) || n > (mode == MODE_CORE ? 1024 : 512)) return sh;
+    if (words > 16 || n > 1024) return sh;
     sh.words = pow2_at_least(words);   // 1, 2, 4, 8 or 16
     // default: one class per lane (64 classes per row) up to 8 words; 16-word
     // masks take two lanes a class (32 classes per row, 8 words a lane)
@@ -842,11 +843,11 @@ MaskShape mask_walk_shape(int32_t nA, int32_t nB, int mode, int lpc) {
     if (sh.words == 16 && lpc != 2 && lpc != 4) return MaskShape{};
     sh.lpc = lpc;
     const int cpr = 64 / lpc;
-    // Walks keep one row of classes in registers; a walk that would need more
-    // (rare: more than 64 / lpc multi-member classes at once) is walked again
-    // by the class-id walk in the same workgroup, with this LDS.
-    sh.rows = 1;
-    if (sh.rows > 16) return MaskShape{};
+    // Walks keep one row of classes in registers (two for 16-word masks, which
+    // take two lanes a class); a walk that would need more (more than
+    // rows * 64 / lpc multi-member classes at once) is walked again by the
+    // class-id walk in the same workgroup, with this LDS.
+    sh.rows = sh.words == 16 ? 2 : 1;
     sh.pair_cap = mode == MODE_CORE ? mask_pair_cap(sh.words) : 0;
     const size_t stage_words = (size_t)sh.rows * cpr * (sh.words + 1);
     const size_t union_words = stage_words > (size_t)sh.pair_cap / 2 ? stage_words
@@ -878,7 +879,8 @@ hipError_t launch_mask_walk(const WalkArgs &a, int mode, int lpc, int64_t n_bloc
                             : launch_lpc<MODE_POOLED, 4>(a, sh, n_blocks, s);
         case 8: return core ? launch_lpc<MODE_CORE, 8>(a, sh, n_blocks, s)
                             : launch_lpc<MODE_POOLED, 8>(a, sh, n_blocks, s);
-        case 16: return core ? launch_wide<MODE_CORE>(a, sh, n_blocks, s) : hipErrorInvalidValue;
+        case 16: return core ? launch_wide<MODE_CORE>(a, sh, n_blocks, s)
+                             : launch_wide<MODE_POOLED>(a, sh, n_blocks, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -258,11 +258,12 @@ def test_ihs_mask_lanes(ss, lpc, n):
     check_ihs(got, ref, "n=%d lpc=%d" % (n, lpc))
 
 
-@pytest.mark.parametrize("lpc", [1, 2, 4, 8])
-def test_xpehh_mask_lanes(ss, lpc):
-    a = hapgen.random_haplotypes(200, 800, 5, n_founders=15, switch_p=0.004)
-    b = hapgen.random_haplotypes(190, 800, 6, n_founders=12, switch_p=0.004)
-    say("ss_xpehh 200+190 x 800 mask lanes=%d" % lpc)
+@pytest.mark.parametrize("lpc,na,nb", [(lpc, 200, 190) for lpc in (1, 2, 4, 8)] + [(2, 420, 380), (4, 420, 380)])
+def test_xpehh_mask_lanes(ss, lpc, na, nb):
+    # 200 + 190: 8-word pooled masks; 420 + 380: 16-word masks, 2 or 4 lanes a class
+    a = hapgen.random_haplotypes(na, 800, 5, n_founders=15, switch_p=0.004)
+    b = hapgen.random_haplotypes(nb, 800, 6, n_founders=12, switch_p=0.004)
+    say("ss_xpehh %d+%d x 800 mask lanes=%d" % (na, nb, lpc))
     ss.set_walk_kernel(2)
     ss.set_mask_lanes(lpc)
     try:
@@ -315,10 +316,12 @@ def test_ihs_more_classes_than_a_wave_row(ss, walk, n1, n_same):
     assert ref["steps"][core, 0, 1] > 8
 
 
-def test_xpehh_more_classes_than_a_wave_row(ss, walk):
+@pytest.mark.parametrize("n1,n_same", [(340, 200), (700, 560)])
+def test_xpehh_more_classes_than_a_wave_row(ss, walk, n1, n_same):
     # the two halves of the many-classes sample as populations A and B: the
-    # pooled walk holds more than 64 classes at once
-    H, pos, gpos, core = _many_classes(4)
+    # pooled walk holds more than 64 classes at once (8-word masks at 182 +
+    # 182 haplotypes, 16-word masks at 362 + 362)
+    H, pos, gpos, core = _many_classes(4, n1, n_same)
     A = np.ascontiguousarray(H[:, 0::2])
     B = np.ascontiguousarray(H[:, 1::2])
     say("ss_xpehh many classes walk=%s" % walk)
@@ -363,7 +366,8 @@ def test_xpehh_chr22_shaped_config(ss, walk):
     check_xpehh(got, ref, "chr22 xpehh")
 
 
-@pytest.mark.parametrize("na,nb", [(2, 2), (3, 64), (64, 65), (100, 7), (400, 300), (2500, 2500)])
+@pytest.mark.parametrize("na,nb", [(2, 2), (3, 64), (64, 65), (100, 7), (400, 300), (512, 512), (500, 524),
+                                   (2500, 2500)])
 def test_xpehh_ragged_populations(ss, walk, na, nb):
     M = 600 if na + nb < 2000 else 200
     a = hapgen.random_haplotypes(na, M, na, n_founders=max(2, na // 20), switch_p=0.01)
