@@ -14,7 +14,7 @@ one region -- arrive over time.  The server
     and memory free up, and their work overlaps on the GPU;
   * completes each request as soon as its own results are ready: the torch
     backend enqueues a batch as up to two ss_scan_batch calls, the requests
-    walked by the register-bitmask kernel (512 haplotypes or fewer in the
+    walked by the register-bitmask kernel (1,024 haplotypes or fewer in the
     walk) first, each followed by an event, so that small requests do not wait
     for the longest walk of a large one; the batch's memory and stream are
     released when its last event has fired;
@@ -92,12 +92,12 @@ def request_work(kind: str, n_a: int, n_b: int, n_sites: int) -> float:
 
 
 # Haplotypes in a walk up to which the register-bitmask kernel takes a request.
-SMALL_WALK_HAPS = 512
+SMALL_WALK_HAPS = 1024
 
 
 class TorchBackend:
     """Runs batches through ss_scan_batch on a pool of streams.  A batch is
-    enqueued as one ss_scan_batch call for the requests of at most 512
+    enqueued as one ss_scan_batch call for the requests of at most 1,024
     haplotypes in the walk (the bitmask kernel, one launch per scan), then one
     for the others (one persistent launch), each followed by an event; the
     requests of a call are complete when its event has fired."""
