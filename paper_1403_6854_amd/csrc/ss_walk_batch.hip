@@ -87,6 +87,20 @@ __device__ __forceinline__ uint64_t key_of(const uint64_t *hb, int64_t mwp, int 
     return dir > 0 ? x : __builtin_bitreverse64(x);
 }
 
+// Largest S in [0, P] with (double)S / (double)P < cutoff (P >= 1, cutoff >
+// 0), found by testing 64 consecutive candidates around cutoff * P, one per
+// lane: fl(S / P) is monotone in S, so a core's stop test is then the
+// integer test S <= threshold.
+__device__ __forceinline__ uint32_t stop_threshold(uint32_t P, double cutoff, int lane) {
+    const double Pd = (double)P;
+    int64_t s = (int64_t)(cutoff * Pd) - 32 + lane;
+    if (s < 0) s = 0;
+    if (s > (int64_t)P) s = (int64_t)P;
+    const uint64_t m = __ballot((double)s / Pd < cutoff);
+    const int top = 63 - __builtin_clzll(m);   // m != 0: candidate 0 is always below
+    return (uint32_t)__builtin_amdgcn_readlane((uint32_t)s, top);
+}
+
 // Exclusive workgroup sum (u64); wtot holds one total per wave.
 __device__ __forceinline__ uint64_t block_excl_sum(uint64_t v, uint64_t *wtot, uint64_t &total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -223,7 +237,12 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
     const uint32_t i0 = init[0], i1 = init[1];
 
     bool act0, act1;
-    double ihh0 = 0.0, ihh1 = 0.0, ep0, ep1, P0, P1, PP = 1.0;
+    // The EHH values and iHH sums are wave 0's (it writes the results); every
+    // wave takes the same stop decisions from exact integer thresholds:
+    // a core stops at the first marker with S <= thr (iHS: per core; XPEHH:
+    // the pooled S against thr0).
+    double ihh0 = 0.0, ihh1 = 0.0, ep0, ep1, P0, P1;
+    uint32_t thr0 = 0u, thr1 = 0u;
     int32_t steps0 = 0, steps1 = 0;
     uint32_t sa0, sa1, sa2 = 0;   // S after the last marker (iHS: cores 0, 1; XPEHH: A, B, pooled)
     if (MODE == MODE_CORE) {
@@ -232,6 +251,8 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
         P1 = (double)choose2(n1);
         act0 = n0 >= 2u;
         act1 = n1 >= 2u;
+        if (act0) thr0 = stop_threshold(choose2(n0), G.cutoff, lane);
+        if (act1) thr1 = stop_threshold(choose2(n1), G.cutoff, lane);
         ep0 = 1.0;
         ep1 = 1.0;
         sa0 = choose2(n0);
@@ -249,13 +270,13 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
         const uint32_t a0 = i0 & 0xFFFFu, b0 = i0 >> 16, a1 = i1 & 0xFFFFu, b1 = i1 >> 16;
         P0 = (double)choose2((uint32_t)nA);
         P1 = (double)choose2((uint32_t)nB);
-        PP = (double)choose2((uint32_t)(nA + nB));
         // x0 is part of the haplotype: each population's curve starts at its
         // whole-sample EHH at x0
         ep0 = (double)(choose2(a0) + choose2(a1)) / P0;
         ep1 = (double)(choose2(b0) + choose2(b1)) / P1;
         act0 = true;
         act1 = false;
+        thr0 = stop_threshold(choose2((uint32_t)(nA + nB)), G.cutoff, lane);
         sa0 = choose2(a0) + choose2(a1);
         sa1 = choose2(b0) + choose2(b1);
         sa2 = choose2(a0 + b0) + choose2(a1 + b1);
@@ -303,7 +324,6 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
                 status = abort_st;
                 goto done;
             }
-            const double g = readlane_f64(gl, i);
             const int par = step & 1;
             uint32_t *szc = par ? szv1 : szv0;
             uint32_t *szn = par ? szv0 : szv1;
@@ -427,21 +447,21 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
             if (MODE == MODE_CORE) {
                 if (act0) {
                     steps0 += 1;
-                    const double e = (double)S0 / P0;
-                    if (e < G.cutoff) {
+                    if (S0 <= thr0) {
                         act0 = false;
-                    } else {
-                        ihh0 += 0.5 * (ep0 + e) * g;
+                    } else if (wave == 0) {
+                        const double e = (double)S0 / P0;
+                        ihh0 += 0.5 * (ep0 + e) * readlane_f64(gl, i);
                         ep0 = e;
                     }
                 }
                 if (act1) {
                     steps1 += 1;
-                    const double e = (double)S1 / P1;
-                    if (e < G.cutoff) {
+                    if (S1 <= thr1) {
                         act1 = false;
-                    } else {
-                        ihh1 += 0.5 * (ep1 + e) * g;
+                    } else if (wave == 0) {
+                        const double e = (double)S1 / P1;
+                        ihh1 += 0.5 * (ep1 + e) * readlane_f64(gl, i);
                         ep1 = e;
                     }
                 }
@@ -449,9 +469,10 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
                 sa1 = S1;
             } else {
                 steps0 += 1;
-                if ((double)S2 / PP < G.cutoff) {
+                if (S2 <= thr0) {
                     act0 = false;
-                } else {
+                } else if (wave == 0) {
+                    const double g = readlane_f64(gl, i);
                     const double eA = (double)S0 / P0;
                     const double eB = (double)S1 / P1;
                     ihh0 += 0.5 * (ep0 + eA) * g;
@@ -618,7 +639,7 @@ pairs : {
             const uint32_t si0 = sa0 - wave_prefix(hist[lane], lane);
             const uint32_t si1 = sa1 - wave_prefix(hist[64 + lane], lane);
             if (act0) {
-                const uint64_t sm = __ballot((double)si0 / P0 < G.cutoff) & valid;
+                const uint64_t sm = __ballot(si0 <= thr0) & valid;
                 const int nterm = sm ? (int)__builtin_ctzll(sm) : lim;
                 steps0 += sm ? nterm + 1 : lim;
                 if (nterm > 0) {
@@ -632,7 +653,7 @@ pairs : {
                 if (sm) act0 = false;
             }
             if (act1) {
-                const uint64_t sm = __ballot((double)si1 / P1 < G.cutoff) & valid;
+                const uint64_t sm = __ballot(si1 <= thr1) & valid;
                 const int nterm = sm ? (int)__builtin_ctzll(sm) : lim;
                 steps1 += sm ? nterm + 1 : lim;
                 if (nterm > 0) {
@@ -651,7 +672,7 @@ pairs : {
             const uint32_t siP = sa2 - wave_prefix(hist[lane], lane);
             const uint32_t siA = sa0 - wave_prefix(hist[64 + lane], lane);
             const uint32_t siB = sa1 - wave_prefix(hist[128 + lane], lane);
-            const uint64_t sm = __ballot((double)siP / PP < G.cutoff) & valid;
+            const uint64_t sm = __ballot(siP <= thr0) & valid;
             const int nterm = sm ? (int)__builtin_ctzll(sm) : lim;
             steps0 += sm ? nterm + 1 : lim;
             if (nterm > 0) {
