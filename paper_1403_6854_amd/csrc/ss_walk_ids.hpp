@@ -67,6 +67,21 @@ __device__ __forceinline__ double readlane_f64(double v, int i) {
     return __builtin_bit_cast(double, readlane64(__builtin_bit_cast(uint64_t, v), i));
 }
 
+// Largest S in [0, P] with (double)S / (double)P < cutoff (P >= 1, cutoff >
+// 0), found by testing 64 consecutive candidates around cutoff * P, one per
+// lane: fl(S / P) is monotone in S, so a stop test is then S <= threshold.
+__device__ __forceinline__ uint32_t stop_threshold(uint32_t P, double cutoff, int lane) {
+    const double Pd = (double)P;
+    int64_t c0 = (int64_t)(cutoff * Pd) - 32;
+    int64_t s = c0 + lane;
+    if (s < 0) s = 0;
+    if (s > (int64_t)P) s = (int64_t)P;
+    const bool below = (double)s / Pd < cutoff;
+    const uint64_t m = __ballot(below);
+    const int top = 63 - __builtin_clzll(m);   // m != 0: candidate 0 or c0 is always below
+    return (uint32_t)__builtin_amdgcn_readlane((uint32_t)s, top);
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -149,8 +164,13 @@ __device__ void walk_one(const WalkArgs &a, int64_t j, int d) {
     const uint32_t i0 = init[0], i1 = init[1];
 
     // Per-walk scalar state (identical in every thread).
+    // Every wave takes the stop decisions from exact integer thresholds (a core
+    // stops at the first marker with S <= thr; XPEHH: the pooled S against
+    // thr0); the EHH values and iHH sums are wave 0's, whose thread 0 writes
+    // the results.
     bool act0, act1;
-    double ihh0 = 0.0, ihh1 = 0.0, ep0, ep1, P0, P1, PP = 0.0;
+    double ihh0 = 0.0, ihh1 = 0.0, ep0, ep1, P0, P1;
+    uint32_t thr0 = 0u, thr1 = 0u;
     int32_t steps0 = 0, steps1 = 0;
     if (MODE == MODE_CORE) {
         const uint32_t n0 = i0 & 0xFFFFu, n1 = i1 & 0xFFFFu;
@@ -158,6 +178,8 @@ __device__ void walk_one(const WalkArgs &a, int64_t j, int d) {
         P1 = (double)choose2(n1);
         act0 = n0 >= 2u;
         act1 = n1 >= 2u;
+        if (act0) thr0 = stop_threshold(choose2(n0), a.cutoff, lane);
+        if (act1) thr1 = stop_threshold(choose2(n1), a.cutoff, lane);
         ep0 = 1.0;
         ep1 = 1.0;
         if (tid == 0) {
@@ -184,7 +206,7 @@ __device__ void walk_one(const WalkArgs &a, int64_t j, int d) {
         const uint32_t a0 = i0 & 0xFFFFu, b0 = i0 >> 16, a1 = i1 & 0xFFFFu, b1 = i1 >> 16;
         P0 = (double)choose2((uint32_t)a.nA);   // population A
         P1 = (double)choose2((uint32_t)a.nB);   // population B
-        PP = (double)choose2((uint32_t)(a.nA + a.nB));
+        thr0 = stop_threshold(choose2((uint32_t)(a.nA + a.nB)), a.cutoff, lane);
         // x0 is part of the haplotype: each population's curve starts at its
         // whole-sample EHH at x0
         ep0 = (double)(choose2(a0) + choose2(a1)) / P0;
@@ -239,7 +261,6 @@ __device__ void walk_one(const WalkArgs &a, int64_t j, int d) {
         for (int i = 0; i < 64 && (act0 || act1); ++i) {
             if (i == nb) { status = abort_st; goto done; }
             if (TRACE && step >= a.cap) { status = ST_CAP; goto done; }
-            const double g = readlane_f64(gl, i);
 
             const int par = step & 1;
             uint32_t *szc = par ? szv1 : szv0;
@@ -360,29 +381,30 @@ __device__ void walk_one(const WalkArgs &a, int64_t j, int d) {
                 }
                 if (act0) {
                     steps0 += 1;
-                    const double e = (double)S0 / P0;
-                    if (e < a.cutoff) {
+                    if (S0 <= thr0) {
                         act0 = false;
-                    } else {
-                        ihh0 += 0.5 * (ep0 + e) * g;
+                    } else if (wave == 0) {
+                        const double e = (double)S0 / P0;
+                        ihh0 += 0.5 * (ep0 + e) * readlane_f64(gl, i);
                         ep0 = e;
                     }
                 }
                 if (act1) {
                     steps1 += 1;
-                    const double e = (double)S1 / P1;
-                    if (e < a.cutoff) {
+                    if (S1 <= thr1) {
                         act1 = false;
-                    } else {
-                        ihh1 += 0.5 * (ep1 + e) * g;
+                    } else if (wave == 0) {
+                        const double e = (double)S1 / P1;
+                        ihh1 += 0.5 * (ep1 + e) * readlane_f64(gl, i);
                         ep1 = e;
                     }
                 }
             } else {
                 steps0 += 1;
-                if ((double)S2 / PP < a.cutoff) {
+                if (S2 <= thr0) {
                     act0 = false;
-                } else {
+                } else if (wave == 0) {
+                    const double g = readlane_f64(gl, i);
                     const double eA = (double)S0 / P0;
                     const double eB = (double)S1 / P1;
                     ihh0 += 0.5 * (ep0 + eA) * g;

@@ -37,7 +37,7 @@
 //     gives S at each of the 64 markers, and the surviving pairs are compacted
 //     in place.  Long walks then cost a few instructions per pair per 64
 //     markers instead of a full refinement per marker.
-#include "ss_walk_ids.hpp"   // walk_one, choose2, wave_sum, readlane64, readlane_f64
+#include "ss_walk_ids.hpp"   // walk_one, choose2, wave_sum, readlane64, readlane_f64, stop_threshold
 
 namespace ss {
 
@@ -126,20 +126,6 @@ __device__ __forceinline__ void add_terms(double (&acc)[NS], const double (&term
                 acc[s] += v[s][k].y;
             }
     }
-}
-
-// Largest S in [0, P] with (double)S / (double)P < cutoff (P >= 1), found by
-// testing 64 consecutive candidates around cutoff * P, one per lane.
-__device__ __forceinline__ uint32_t stop_threshold(uint32_t P, double cutoff, int lane) {
-    const double Pd = (double)P;
-    int64_t c0 = (int64_t)(cutoff * Pd) - 32;
-    int64_t s = c0 + lane;
-    if (s < 0) s = 0;
-    if (s > (int64_t)P) s = (int64_t)P;
-    const bool below = (double)s / Pd < cutoff;
-    const uint64_t m = __ballot(below);
-    const int top = 63 - __builtin_clzll(m);   // m != 0: candidate 0 or c0 is always below
-    return (uint32_t)__builtin_amdgcn_readlane((uint32_t)s, top);
 }
 
 // Waves per SIMD the compiler is held to, the most that fit without spills:
