@@ -421,29 +421,46 @@ __global__ void __launch_bounds__(kFusedBlock) bin_fused_kernel(int64_t M,
         return threadIdx.x + (uint32_t)((i / kFusedUnroll) * kFusedRound + (i % kFusedUnroll) * kFusedBlock);
     };
     // OK scores of bin b among the round's sites of this thread (site order)
+    // (Sites past the end read site 0 and are then ignored: loads under a
+    // per-lane condition were each waited for before the next was issued.)
     auto load = [&](int64_t j0, bool (&in)[kFusedUnroll], double (&uu)[kFusedUnroll]) {
+        int32_t bj[kFusedUnroll];
+        int32_t st[kFusedUnroll];
 #pragma unroll
         for (int q = 0; q < kFusedUnroll; ++q) {
             const int64_t j = j0 + (int64_t)q * kFusedBlock;
-            const bool inr = j < M;
-            const int32_t bj = inr ? (bin ? bin[j] : 0) : -1;
-            const int8_t st = inr ? status[j] : (int8_t)ST_MAF;
-            uu[q] = inr ? u[j] : 0.0;
-            in[q] = bj == b && st == ST_OK;
+            const int64_t jc = j < M ? j : 0;
+            bj[q] = bin ? bin[jc] : 0;
+            st[q] = status[jc];
+            uu[q] = u[jc];
+        }
+#pragma unroll
+        for (int q = 0; q < kFusedUnroll; ++q) {
+            const bool inr = j0 + (int64_t)q * kFusedBlock < M;
+            in[q] = inr && bj[q] == b && st[q] == ST_OK;
+            if (!inr) uu[q] = 0.0;
         }
     };
     double c = 0.0, sum = 0.0;
     if (R > 0) {
         // bins and statuses of the held sites first, then the scores of the
         // bin's OK sites only: two loads in flight per site at a time
+        // every load issued without a condition (a lane past the end reads
+        // site 0 and ignores it), so that all are in flight together: loads
+        // under a per-lane condition were each waited for before the next
+        int32_t bjv[kHeld], stv[kHeld];
 #pragma unroll
         for (int i = 0; i < kHeld; ++i) {
             const uint32_t j = held_site(i), j0 = j - threadIdx.x;
-            const bool inr = j < (uint32_t)M;
-            const int32_t bj = inr ? (bin ? (bin + j0)[threadIdx.x] : 0) : -1;
-            const int8_t st = inr ? (status + j0)[threadIdx.x] : (int8_t)ST_MAF;
-            if (bj == b) inbin |= 1u << i;
-            if (bj == b && st == ST_OK) okbin |= 1u << i;
+            const int32_t off = j < (uint32_t)M ? (int32_t)threadIdx.x : -(int32_t)j0;
+            bjv[i] = bin ? (bin + j0)[off] : 0;
+            stv[i] = (status + j0)[off];
+        }
+#pragma unroll
+        for (int i = 0; i < kHeld; ++i) {
+            const bool inr = held_site(i) < (uint32_t)M;
+            if (inr && bjv[i] == b) inbin |= 1u << i;
+            if (inr && bjv[i] == b && stv[i] == ST_OK) okbin |= 1u << i;
         }
 #pragma unroll
         for (int i = 0; i < kHeld; ++i) {
