@@ -264,15 +264,38 @@ __global__ void __launch_bounds__(kBlock) combine_kernel(
 // definition (mean first, then squared deviations from it).  Sites are cut
 // into tiles of kTile, one per workgroup; each thread holds kTile / kBlock
 // sites, and for every bin the workgroup sums them with fixed-order wave
-// butterflies; the per-tile partial sums are then added in tile order.  The
+// reductions; the per-tile partial sums are then added in tile order.  The
 // summation order is fixed, so results are identical from run to run.
 constexpr int kTile = 1024;
 
-// Butterfly sum over the 64 lanes of a wave (fixed order: deterministic).
+// Lane value moved by a DPP row operation, the two halves of the double one
+// after the other (lanes the operation does not write, or that read from
+// outside their row with bound_ctrl, get +0.0).
+template <int CTRL, int ROW_MASK, bool BC>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t x = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROW_MASK, 0xF, BC);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROW_MASK,
+                                                              0xF, BC);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wave, in every lane: an inclusive scan in DPP
+// register moves (within each row of 16 lanes by shifts of 1, 2, 4 and 8,
+// then row 0's total into row 1 and row 2's into row 3, then rows 0-1 into
+// rows 2-3), whose last lane holds the total.  The butterfly of lane
+// permutes it replaces went through LDS at every step.
 __device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_f64<0x111, 0xF, true>(v);    // row_shr:1
+    v += dpp_f64<0x112, 0xF, true>(v);    // row_shr:2
+    v += dpp_f64<0x114, 0xF, true>(v);    // row_shr:4
+    v += dpp_f64<0x118, 0xF, true>(v);    // row_shr:8
+    v += dpp_f64<0x142, 0xA, false>(v);   // row_bcast:15
+    v += dpp_f64<0x143, 0xC, false>(v);   // row_bcast:31
+    const uint64_t x = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), 63);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 __global__ void __launch_bounds__(kBlock) bin_partial_kernel(
