@@ -31,16 +31,24 @@ __global__ void __launch_bounds__(kBlock) pack_kernel(const uint8_t *__restrict_
     for (int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * kPackItems;
          base < total; base += stride) {
         int64_t site = base / wps, w = base - site * wps;
-        bool one[kPackItems];
+        // every load issued without a condition (a lane past a row's end
+        // reads byte 0 and ignores it), so that all are in flight together:
+        // loads under a per-lane condition were each waited for before the next
+        uint32_t v[kPackItems];
+        bool ok[kPackItems];
 #pragma unroll
         for (int q = 0; q < kPackItems; ++q) {
             const int64_t h = w * 64 + lane;
-            one[q] = base + q < total && h < n && alleles[site * n + h] != 0;
+            ok[q] = base + q < total && h < n;
+            v[q] = alleles[ok[q] ? site * n + h : 0];
             if (++w == wps) {
                 w = 0;
                 ++site;
             }
         }
+        bool one[kPackItems];
+#pragma unroll
+        for (int q = 0; q < kPackItems; ++q) one[q] = ok[q] && v[q] != 0u;
         uint64_t mine = 0;
 #pragma unroll
         for (int q = 0; q < kPackItems; ++q) {
