@@ -108,10 +108,12 @@ __device__ void segment_part(int64_t blk, int64_t M, const int64_t *__restrict__
         seg[0] = -1.0;
         return;
     }
+    // positions and map read together (the map's reads do not wait on the gap test)
     const int64_t b = pos[k] - pos[k - 1];
+    const double dg = gpos[k] - gpos[k - 1];
     double g = -1.0;
     if (b <= max_gap) {
-        g = physical ? (double)b : gpos[k] - gpos[k - 1];
+        g = physical ? (double)b : dg;
         if (b > gap_scale) g = g * ((double)gap_scale / (double)b);
     }
     seg[k] = g;
@@ -315,13 +317,24 @@ __global__ void __launch_bounds__(kBlock) bin_partial_kernel(
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t t0 = (int64_t)blockIdx.x * kTile;
     double uv[kPer];
-    int32_t bv[kPer];
+    int32_t bv[kPer], sv[kPer];
+    // all loads issued at once, without per-lane conditions (a lane past the
+    // end reads site 0 and ignores it)
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         const int64_t jj = t0 + threadIdx.x + (int64_t)q * kBlock;
-        const bool ok = jj < M && status[jj] == ST_OK;
-        bv[q] = ok ? (bin ? bin[jj] : 0) : -1;
-        uv[q] = ok ? u[jj] : 0.0;
+        const int64_t jc = jj < M ? jj : 0;
+        sv[q] = status[jc];
+        bv[q] = bin ? bin[jc] : 0;
+        uv[q] = u[jc];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const bool ok = t0 + threadIdx.x + (int64_t)q * kBlock < M && sv[q] == ST_OK;
+        if (!ok) {
+            bv[q] = -1;
+            uv[q] = 0.0;
+        }
     }
     for (int b = 0; b < nbins; ++b) {
         // second pass: squared deviations from the bin's mean
@@ -387,11 +400,14 @@ __global__ void __launch_bounds__(kBlock) standardize_kernel(int64_t M,
                                                              double *__restrict__ z) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= M) return;
+    // the site's status, bin and score read together, not one after another
+    const int8_t st = status[j];
+    const int b = bin ? bin[j] : 0;
+    const double uj = u[j];
     double out = __builtin_nan("");
-    if (status[j] == ST_OK) {
-        const int b = bin ? bin[j] : 0;
+    if (st == ST_OK) {
         const double N = binstat[3 * b + 0], mean = binstat[3 * b + 1], sd = binstat[3 * b + 2];
-        if (N >= 2.0 && sd > 0.0) out = (u[j] - mean) / sd;
+        if (N >= 2.0 && sd > 0.0) out = (uj - mean) / sd;
         else status[j] = ST_BIN;
     }
     z[j] = out;
