@@ -44,7 +44,9 @@ PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 int32 lanes/clk x 2.4
 PROXY_OPS_PER_CELL = 51.0 / 256.0           # int32 lane-ops per haplotype-cell of the refinement
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_traffic.json")
-WALK_SRC = os.path.join(ROOT, "paper_1403_6854_amd", "csrc", "ss_walk_mask.hip")
+# the walk kernel's sources: the mask walk and the class-id walk it falls back on
+WALK_SRC = [os.path.join(ROOT, "paper_1403_6854_amd", "csrc", f)
+            for f in ("ss_walk_mask.hip", "ss_walk_ids.hpp", "ss_internal.hpp")]
 
 
 def log(msg):
@@ -52,7 +54,10 @@ def log(msg):
 
 
 def walk_src_sha() -> str:
-    return hashlib.sha256(open(WALK_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in WALK_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str):
@@ -538,7 +543,7 @@ def main():
                   "unit": "core loci/s", "ms_per_step": round(elx / args.steps * 1e3, 5),
                   "walk_kernel_ms": round(walk_ms_x, 5), "work_cells": Wx,
                   "achieved_TOPs": round(Wx / (walk_ms_x * 1e-3) / 1e12, 4)},
-        "scaling": scaling,
+        "scaling_sweep": scaling,
         "batched": batched,
         "served": served,
         "context": {"paper_cpu_loci_per_s": {"ihs_ceu22_1thread": 62.7, "ihs_ceu22_16threads": 671,

@@ -108,14 +108,13 @@ __device__ void segment_part(int64_t blk, int64_t M, const int64_t *__restrict__
         seg[0] = -1.0;
         return;
     }
-    // positions and map read together (the map's reads do not wait on the gap test)
+    // positions and map read together: the map is used whatever the gap
+    // test says, so its reads do not wait for it
     const int64_t b = pos[k] - pos[k - 1];
     const double dg = gpos[k] - gpos[k - 1];
-    double g = -1.0;
-    if (b <= max_gap) {
-        g = physical ? (double)b : dg;
-        if (b > gap_scale) g = g * ((double)gap_scale / (double)b);
-    }
+    double g = physical ? (double)b : dg;
+    if (b > gap_scale) g = g * ((double)gap_scale / (double)b);
+    if (b > max_gap) g = -1.0;
     seg[k] = g;
 }
 
@@ -217,6 +216,9 @@ __global__ void __launch_bounds__(kBlock) combine_kernel(
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= M) return;
     const double nan = __builtin_nan("");
+    // the records are read before the flag, not after it (a site that was not
+    // walked reads its slots and ignores them)
+    const WalkRec r0 = rec[4 * j + 0], r1 = rec[4 * j + 1], r2 = rec[4 * j + 2], r3 = rec[4 * j + 3];
     const bool walked = walk_flag == nullptr || walk_flag[j] != 0;
     if (!walked) {
         out_a[j] = nan;
@@ -230,7 +232,6 @@ __global__ void __launch_bounds__(kBlock) combine_kernel(
     }
     // a direction aborts if the walk of either core aborted (iHS walks may be
     // split by core; joint walks write the same status to both slots)
-    const WalkRec r0 = rec[4 * j + 0], r1 = rec[4 * j + 1], r2 = rec[4 * j + 2], r3 = rec[4 * j + 3];
     const int32_t sd = r0.status != ST_OK ? r0.status : r1.status;
     const int32_t su = r2.status != ST_OK ? r2.status : r3.status;
     int32_t st = sd != ST_OK ? sd : su;
@@ -400,10 +401,10 @@ __global__ void __launch_bounds__(kBlock) standardize_kernel(int64_t M,
                                                              double *__restrict__ z) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= M) return;
-    // the site's status, bin and score read together, not one after another
+    // the site's score, status and bin read together, not one after another
+    const double uj = u[j];
     const int8_t st = status[j];
     const int b = bin ? bin[j] : 0;
-    const double uj = u[j];
     double out = __builtin_nan("");
     if (st == ST_OK) {
         const double N = binstat[3 * b + 0], mean = binstat[3 * b + 1], sd = binstat[3 * b + 2];
