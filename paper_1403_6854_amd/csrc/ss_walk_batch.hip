@@ -20,6 +20,16 @@
 //     XOR of the pair's 64-marker keys from the haplotype-major copy, lowest
 //     set bit = the marker where the pair splits, per-type 64-bin histograms
 //     give S at each marker of the pass;
+//   * reference passes (iHS walks past their first 64 markers, at most 256
+//     classes): a whole 64-marker batch at once when few members differ from
+//     their class's lowest member within it.  A member's first difference
+//     from the reference, and for members that leave at the same marker the
+//     first difference of their keys, give every pair that splits in the
+//     batch (Eq. 3 needs only the number of pairs still identical at each
+//     marker), and the classes after the batch are the stayers plus the
+//     leavers grouped by key.  Long walks through a sweep, a few large
+//     classes of near-identical haplotypes, take most of their markers this
+//     way;
 //   * the grid is persistent: each workgroup takes the next `chunk` items from
 //     a global counter until the batch is done, so walks of very different
 //     lengths and regions of different sizes balance across the GPU.
@@ -127,9 +137,21 @@ __device__ __forceinline__ uint64_t block_excl_sum(uint64_t v, uint64_t *wtot, u
 // built; keys, the second pair buffer and the histograms then reuse it.
 struct BLay {
     uint32_t cnt1, szv0, szv1, map, sacc, knext, init, ovf, wtot, mem, pairs0;
-    uint32_t keys, pairs1, hist, pcnt, total;
+    uint32_t keys, pairs1, hist, pcnt;
+    uint32_t dref, dkey, dcnt, doff, ekey, einfo, elead, egid, dhist, dctl;   // reference pass
+    uint32_t total;
     int kmax, copies;
 };
+
+// Reference pass: a walk that has gone kDevMinStep markers with at most
+// kDevClasses classes tries each 64-marker batch in one step; the batch is
+// refined marker by marker instead when more than kDevCap members leave
+// their class's reference, or when the pairs among the leavers of a class
+// (sum of squares of the leaver counts) exceed kDevWork.
+constexpr int kDevClasses = 256;
+constexpr int kDevCap = 512;
+constexpr uint32_t kDevWork = 1u << 16;
+constexpr int kDevMinStep = 64;
 
 __host__ __device__ inline uint32_t al16(uint32_t x) { return (x + 15u) & ~15u; }
 
@@ -163,12 +185,22 @@ __host__ __device__ inline BLay batch_layout(int lmax, int kcls, int pcap, int k
     l.wtot = o;   o = al16(o + 8u * 16u);
     l.mem = o;    o = al16(o + 2u * (uint32_t)kcap);
     l.pairs0 = o; o = al16(o + 4u * (uint32_t)pcap);
+    l.dref = o;   o = al16(o + 4u * kDevClasses);
+    l.dkey = o;   o = al16(o + 8u * kDevClasses);
+    l.dcnt = o;   o = al16(o + 4u * kDevClasses);
+    l.doff = o;   o = al16(o + 4u * kDevClasses);
+    l.ekey = o;   o = al16(o + 8u * kDevCap);
+    l.einfo = o;  o = al16(o + 4u * kDevCap);
+    l.elead = o;  o = al16(o + 4u * kDevCap);
+    l.egid = o;   o = al16(o + 4u * kDevCap);
+    l.dhist = o;  o = al16(o + 4u * 3u * 64u);
+    l.dctl = o;   o = al16(o + 16u);
     l.total = o;
     return l;
 }
 
 template <int MODE, int R>
-__device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *base,
+__device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *base,
                          const BLay &Ly, int pcap, int kcap, int64_t item, int64_t *redo,
                          int32_t *redo_count) {
     // fields are read through the pointer where they are used (scalar loads),
@@ -210,7 +242,12 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
         return wq < WA ? G.bitsA[k * G.wpsA + wq] : G.bitsB[k * G.wpsB + (wq - WA)];
     };
     auto word = [&](int r) -> bool { return wave + r * wpg < Wused; };
-    auto incu = [&](int r) -> uint32_t { return wave + r * wpg < WA ? 1u : 0x10000u; };
+    // count increment of slot r's members: 1 in population A, 1 << 16 in B
+    // (wave-uniform; iHS has A only)
+    auto incu = [&](int r) -> uint32_t {
+        return MODE == MODE_CORE ? 1u
+                                 : (uint32_t)__builtin_amdgcn_readfirstlane(wave + r * wpg < WA ? 1u : 0x10000u);
+    };
     int32_t cls[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -298,7 +335,351 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
     int32_t status = ST_OK;
     int step = 0;
     bool pmode = false;
+    // the two class-size arrays take turns by marker parity; a reference
+    // pass (64 markers, an even count) swaps them once more
+    int pflip = 0;
+    // (iHS walks: the pooled walks of XPEHH end within a few markers of their
+    // first splits, and the pass's code would cost their per-marker loop
+    // registers)
+    const bool can_dev = MODE == MODE_CORE && G.hbitsA != nullptr;
+
+    // End of a 64-marker pass: hist[t][L] counts the class-mate pairs of type
+    // t (iHS: core 0, core 1; XPEHH: pooled, A-A, B-B) whose alleles first
+    // differ at marker L of the pass, so S after marker L is the S before the
+    // pass less the prefix sum; then each walking core's stop test, steps
+    // and trapezoid terms (added in marker order).  Markers from nb on are
+    // past an abort and are not walked.
+    auto settle = [&](const uint32_t *hist, int nb, double gl) {
+        const uint64_t valid = low_bits(nb);
+        const int lim = nb < 64 ? nb : 64;
+        if (MODE == MODE_CORE) {
+            // each core stops at its own first sub-cutoff marker of the pass
+            const uint32_t si0 = sa0 - wave_prefix(hist[lane], lane);
+            const uint32_t si1 = sa1 - wave_prefix(hist[64 + lane], lane);
+            if (act0) {
+                const uint64_t sm = __ballot(si0 <= thr0) & valid;
+                const int nterm = sm ? (int)__builtin_ctzll(sm) : lim;
+                steps0 += sm ? nterm + 1 : lim;
+                if (nterm > 0) {
+                    const double e = (double)si0 / P0;
+                    double prev = __shfl_up(e, 1, 64);
+                    if (lane == 0) prev = ep0;
+                    const double term = 0.5 * (prev + e) * gl;
+                    for (int t = 0; t < nterm; ++t) ihh0 += readlane_f64(term, t);
+                    ep0 = readlane_f64(e, nterm - 1);
+                }
+                if (sm) act0 = false;
+            }
+            if (act1) {
+                const uint64_t sm = __ballot(si1 <= thr1) & valid;
+                const int nterm = sm ? (int)__builtin_ctzll(sm) : lim;
+                steps1 += sm ? nterm + 1 : lim;
+                if (nterm > 0) {
+                    const double e = (double)si1 / P1;
+                    double prev = __shfl_up(e, 1, 64);
+                    if (lane == 0) prev = ep1;
+                    const double term = 0.5 * (prev + e) * gl;
+                    for (int t = 0; t < nterm; ++t) ihh1 += readlane_f64(term, t);
+                    ep1 = readlane_f64(e, nterm - 1);
+                }
+                if (sm) act1 = false;
+            }
+            sa0 = (uint32_t)__builtin_amdgcn_readlane(si0, 63);
+            sa1 = (uint32_t)__builtin_amdgcn_readlane(si1, 63);
+        } else {
+            const uint32_t siP = sa2 - wave_prefix(hist[lane], lane);
+            const uint32_t siA = sa0 - wave_prefix(hist[64 + lane], lane);
+            const uint32_t siB = sa1 - wave_prefix(hist[128 + lane], lane);
+            const uint64_t sm = __ballot(siP <= thr0) & valid;
+            const int nterm = sm ? (int)__builtin_ctzll(sm) : lim;
+            steps0 += sm ? nterm + 1 : lim;
+            if (nterm > 0) {
+                const double eA = (double)siA / P0;
+                const double eB = (double)siB / P1;
+                double pA = __shfl_up(eA, 1, 64);
+                double pBv = __shfl_up(eB, 1, 64);
+                if (lane == 0) {
+                    pA = ep0;
+                    pBv = ep1;
+                }
+                const double tA = 0.5 * (pA + eA) * gl;
+                const double tB = 0.5 * (pBv + eB) * gl;
+                for (int t = 0; t < nterm; ++t) {
+                    ihh0 += readlane_f64(tA, t);
+                    ihh1 += readlane_f64(tB, t);
+                }
+                ep0 = readlane_f64(eA, nterm - 1);
+                ep1 = readlane_f64(eB, nterm - 1);
+            }
+            if (sm) act0 = false;
+            sa2 = (uint32_t)__builtin_amdgcn_readlane(siP, 63);
+            sa0 = (uint32_t)__builtin_amdgcn_readlane(siA, 63);
+            sa1 = (uint32_t)__builtin_amdgcn_readlane(siB, 63);
+        }
+    };
+
     while (act0 || act1) {
+        if (can_dev && step >= kDevMinStep && K <= kDevClasses) {
+            // ---- reference pass over the next 64 markers ---------------------
+            // Each class's lowest member is its reference; a member "leaves" at
+            // the first marker where its 64-marker key differs from the
+            // reference's.  Two class-mates that leave at different markers
+            // (or one that never leaves) first differ where the earlier one
+            // leaves; two that leave at the same marker agree there and first
+            // differ where their keys do.  So every pair that splits in the
+            // pass is counted from the leavers alone, and the classes after
+            // the pass are each class's stayers plus its leavers grouped by
+            // key.
+            const int par = (step & 1) ^ pflip;
+            uint32_t *szc = par ? szv1 : szv0;
+            uint32_t *szn = par ? szv0 : szv1;
+            uint32_t *dref = (uint32_t *)(base + Ly.dref);   // [class] lowest member
+            uint64_t *dkey = (uint64_t *)(base + Ly.dkey);   // [class] its key
+            uint32_t *dcnt = (uint32_t *)(base + Ly.dcnt);   // [class] leavers, A | B << 16
+            uint32_t *doff = (uint32_t *)(base + Ly.doff);   // [class] first entry of its leavers
+            uint64_t *ekey = (uint64_t *)(base + Ly.ekey);   // [leaver] key
+            uint32_t *einfo = (uint32_t *)(base + Ly.einfo); // [leaver] class | marker << 16 | B << 23
+            int32_t *elead = (int32_t *)(base + Ly.elead);   // [leaver] first leaver with its key
+            int32_t *egid = (int32_t *)(base + Ly.egid);     // [leaver] group size, then new class
+            uint32_t *dhist = (uint32_t *)(base + Ly.dhist); // [3][64] pairs splitting per marker
+            uint32_t *dctl = (uint32_t *)(base + Ly.dctl);   // leavers, their pair work, classes, members
+            uint64_t *wtot = (uint64_t *)(base + Ly.wtot);
+            for (int c = tid; c < K; c += T) {
+                dref[c] = 0xFFFFFFFFu;
+                dcnt[c] = 0u;
+            }
+            for (int x = tid; x < 3 * 64; x += T) dhist[x] = 0u;
+            if (tid < 4) dctl[tid] = 0u;
+            const int64_t k0 = j + (int64_t)dir * (int64_t)(step + 1);
+            const int64_t kb = k0 + (int64_t)dir * (int64_t)lane;
+            const bool inr = kb >= 0 && kb < G.M;
+            const double sv = inr ? G.seg[dir > 0 ? kb : kb + 1] : 0.0;
+            const int32_t stl = !inr ? ST_EDGE : (sv < 0.0 ? ST_GAP : ST_OK);
+            const double gl = stl == ST_OK ? sv : 0.0;
+            const uint64_t abort_mask = __ballot(stl != ST_OK);
+            const int nb = abort_mask ? (int)__builtin_ctzll(abort_mask) : 64;
+            const int32_t abort_st = abort_mask ? (int32_t)__builtin_amdgcn_readlane(stl, nb) : ST_OK;
+            // member index of slot r: (word) * 64 + lane, built from a value
+            // the compiler cannot hoist out of the walk's loop (sixteen
+            // hoisted indices or row addresses would hold registers for the
+            // whole walk)
+            uint32_t g0 = (uint32_t)(wave * 64 + lane);
+            asm volatile("" : "+v"(g0));
+            auto gid = [&](int r) -> uint32_t { return g0 + (uint32_t)(r * wpg * 64); };
+            auto hkey = [&](int r) -> uint64_t {
+                const int wq = wave + r * wpg;
+                return wq < WA ? key_of(G.hbitsA, G.mwp, (int)gid(r), k0, dir)
+                               : key_of(G.hbitsB, G.mwp, (int)gid(r) - WA * 64, k0, dir);
+            };
+            __syncthreads();
+            // (1) references.  Members of a stopped core's classes leave the
+            // walk now (the next marker would drop them as well).
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (cls[r] != DEAD) {
+                    if (MODE == MODE_CORE && !((szc[cls[r]] >> 31) ? act1 : act0)) cls[r] = DEAD;
+                    else atomicMin(&dref[cls[r]], gid(r));
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (cls[r] != DEAD && dref[cls[r]] == gid(r)) dkey[cls[r]] = hkey(r);
+            __syncthreads();
+            // (2) the leavers (bit r of leave: slot r's member leaves), counted
+            // per class
+            uint32_t leave = 0u, nd = 0u, sq = 0u;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (cls[r] != DEAD && hkey(r) != dkey[cls[r]]) {
+                    const uint32_t old = atomicAdd(&dcnt[cls[r]], incu(r));
+                    const uint32_t rank = (old & 0xFFFFu) + (old >> 16);
+                    leave |= 1u << r;
+                    nd += 1u;
+                    sq += 2u * rank + 1u;
+                }
+            }
+            nd = wave_sum(nd);
+            sq = wave_sum(sq);
+            if (lane == 0 && nd) {
+                atomicAdd(&dctl[0], nd);
+                atomicAdd(&dctl[1], sq);
+            }
+            __syncthreads();
+            const uint32_t D = dctl[0], SQ = dctl[1];
+            if (D <= (uint32_t)kDevCap && SQ <= kDevWork) {
+                // (3) each class's leavers into one run of entries (dref, no
+                // longer needed, becomes each run's fill cursor)
+                const int KT = (K + T - 1) / T;
+                uint64_t loc = 0;
+                for (int qq = 0; qq < KT; ++qq) {
+                    const int c = tid * KT + qq;
+                    if (c < K) {
+                        const uint32_t v = dcnt[c];
+                        loc += (v & 0xFFFFu) + (v >> 16);
+                    }
+                }
+                uint64_t tot;
+                uint64_t ex = block_excl_sum(loc, wtot, tot);
+                for (int qq = 0; qq < KT; ++qq) {
+                    const int c = tid * KT + qq;
+                    if (c < K) {
+                        doff[c] = (uint32_t)ex;
+                        dref[c] = (uint32_t)ex;
+                        const uint32_t v = dcnt[c];
+                        ex += (v & 0xFFFFu) + (v >> 16);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if ((leave >> r) & 1u) {
+                        const int x = (int)atomicAdd(&dref[cls[r]], 1u);
+                        const uint64_t kx = hkey(r);
+                        ekey[x] = kx;
+                        const uint32_t dx = (uint32_t)__builtin_ctzll(kx ^ dkey[cls[r]]);
+                        einfo[x] = (uint32_t)cls[r] | (dx << 8) | ((incu(r) >> 16) << 14) | (gid(r) << 15);
+                    }
+                }
+                __syncthreads();
+                // (4) per leaver: its pairs with the class-mates that leave
+                // later or never (split where it leaves), its pairs with the
+                // earlier entries leaving at the same marker (split where the
+                // keys differ), and the first entry with its whole key
+                for (int x = tid; x < (int)D; x += T) {
+                    const uint32_t inf = einfo[x];
+                    const int c = (int)(inf & 0xFFu);
+                    const uint32_t dx = (inf >> 8) & 63u;
+                    const bool xb = ((inf >> 14) & 1u) != 0u;
+                    const uint64_t kx = ekey[x];
+                    const int s0 = (int)doff[c];
+                    const uint32_t dv = dcnt[c];
+                    const int s1 = s0 + (int)((dv & 0xFFFFu) + (dv >> 16));
+                    const uint32_t sz = szc[c];
+                    uint32_t leA = 0u, leB = 0u, gA = 0u, gB = 0u;
+                    int lead = x;
+                    for (int y = s0; y < s1; ++y) {
+                        const uint32_t iy = einfo[y];
+                        const uint32_t dy = (iy >> 8) & 63u;
+                        const bool yb = ((iy >> 14) & 1u) != 0u;
+                        if (dy <= dx) {
+                            if (yb) ++leB;
+                            else ++leA;
+                        }
+                        if (dy == dx) {
+                            const uint64_t z = kx ^ ekey[y];
+                            if (z == 0ull) {
+                                if (yb) ++gB;
+                                else ++gA;
+                                if (y < lead) lead = y;
+                            } else if (y < x) {
+                                const int L = (int)__builtin_ctzll(z);
+                                if (MODE == MODE_CORE) {
+                                    atomicAdd(&dhist[(sz >> 31) * 64u + (uint32_t)L], 1u);
+                                } else {
+                                    atomicAdd(&dhist[L], 1u);
+                                    if (!xb && !yb) atomicAdd(&dhist[64 + L], 1u);
+                                    else if (xb && yb) atomicAdd(&dhist[128 + L], 1u);
+                                }
+                            }
+                        }
+                    }
+                    if (MODE == MODE_CORE) {
+                        const uint32_t rest = (sz & 0xFFFFu) - leA;
+                        if (rest) atomicAdd(&dhist[(sz >> 31) * 64u + dx], rest);
+                    } else {
+                        const uint32_t nA = sz & 0xFFFFu, nB = sz >> 16;
+                        const uint32_t rest = nA + nB - leA - leB;
+                        if (rest) atomicAdd(&dhist[dx], rest);
+                        const uint32_t same = xb ? nB - leB : nA - leA;
+                        if (same) atomicAdd(&dhist[(xb ? 128u : 64u) + dx], same);
+                    }
+                    elead[x] = lead;
+                    if (lead == x) egid[x] = (int32_t)(gA | (gB << 16));
+                }
+                __syncthreads();
+                settle(dhist, nb, gl);
+                if (!(act0 || act1)) goto done;
+                if (nb < 64) {
+                    status = abort_st;
+                    goto done;
+                }
+                // (5) the classes after the pass: stayers, and groups of
+                // leavers with one key, of >= 2 members of a walking core
+                for (int c = tid; c < K; c += T) {
+                    const uint32_t sz = szc[c], dv = dcnt[c];
+                    uint32_t nsz, cnt;
+                    bool keep;
+                    if (MODE == MODE_CORE) {
+                        cnt = (sz & 0xFFFFu) - (dv & 0xFFFFu);
+                        keep = ((sz >> 31) ? act1 : act0) && cnt >= 2u;
+                        nsz = cnt | (sz & 0x80000000u);
+                    } else {
+                        const uint32_t ra = (sz & 0xFFFFu) - (dv & 0xFFFFu), rb = (sz >> 16) - (dv >> 16);
+                        cnt = ra + rb;
+                        keep = cnt >= 2u;
+                        nsz = ra | (rb << 16);
+                    }
+                    int32_t id = DEAD;
+                    if (keep) {
+                        id = (int32_t)atomicAdd(&dctl[2], 1u);
+                        if (id < kmax) szn[id] = nsz;
+                        atomicAdd(&dctl[3], cnt);
+                    }
+                    map[2 * c] = id;
+                }
+                for (int x = tid; x < (int)D; x += T) {
+                    if (elead[x] != x) continue;
+                    const uint32_t g = (uint32_t)egid[x];
+                    const uint32_t cnt = (g & 0xFFFFu) + (g >> 16);
+                    const uint32_t sz = szc[einfo[x] & 0xFFu];
+                    const bool keep = (MODE == MODE_CORE ? ((sz >> 31) ? act1 : act0) : true) && cnt >= 2u;
+                    int32_t id = DEAD;
+                    if (keep) {
+                        id = (int32_t)atomicAdd(&dctl[2], 1u);
+                        if (id < kmax) szn[id] = MODE == MODE_CORE ? (cnt | (sz & 0x80000000u)) : g;
+                        atomicAdd(&dctl[3], cnt);
+                    }
+                    egid[x] = id;
+                }
+                __syncthreads();
+                const int Kn = (int)dctl[2];
+                const uint32_t members = dctl[3];
+                if (Kn > kmax) goto overflowed;   // the walk is redone with full tables
+                // members: a stayer takes its class's new id, a leaver finds
+                // its entry in its class's run and takes its group's
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (cls[r] == DEAD) continue;
+                    if ((leave >> r) & 1u) {
+                        const int c = cls[r];
+                        const int s0 = (int)doff[c];
+                        const uint32_t dv = dcnt[c];
+                        const int s1 = s0 + (int)((dv & 0xFFFFu) + (dv >> 16));
+                        int x = s0;
+                        while (x < s1 - 1 && (einfo[x] >> 15) != gid(r)) ++x;
+                        cls[r] = egid[elead[x]];
+                    } else {
+                        cls[r] = map[2 * cls[r]];
+                    }
+                }
+                K = Kn;
+                pflip ^= 1;
+                step += 64;
+                if (tid < 8) sacc[tid] = 0u;
+                if (tid < 2) knext[tid] = 0;
+                __syncthreads();
+                if (can_pair && (act0 || act1)) {
+                    const uint32_t left = MODE == MODE_CORE ? (act0 ? sa0 : 0u) + (act1 ? sa1 : 0u) : sa2;
+                    if (left <= (uint32_t)pcap && members <= (uint32_t)kcap) {
+                        pmode = true;
+                        goto pairs;
+                    }
+                }
+                continue;
+            }
+            __syncthreads();   // a pass not taken: its arrays are free again
+        }
         // stage the next 64 markers: lane i holds the row words and the
         // segment of step (step + 1 + i)
         const int64_t kb = j + (int64_t)dir * (int64_t)(step + 1 + lane);
@@ -324,7 +705,7 @@ __device__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *
                 status = abort_st;
                 goto done;
             }
-            const int par = step & 1;
+            const int par = (step & 1) ^ pflip;
             uint32_t *szc = par ? szv1 : szv0;
             uint32_t *szn = par ? szv0 : szv1;
             uint32_t *sa = sacc + 4 * par;
@@ -500,7 +881,7 @@ pairs : {
     // ---- build the list of identical pairs from the live classes ----------------
     // classes of a stopped core are still in the table; they are skipped
     __syncthreads();
-    const int par = step & 1;
+    const int par = (step & 1) ^ pflip;
     uint32_t *szc = par ? szv1 : szv0;     // sizes of the current classes
     uint32_t *sbase = par ? szv0 : szv1;   // member offset of each class
     uint64_t *wtot = (uint64_t *)(base + Ly.wtot);
@@ -632,72 +1013,7 @@ pairs : {
             if (surv) pout[wo + __popcll(sm & low_bits(lane))] = pr;
         }
         __syncthreads();
-        const uint64_t valid = low_bits(nb);
-        const int lim = nb < 64 ? nb : 64;
-        if (MODE == MODE_CORE) {
-            // each core stops at its own first sub-cutoff marker of the pass
-            const uint32_t si0 = sa0 - wave_prefix(hist[lane], lane);
-            const uint32_t si1 = sa1 - wave_prefix(hist[64 + lane], lane);
-            if (act0) {
-                const uint64_t sm = __ballot(si0 <= thr0) & valid;
-                const int nterm = sm ? (int)__builtin_ctzll(sm) : lim;
-                steps0 += sm ? nterm + 1 : lim;
-                if (nterm > 0) {
-                    const double e = (double)si0 / P0;
-                    double prev = __shfl_up(e, 1, 64);
-                    if (lane == 0) prev = ep0;
-                    const double term = 0.5 * (prev + e) * gl;
-                    for (int t = 0; t < nterm; ++t) ihh0 += readlane_f64(term, t);
-                    ep0 = readlane_f64(e, nterm - 1);
-                }
-                if (sm) act0 = false;
-            }
-            if (act1) {
-                const uint64_t sm = __ballot(si1 <= thr1) & valid;
-                const int nterm = sm ? (int)__builtin_ctzll(sm) : lim;
-                steps1 += sm ? nterm + 1 : lim;
-                if (nterm > 0) {
-                    const double e = (double)si1 / P1;
-                    double prev = __shfl_up(e, 1, 64);
-                    if (lane == 0) prev = ep1;
-                    const double term = 0.5 * (prev + e) * gl;
-                    for (int t = 0; t < nterm; ++t) ihh1 += readlane_f64(term, t);
-                    ep1 = readlane_f64(e, nterm - 1);
-                }
-                if (sm) act1 = false;
-            }
-            sa0 = (uint32_t)__builtin_amdgcn_readlane(si0, 63);
-            sa1 = (uint32_t)__builtin_amdgcn_readlane(si1, 63);
-        } else {
-            const uint32_t siP = sa2 - wave_prefix(hist[lane], lane);
-            const uint32_t siA = sa0 - wave_prefix(hist[64 + lane], lane);
-            const uint32_t siB = sa1 - wave_prefix(hist[128 + lane], lane);
-            const uint64_t sm = __ballot(siP <= thr0) & valid;
-            const int nterm = sm ? (int)__builtin_ctzll(sm) : lim;
-            steps0 += sm ? nterm + 1 : lim;
-            if (nterm > 0) {
-                const double eA = (double)siA / P0;
-                const double eB = (double)siB / P1;
-                double pA = __shfl_up(eA, 1, 64);
-                double pBv = __shfl_up(eB, 1, 64);
-                if (lane == 0) {
-                    pA = ep0;
-                    pBv = ep1;
-                }
-                const double tA = 0.5 * (pA + eA) * gl;
-                const double tB = 0.5 * (pBv + eB) * gl;
-                for (int t = 0; t < nterm; ++t) {
-                    ihh0 += readlane_f64(tA, t);
-                    ihh1 += readlane_f64(tB, t);
-                }
-                ep0 = readlane_f64(eA, nterm - 1);
-                ep1 = readlane_f64(eB, nterm - 1);
-            }
-            if (sm) act0 = false;
-            sa2 = (uint32_t)__builtin_amdgcn_readlane(siP, 63);
-            sa0 = (uint32_t)__builtin_amdgcn_readlane(siA, 63);
-            sa1 = (uint32_t)__builtin_amdgcn_readlane(siB, 63);
-        }
+        settle(hist, nb, gl);
         if ((act0 || act1) && nb < 64) {
             status = abort_st;
             break;

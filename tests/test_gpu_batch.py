@@ -357,3 +357,55 @@ def test_batch_pooled_9000_haplotypes(ss, cfg):
         ss.set_batch_config(ss.BatchConfig())
     for g, (_, _, _, ref) in zip(got, regs):
         check_xpehh(g, ref, "batch pooled 9000 %s" % cfg)
+
+
+# Regions above 1,024 haplotypes with a planted sweep: walks from cores in the
+# sweep block run for hundreds of markers with a few large classes, the case
+# the 64-marker reference passes of the class-id walk take.  (n, sites, sweep
+# site, phi, first site after a gap beyond max_gap or None): sweeps in the
+# middle, near the data's end (walks end at the edge inside a pass) and cut
+# by a gap (walks abort inside a pass).
+SWEEP_REGIONS = [(1500, 1400, 700, 0.7, None), (1300, 1200, 1120, 0.8, None),
+                 (1400, 1300, 600, 0.75, 680), (2100, 900, 450, 0.9, None)]
+SWEEP_CONFIGS = [dict(), dict(threads=128), dict(slots=4), dict(class_cap=64),
+                 dict(pair_cap=0), dict(threads=1024, counter_copies=8)]
+
+
+def _sweep_region(n, m, site, phi, gap, seed):
+    d = hapgen.copying_model(n, m, 1_400_000, 30, 0.003, seed, sweeps=[(site, phi)])
+    pos, gpos = d.pos_bp.copy(), d.gpos_cm.copy()
+    if gap is not None:
+        pos[gap:] += 300_000
+        gpos[gap:] += 0.3
+    return d.alleles, pos, gpos
+
+
+@pytest.fixture(scope="module")
+def sweep_regions(ss):
+    out = []
+    for i, (n, m, site, phi, gap) in enumerate(SWEEP_REGIONS):
+        al, pos, gpos = _sweep_region(n, m, site, phi, gap, 40 + i)
+        ref = oracle.ihs(al, pos, gpos)
+        assert ref["steps"].max() >= 192, "walks too short for the reference passes"
+        if gap is not None:
+            assert (ref["status"] == 3).any(), "no walk aborts at the gap"
+        out.append(("ihs", _hm(ss, al, pos, gpos), None, ref))
+    return out
+
+
+@pytest.mark.parametrize("cfg", SWEEP_CONFIGS,
+                         ids=[",".join("%s=%s" % kv for kv in c.items()) or "default"
+                              for c in SWEEP_CONFIGS])
+def test_sweep_regions_long_walks(ss, sweep_regions, cfg):
+    say("ss_scan_batch sweep regions config %s" % cfg)
+    ss.set_batch_config(ss.BatchConfig(small_kernel=0, **cfg))
+    try:
+        _, got = _run_batch(ss, sweep_regions)
+    finally:
+        ss.set_batch_config(ss.BatchConfig())
+    _check_all(got, sweep_regions, "sweep batch %s" % cfg)
+    if not cfg:
+        for (kind, ha, _, _), g in zip(sweep_regions, got):
+            one = _np(ss.ihs(ha, steps=True))
+            for k in one:
+                np.testing.assert_array_equal(g[k], one[k], err_msg="single call " + k)
