@@ -183,19 +183,23 @@ __host__ __device__ inline BLay batch_layout(int lmax, int kcls, int pcap, int k
     l.pcnt = v;   v = al16(v + 16u);
     o = table_end > v ? table_end : v;
     l.wtot = o;   o = al16(o + 8u * 16u);
-    l.mem = o;    o = al16(o + 2u * (uint32_t)kcap);
-    l.pairs0 = o; o = al16(o + 4u * (uint32_t)pcap);
-    l.dref = o;   o = al16(o + 4u * kDevClasses);
-    l.dkey = o;   o = al16(o + 8u * kDevClasses);
-    l.dcnt = o;   o = al16(o + 4u * kDevClasses);
-    l.doff = o;   o = al16(o + 4u * kDevClasses);
-    l.ekey = o;   o = al16(o + 8u * kDevCap);
-    l.einfo = o;  o = al16(o + 4u * kDevCap);
-    l.elead = o;  o = al16(o + 4u * kDevCap);
-    l.egid = o;   o = al16(o + 4u * kDevCap);
-    l.dhist = o;  o = al16(o + 4u * 3u * 64u);
-    l.dctl = o;   o = al16(o + 16u);
-    l.total = o;
+    // the member and pair lists of the pairwise tail, and the reference
+    // passes' arrays (which end before the tail starts), share what follows
+    uint32_t t = o;
+    l.mem = t;    t = al16(t + 2u * (uint32_t)kcap);
+    l.pairs0 = t; t = al16(t + 4u * (uint32_t)pcap);
+    uint32_t r = o;
+    l.dref = r;   r = al16(r + 4u * kDevClasses);
+    l.dkey = r;   r = al16(r + 8u * kDevClasses);
+    l.dcnt = r;   r = al16(r + 4u * kDevClasses);
+    l.doff = r;   r = al16(r + 4u * kDevClasses);
+    l.ekey = r;   r = al16(r + 8u * kDevCap);
+    l.einfo = r;  r = al16(r + 4u * kDevCap);
+    l.elead = r;  r = al16(r + 4u * kDevCap);
+    l.egid = r;   r = al16(r + 4u * kDevCap);
+    l.dhist = r;  r = al16(r + 4u * 3u * 64u);
+    l.dctl = r;   r = al16(r + 16u);
+    l.total = t > r ? t : r;
     return l;
 }
 
