@@ -715,16 +715,15 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
             uint32_t *sa = sacc + 4 * par;
             int32_t *kn = knext + par;
 
-            // (1) ones per class
-            int32_t bit[R];
+            // (1) ones per class; a member's class id becomes its child's
+            // index in the class pass's map, 2 * class + allele
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                bit[r] = 0;
-                if (word(r)) {
+                if (word(r) && cls[r] != DEAD) {
                     const uint64_t w = readlane64(rowv[r], i);
-                    bit[r] = (int32_t)((w >> lane) & 1ull);
-                    if (cls[r] != DEAD && bit[r])
-                        atomicAdd(&cnt1[cls[r] * ncp + (lane & (ncp - 1))], incu(r));
+                    const int32_t bit = (int32_t)((w >> lane) & 1ull);
+                    if (bit) atomicAdd(&cnt1[cls[r] * ncp + (lane & (ncp - 1))], incu(r));
+                    cls[r] = 2 * cls[r] + bit;
                 }
             }
             __syncthreads();
@@ -819,7 +818,7 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
             // (3) new class ids
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (cls[r] != DEAD) cls[r] = map[2 * cls[r] + bit[r]];
+                if (cls[r] != DEAD) cls[r] = map[cls[r]];
             K = kn[0];
             const uint32_t S0 = sa[0], S1 = sa[1], S2 = sa[2], members = sa[3];
             if (tid == 0) {
