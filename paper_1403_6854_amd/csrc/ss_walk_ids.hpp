@@ -95,7 +95,11 @@ template <int MODE, bool TRACE, int R>
 __device__ void walk_one(const WalkArgs &a, int64_t j, int d) {
     extern __shared__ uint32_t smem[];
     const int T = blockDim.x;
-    const int tid = threadIdx.x;
+    // the thread index comes from a value the compiler cannot share with
+    // the caller's (inlined into the bitmask walk as its fallback, addresses
+    // built from a shared index were kept from the kernel's start and spilled)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wpg = T >> 6;

@@ -300,13 +300,18 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
     // wave's NR rows.
     auto compact = [&](const bool (&split)[NR], const uint64_t (&zm)[NR][WPL],
                        const uint32_t (&za)[NR], const uint32_t (&zb)[NR]) -> bool {
-        const uint64_t below_group = (q == 0) ? 0ull : ((1ull << (q * LPC)) - 1ull);
+        // leader lanes set in a mask below this lane's class: the set lanes
+        // below this lane, less its own leader's if this lane is not one
+        auto groups_below = [&](uint64_t lmask) -> int {
+            const uint32_t b = lanes_below(lmask);
+            return (int)(g ? b - (uint32_t)((lmask >> (lane - g)) & 1ull) : b);
+        };
         int nlive = 0, nsplit = 0;
         int at[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const uint64_t lm = __ballot(leader && ca[r] + cb[r] >= 2u);
-            at[r] = nlive + __popcll(lm & below_group);
+            at[r] = nlive + groups_below(lm);
             nlive += __popcll(lm);
             nsplit += __popcll(__ballot(leader && split[r]));
         }
@@ -322,7 +327,7 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
             }
             const uint64_t sm = __ballot(leader && split[r]);
             if (split[r]) {
-                uint64_t *e = stage + (size_t)(nsp + __popcll(sm & below_group)) * (W + 1);
+                uint64_t *e = stage + (size_t)(nsp + groups_below(sm)) * (W + 1);
 #pragma unroll
                 for (int t = 0; t < WPL; ++t) e[g * WPL + t] = zm[r][t];
                 if (leader) e[W] = (uint64_t)(za[r] | (zb[r] << 16));
@@ -377,8 +382,7 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
 #pragma unroll
                 for (int r = 0; r < NR; ++r)
                     if (r == rr) mw = readlane64(m[r][w % WPL], qq * LPC + w / WPL);
-                const uint64_t below = lane ? (mw & ((1ull << lane) - 1ull)) : 0ull;
-                if ((mw >> lane) & 1ull) memb[nmem + sz + __popcll(below)] = (uint16_t)(64 * w + lane);
+                if ((mw >> lane) & 1ull) memb[nmem + sz + (int)lanes_below(mw)] = (uint16_t)(64 * w + lane);
                 sz += __popcll(mw);
             }
             // the class's members are entries nmem .. nmem + sz - 1 of the
@@ -690,8 +694,7 @@ __global__ void __launch_bounds__(64, (mask_waves_per_eu<MODE, W>())) mask_walk_
                 if (in && L < 64) atomicAdd(&hist[L], 1u);
                 const bool surv = in && L == 64;
                 const uint64_t sm = __ballot(surv);
-                const uint64_t below = lane ? (sm & ((1ull << lane) - 1ull)) : 0ull;
-                if (surv) pairs[wpos + __popcll(below)] = pr;   // wpos <= p0: in place
+                if (surv) pairs[wpos + (int)lanes_below(sm)] = pr;   // wpos <= p0: in place
                 wpos += __popcll(sm);
             }
             __syncthreads();
