@@ -182,8 +182,9 @@ struct WorkQueue {
     int part, left;
     unsigned long long pend;   // offset taken in `part`, not yet handed out
 
-    __device__ int64_t bound(int x) const { return total * x / kParts; }
-    __device__ void init(unsigned long long *c, int64_t t, int ch) {
+    // (inlined: called, the queue would live in scratch memory for its address)
+    __device__ __forceinline__ int64_t bound(int x) const { return total * x / kParts; }
+    __device__ __forceinline__ void init(unsigned long long *c, int64_t t, int ch) {
         ctr = c;
         total = t;
         chunk = (unsigned long long)ch;
@@ -193,7 +194,7 @@ struct WorkQueue {
     }
     // The grab issued last as the chunk [lo, hi); lo == hi == total once every
     // part is used up.
-    __device__ void resolve(int64_t &lo, int64_t &hi) {
+    __device__ __forceinline__ void resolve(int64_t &lo, int64_t &hi) {
         for (;;) {
             const int64_t a = bound(part), b = bound(part + 1);
             const int64_t s = a + (int64_t)pend;
@@ -211,7 +212,7 @@ struct WorkQueue {
         }
     }
     // The next grab in the current part, in flight while a chunk is walked.
-    __device__ void prefetch() { pend = atomicAdd(ctr + part * kCtrStride, chunk); }
+    __device__ __forceinline__ void prefetch() { pend = atomicAdd(ctr + part * kCtrStride, chunk); }
 };
 
 // Arguments of one launch of the class-id batch walk.

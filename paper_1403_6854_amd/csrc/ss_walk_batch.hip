@@ -211,7 +211,10 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
     // so that a copy of the descriptor does not hold registers for the walk
     const Region &G = *Gp;
     const int T = (int)blockDim.x;
-    const int tid = threadIdx.x;
+    // (from a value the compiler cannot share with the persistent loop's, so
+    // that indices built from it are not kept live across items)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wpg = T >> 6;
