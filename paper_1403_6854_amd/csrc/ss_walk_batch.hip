@@ -13,7 +13,11 @@
 //     register.  Per marker the members with allele 1 count into their
 //     class's LDS counter, then one pass over the classes makes the children,
 //     drops those with < 2 members (and the classes of a core whose walk has
-//     stopped), gives the survivors dense ids, and sums C(., 2);
+//     stopped), gives the survivors dense ids, and sums C(., 2).  iHS walks
+//     take two markers per step: each member counts its pair of alleles (one
+//     64-bit counter with 21-bit fields for 01, 10 and 11), the class pass
+//     makes up to four children and the sums after each of the two markers
+//     (the first from the children's sizes by first allele);
 //   * once the identical pairs left (the iHS cores' pairs, or the pooled
 //     pairs of XPEHH) number at most the pair capacity, the live classes are
 //     expanded into the list of those pairs and each pass covers 64 markers:
@@ -165,11 +169,13 @@ __host__ __device__ inline BLay batch_layout(int lmax, int kcls, int pcap, int k
     l.copies = copies;
     const uint32_t K = (uint32_t)l.kmax;
     uint32_t o = 0;
-    l.cnt1 = o;  o += 4u * K * (uint32_t)copies;
+    // counters: 32-bit ones per class, or (iHS steps over two markers)
+    // 64-bit fields of the allele pairs 01, 10 and 11
+    l.cnt1 = o;  o += 8u * K * (uint32_t)copies;
     l.szv0 = o;  o += 4u * K;
     l.szv1 = o;  o += 4u * K;
-    l.map = o;   o += 8u * K;
-    l.sacc = o;  o += 32u;
+    l.map = o;   o += 16u * K;   // children of each class: 2 per marker, 4 per two
+    l.sacc = o;  o += 64u;
     l.knext = o; o += 8u;
     l.init = o;  o += 8u;
     l.ovf = o;   o += 8u;
@@ -233,8 +239,8 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
     uint32_t *init = (uint32_t *)(base + Ly.init);
     int32_t *ovf = (int32_t *)(base + Ly.ovf);   // the class table overflowed
 
-    for (int i = tid; i < kmax * ncp; i += T) cnt1[i] = 0u;
-    if (tid < 8) sacc[tid] = 0u;
+    for (int i = tid; i < 2 * kmax * ncp; i += T) cnt1[i] = 0u;
+    if (tid < 16) sacc[tid] = 0u;
     if (tid < 2) {
         knext[tid] = 0;
         init[tid] = 0u;
@@ -673,7 +679,7 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                 K = Kn;
                 pflip ^= 1;
                 step += 64;
-                if (tid < 8) sacc[tid] = 0u;
+                if (tid < 16) sacc[tid] = 0u;
                 if (tid < 2) knext[tid] = 0;
                 __syncthreads();
                 if (can_pair && (act0 || act1)) {
@@ -707,113 +713,219 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
         const int nb = abort_mask ? (int)__builtin_ctzll(abort_mask) : 64;
         const int32_t abort_st = abort_mask ? (int32_t)__builtin_amdgcn_readlane(stl, nb) : ST_OK;
 
-        for (int i = 0; i < 64 && (act0 || act1); ++i) {
+        for (int i = 0; i < 64 && (act0 || act1);) {
             if (i == nb) {
                 status = abort_st;
                 goto done;
             }
+            // iHS walks refine two markers per step while both are walked:
+            // one count per member of its alleles at both, one class pass
+            // making the up to four children (S after the first marker from
+            // the children's pairs by first allele), so half the workgroup
+            // barriers and LDS round trips per marker
+            const bool two = MODE == MODE_CORE && i + 1 < nb && i + 1 < 64;
             const int par = (step & 1) ^ pflip;
             uint32_t *szc = par ? szv1 : szv0;
             uint32_t *szn = par ? szv0 : szv1;
-            uint32_t *sa = sacc + 4 * par;
+            uint32_t *sa = sacc + 8 * par;
             int32_t *kn = knext + par;
+            uint64_t *cnt2 = (uint64_t *)cnt1;
 
-            // (1) ones per class; a member's class id becomes its child's
-            // index in the class pass's map, 2 * class + allele
+            // (1) alleles per class; a member's class id becomes its child's
+            // index in the class pass's map: 2 * class + allele, or
+            // 4 * class + (first allele) * 2 + second allele
+            if (two) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (word(r) && cls[r] != DEAD) {
-                    const uint64_t w = readlane64(rowv[r], i);
-                    const int32_t bit = (int32_t)((w >> lane) & 1ull);
-                    if (bit) atomicAdd(&cnt1[cls[r] * ncp + (lane & (ncp - 1))], incu(r));
-                    cls[r] = 2 * cls[r] + bit;
+                for (int r = 0; r < R; ++r) {
+                    if (word(r) && cls[r] != DEAD) {
+                        const int32_t b1 = (int32_t)((readlane64(rowv[r], i) >> lane) & 1ull);
+                        const int32_t b2 = (int32_t)((readlane64(rowv[r], i + 1) >> lane) & 1ull);
+                        const int32_t ab = 2 * b1 + b2;
+                        if (ab) atomicAdd(&cnt2[cls[r] * ncp + (lane & (ncp - 1))], 1ull << (21 * (ab - 1)));
+                        cls[r] = 4 * cls[r] + ab;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (word(r) && cls[r] != DEAD) {
+                        const uint64_t w = readlane64(rowv[r], i);
+                        const int32_t bit = (int32_t)((w >> lane) & 1ull);
+                        if (bit) atomicAdd(&cnt1[cls[r] * ncp + (lane & (ncp - 1))], incu(r));
+                        cls[r] = 2 * cls[r] + bit;
+                    }
                 }
             }
             __syncthreads();
 
             // (2) split every class, keep children with >= 2 members
-            for (int c0 = 0; c0 < K; c0 += T) {
-                const int c = c0 + tid;
-                const bool in = c < K;
-                uint32_t one = 0u, sz = 0u;
-                if (in) {
-                    for (int q = 0; q < ncp; ++q) {
-                        one += cnt1[c * ncp + q];
-                        cnt1[c * ncp + q] = 0u;
+            if (two) {
+                for (int c0 = 0; c0 < K; c0 += T) {
+                    const int c = c0 + tid;
+                    const bool in = c < K;
+                    uint64_t f = 0ull;
+                    uint32_t sz = 0u;
+                    if (in) {
+                        for (int q = 0; q < ncp; ++q) {
+                            f += cnt2[c * ncp + q];
+                            cnt2[c * ncp + q] = 0ull;
+                        }
+                        sz = szc[c];
                     }
-                    sz = szc[c];
-                }
-                bool keepz = false, keepo = false;
-                uint32_t wz = 0u, wo = 0u;
-                uint32_t s0 = 0u, s1 = 0u, s2 = 0u, s3 = 0u;   // s3: members kept
-                if (in) {
-                    if (MODE == MODE_CORE) {
-                        const uint32_t core = sz >> 31;
-                        const uint32_t n = sz & 0xFFFFu;
-                        const uint32_t o = one, z = n - one;
-                        const bool live = core ? act1 : act0;
-                        const uint32_t sc = choose2(o) + choose2(z);
-                        if (core) s1 = sc;
-                        else s0 = sc;
-                        keepz = live && z >= 2u;
-                        keepo = live && o >= 2u;
-                        s3 = (keepz ? z : 0u) + (keepo ? o : 0u);
-                        wz = z | (core << 31);
-                        wo = o | (core << 31);
-                    } else {
-                        const uint32_t nAc = sz & 0xFFFFu, nBc = sz >> 16;
-                        const uint32_t oA = one & 0xFFFFu, oB = one >> 16;
-                        const uint32_t zA = nAc - oA, zB = nBc - oB;
-                        s0 = choose2(oA) + choose2(zA);
-                        s1 = choose2(oB) + choose2(zB);
-                        s2 = choose2(oA + oB) + choose2(zA + zB);
-                        keepz = zA + zB >= 2u;
-                        keepo = oA + oB >= 2u;
-                        s3 = (keepz ? zA + zB : 0u) + (keepo ? oA + oB : 0u);
-                        wz = zA | (zB << 16);
-                        wo = oA | (oB << 16);
-                    }
-                }
-                const uint64_t bz = __ballot(keepz);
-                const uint64_t bo = __ballot(keepo);
-                const int nz = __popcll(bz), no = __popcll(bo);
-                // one wave owns the counters outright; several share them
-                int basei = 0;
-                if (wpg == 1) {
-                    basei = kn[0];
-                } else {
-                    if (lane == 0 && nz + no > 0) basei = atomicAdd(kn, nz + no);
-                    basei = __shfl(basei, 0, 64);
-                }
-                const int idz = basei + (int)lanes_below(bz);
-                const int ido = basei + nz + (int)lanes_below(bo);
-                const bool fits = basei + nz + no <= kmax;   // wave-uniform
-                if (!fits && lane == 0) *ovf = 1;
-                if (in) {
-                    map[2 * c] = keepz ? idz : DEAD;
-                    map[2 * c + 1] = keepo ? ido : DEAD;
-                }
-                if (fits && keepz) szn[idz] = wz;
-                if (fits && keepo) szn[ido] = wo;
-                s0 = wave_sum(s0);
-                s1 = wave_sum(s1);
-                if (MODE == MODE_POOLED) s2 = wave_sum(s2);
-                if (can_pair) s3 = wave_sum(s3);
-                if (lane == 0) {
+                    const uint32_t core = sz >> 31;
+                    const uint32_t n = sz & 0xFFFFu;
+                    const uint32_t m01 = (uint32_t)(f & 0x1FFFFFull);
+                    const uint32_t m10 = (uint32_t)((f >> 21) & 0x1FFFFFull);
+                    const uint32_t m11 = (uint32_t)(f >> 42);
+                    const uint32_t m00 = n - m01 - m10 - m11;
+                    const bool live = in && (core ? act1 : act0);
+                    // S after the first marker (children by first allele) and
+                    // after the second (the four children)
+                    const uint32_t sf = in ? choose2(m00 + m01) + choose2(m10 + m11) : 0u;
+                    const uint32_t ss2 = in ? choose2(m00) + choose2(m01) + choose2(m10) + choose2(m11) : 0u;
+                    const bool k00 = live && m00 >= 2u, k01 = live && m01 >= 2u;
+                    const bool k10 = live && m10 >= 2u, k11 = live && m11 >= 2u;
+                    uint32_t s3 = (k00 ? m00 : 0u) + (k01 ? m01 : 0u) + (k10 ? m10 : 0u) + (k11 ? m11 : 0u);
+                    const uint64_t b00 = __ballot(k00), b01 = __ballot(k01);
+                    const uint64_t b10 = __ballot(k10), b11 = __ballot(k11);
+                    const int n00 = __popcll(b00), n01 = __popcll(b01);
+                    const int n10 = __popcll(b10), n11 = __popcll(b11);
+                    const int nk = n00 + n01 + n10 + n11;
+                    int basei = 0;
                     if (wpg == 1) {
-                        kn[0] = basei + nz + no;
-                        sa[0] += s0;
-                        sa[1] += s1;
-                        if (MODE == MODE_POOLED) sa[2] += s2;
-                        sa[3] += s3;
+                        basei = kn[0];
                     } else {
-                        if (s0) atomicAdd(&sa[0], s0);
-                        if (s1) atomicAdd(&sa[1], s1);
-                        if (MODE == MODE_POOLED && s2) atomicAdd(&sa[2], s2);
-                        if (s3) atomicAdd(&sa[3], s3);
+                        if (lane == 0 && nk > 0) basei = atomicAdd(kn, nk);
+                        basei = __shfl(basei, 0, 64);
                     }
+                    const int i00 = basei + (int)lanes_below(b00);
+                    const int i01 = basei + n00 + (int)lanes_below(b01);
+                    const int i10 = basei + n00 + n01 + (int)lanes_below(b10);
+                    const int i11 = basei + n00 + n01 + n10 + (int)lanes_below(b11);
+                    const bool fits = basei + nk <= kmax;   // wave-uniform
+                    if (!fits && lane == 0) *ovf = 1;
+                    if (in) {
+                        map[4 * c + 0] = k00 ? i00 : DEAD;
+                        map[4 * c + 1] = k01 ? i01 : DEAD;
+                        map[4 * c + 2] = k10 ? i10 : DEAD;
+                        map[4 * c + 3] = k11 ? i11 : DEAD;
+                    }
+                    if (fits) {
+                        const uint32_t cb = core << 31;
+                        if (k00) szn[i00] = m00 | cb;
+                        if (k01) szn[i01] = m01 | cb;
+                        if (k10) szn[i10] = m10 | cb;
+                        if (k11) szn[i11] = m11 | cb;
+                    }
+                    uint32_t f0 = core ? 0u : sf, f1 = core ? sf : 0u;
+                    uint32_t t0 = core ? 0u : ss2, t1 = core ? ss2 : 0u;
+                    f0 = wave_sum(f0);
+                    f1 = wave_sum(f1);
+                    t0 = wave_sum(t0);
+                    t1 = wave_sum(t1);
+                    if (can_pair) s3 = wave_sum(s3);
+                    if (lane == 0) {
+                        if (wpg == 1) {
+                            kn[0] = basei + nk;
+                            sa[0] += t0;
+                            sa[1] += t1;
+                            sa[3] += s3;
+                            sa[4] += f0;
+                            sa[5] += f1;
+                        } else {
+                            if (t0) atomicAdd(&sa[0], t0);
+                            if (t1) atomicAdd(&sa[1], t1);
+                            if (s3) atomicAdd(&sa[3], s3);
+                            if (f0) atomicAdd(&sa[4], f0);
+                            if (f1) atomicAdd(&sa[5], f1);
+                        }
+                    }
+                    if (wpg == 1) __syncthreads();   // kn[0] is read again next round
                 }
-                if (wpg == 1) __syncthreads();   // kn[0] is read again next round
+            } else {
+                for (int c0 = 0; c0 < K; c0 += T) {
+                    const int c = c0 + tid;
+                    const bool in = c < K;
+                    uint32_t one = 0u, sz = 0u;
+                    if (in) {
+                        for (int q = 0; q < ncp; ++q) {
+                            one += cnt1[c * ncp + q];
+                            cnt1[c * ncp + q] = 0u;
+                        }
+                        sz = szc[c];
+                    }
+                    bool keepz = false, keepo = false;
+                    uint32_t wz = 0u, wo = 0u;
+                    uint32_t s0 = 0u, s1 = 0u, s2 = 0u, s3 = 0u;   // s3: members kept
+                    if (in) {
+                        if (MODE == MODE_CORE) {
+                            const uint32_t core = sz >> 31;
+                            const uint32_t n = sz & 0xFFFFu;
+                            const uint32_t o = one, z = n - one;
+                            const bool live = core ? act1 : act0;
+                            const uint32_t sc = choose2(o) + choose2(z);
+                            if (core) s1 = sc;
+                            else s0 = sc;
+                            keepz = live && z >= 2u;
+                            keepo = live && o >= 2u;
+                            s3 = (keepz ? z : 0u) + (keepo ? o : 0u);
+                            wz = z | (core << 31);
+                            wo = o | (core << 31);
+                        } else {
+                            const uint32_t nAc = sz & 0xFFFFu, nBc = sz >> 16;
+                            const uint32_t oA = one & 0xFFFFu, oB = one >> 16;
+                            const uint32_t zA = nAc - oA, zB = nBc - oB;
+                            s0 = choose2(oA) + choose2(zA);
+                            s1 = choose2(oB) + choose2(zB);
+                            s2 = choose2(oA + oB) + choose2(zA + zB);
+                            keepz = zA + zB >= 2u;
+                            keepo = oA + oB >= 2u;
+                            s3 = (keepz ? zA + zB : 0u) + (keepo ? oA + oB : 0u);
+                            wz = zA | (zB << 16);
+                            wo = oA | (oB << 16);
+                        }
+                    }
+                    const uint64_t bz = __ballot(keepz);
+                    const uint64_t bo = __ballot(keepo);
+                    const int nz = __popcll(bz), no = __popcll(bo);
+                    // one wave owns the counters outright; several share them
+                    int basei = 0;
+                    if (wpg == 1) {
+                        basei = kn[0];
+                    } else {
+                        if (lane == 0 && nz + no > 0) basei = atomicAdd(kn, nz + no);
+                        basei = __shfl(basei, 0, 64);
+                    }
+                    const int idz = basei + (int)lanes_below(bz);
+                    const int ido = basei + nz + (int)lanes_below(bo);
+                    const bool fits = basei + nz + no <= kmax;   // wave-uniform
+                    if (!fits && lane == 0) *ovf = 1;
+                    if (in) {
+                        map[2 * c] = keepz ? idz : DEAD;
+                        map[2 * c + 1] = keepo ? ido : DEAD;
+                    }
+                    if (fits && keepz) szn[idz] = wz;
+                    if (fits && keepo) szn[ido] = wo;
+                    s0 = wave_sum(s0);
+                    s1 = wave_sum(s1);
+                    if (MODE == MODE_POOLED) s2 = wave_sum(s2);
+                    if (can_pair) s3 = wave_sum(s3);
+                    if (lane == 0) {
+                        if (wpg == 1) {
+                            kn[0] = basei + nz + no;
+                            sa[0] += s0;
+                            sa[1] += s1;
+                            if (MODE == MODE_POOLED) sa[2] += s2;
+                            sa[3] += s3;
+                        } else {
+                            if (s0) atomicAdd(&sa[0], s0);
+                            if (s1) atomicAdd(&sa[1], s1);
+                            if (MODE == MODE_POOLED && s2) atomicAdd(&sa[2], s2);
+                            if (s3) atomicAdd(&sa[3], s3);
+                        }
+                    }
+                    if (wpg == 1) __syncthreads();   // kn[0] is read again next round
+                }
             }
             __syncthreads();
             if (*ovf) goto overflowed;   // the walk is redone with full tables
@@ -824,14 +936,61 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                 if (cls[r] != DEAD) cls[r] = map[cls[r]];
             K = kn[0];
             const uint32_t S0 = sa[0], S1 = sa[1], S2 = sa[2], members = sa[3];
+            const uint32_t F0 = sa[4], F1 = sa[5];   // two markers: S after the first
             if (tid == 0) {
-                uint32_t *other = sacc + 4 * (par ^ 1);
-                other[0] = other[1] = other[2] = other[3] = 0u;
+                uint32_t *other = sacc + 8 * (par ^ 1);
+                for (int x = 0; x < 8; ++x) other[x] = 0u;
                 knext[par ^ 1] = 0;
             }
-            step += 1;
+            step += two ? 2 : 1;
+            if (two) pflip ^= 1;   // the children's sizes are current after an even step
 
-            if (MODE == MODE_CORE) {
+            if (MODE == MODE_CORE && two) {
+                // the first marker's stop tests and terms, then the second's
+                // for the cores still walking
+                if (act0) {
+                    steps0 += 1;
+                    if (F0 <= thr0) {
+                        act0 = false;
+                    } else {
+                        if (wave == 0) {
+                            const double e = (double)F0 / P0;
+                            ihh0 += 0.5 * (ep0 + e) * readlane_f64(gl, i);
+                            ep0 = e;
+                        }
+                        steps0 += 1;
+                        if (S0 <= thr0) {
+                            act0 = false;
+                        } else if (wave == 0) {
+                            const double e = (double)S0 / P0;
+                            ihh0 += 0.5 * (ep0 + e) * readlane_f64(gl, i + 1);
+                            ep0 = e;
+                        }
+                    }
+                }
+                if (act1) {
+                    steps1 += 1;
+                    if (F1 <= thr1) {
+                        act1 = false;
+                    } else {
+                        if (wave == 0) {
+                            const double e = (double)F1 / P1;
+                            ihh1 += 0.5 * (ep1 + e) * readlane_f64(gl, i);
+                            ep1 = e;
+                        }
+                        steps1 += 1;
+                        if (S1 <= thr1) {
+                            act1 = false;
+                        } else if (wave == 0) {
+                            const double e = (double)S1 / P1;
+                            ihh1 += 0.5 * (ep1 + e) * readlane_f64(gl, i + 1);
+                            ep1 = e;
+                        }
+                    }
+                }
+                sa0 = S0;
+                sa1 = S1;
+            } else if (MODE == MODE_CORE) {
                 if (act0) {
                     steps0 += 1;
                     if (S0 <= thr0) {
@@ -879,6 +1038,7 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                     goto pairs;
                 }
             }
+            i += two ? 2 : 1;
         }
     }
     goto done;
