@@ -409,3 +409,25 @@ def test_sweep_regions_long_walks(ss, sweep_regions, cfg):
             one = _np(ss.ihs(ha, steps=True))
             for k in one:
                 np.testing.assert_array_equal(g[k], one[k], err_msg="single call " + k)
+
+
+def test_gaps_at_every_offset_in_two_marker_steps(ss):
+    """iHS walks over more than 1,024 haplotypes refine two markers per step;
+    gaps beyond max_gap after sites of both parities make walks abort on the
+    first and on the second marker of a step, and near the data's ends."""
+    d = hapgen.copying_model(1100, 700, 900_000, 25, 0.01, 77)
+    pos, gpos = d.pos_bp.copy(), d.gpos_cm.copy()
+    for at in (90, 181, 273, 366, 460, 555):
+        pos[at:] += 250_000
+        gpos[at:] += 0.25
+    ref = oracle.ihs(d.alleles, pos, gpos)
+    assert (ref["status"] == 3).sum() > 50
+    regions = [("ihs", _hm(ss, d.alleles, pos, gpos), None, ref)]
+    for cfg in (dict(small_kernel=0), dict(small_kernel=0, threads=128), dict(small_kernel=0, class_cap=64)):
+        say("ss_scan_batch gaps config %s" % cfg)
+        ss.set_batch_config(ss.BatchConfig(**cfg))
+        try:
+            _, got = _run_batch(ss, regions)
+        finally:
+            ss.set_batch_config(ss.BatchConfig())
+        _check_all(got, regions, "gaps %s" % cfg)
