@@ -718,12 +718,14 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                 status = abort_st;
                 goto done;
             }
-            // iHS walks refine two markers per step while both are walked:
-            // one count per member of its alleles at both, one class pass
-            // making the up to four children (S after the first marker from
-            // the children's pairs by first allele), so half the workgroup
-            // barriers and LDS round trips per marker
-            const bool two = MODE == MODE_CORE && i + 1 < nb && i + 1 < 64;
+            // Walks refine two markers per step while both are walked: one
+            // count per member of its alleles at both, one class pass making
+            // the up to four children (S after the first marker from the
+            // children's pairs by first allele), so half the workgroup
+            // barriers and LDS round trips per marker.  (XPEHH counts each
+            // population in its own word, so it needs the counter copies'
+            // space: with a single copy it takes one marker per step.)
+            const bool two = (MODE == MODE_CORE || ncp >= 2) && i + 1 < nb && i + 1 < 64;
             const int par = (step & 1) ^ pflip;
             uint32_t *szc = par ? szv1 : szv0;
             uint32_t *szn = par ? szv0 : szv1;
@@ -741,7 +743,14 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                         const int32_t b1 = (int32_t)((readlane64(rowv[r], i) >> lane) & 1ull);
                         const int32_t b2 = (int32_t)((readlane64(rowv[r], i + 1) >> lane) & 1ull);
                         const int32_t ab = 2 * b1 + b2;
-                        if (ab) atomicAdd(&cnt2[cls[r] * ncp + (lane & (ncp - 1))], 1ull << (21 * (ab - 1)));
+                        if (MODE == MODE_CORE) {
+                            if (ab) atomicAdd(&cnt2[cls[r] * ncp + (lane & (ncp - 1))], 1ull << (21 * (ab - 1)));
+                        } else {
+                            // half the copies, two words each: population A's, B's
+                            const int h = ncp >> 1;
+                            if (ab) atomicAdd(&cnt2[2 * (cls[r] * h + (lane & (h - 1))) + (int)(incu(r) >> 16)],
+                                              1ull << (21 * (ab - 1)));
+                        }
                         cls[r] = 4 * cls[r] + ab;
                     }
                 }
@@ -759,7 +768,7 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
             __syncthreads();
 
             // (2) split every class, keep children with >= 2 members
-            if (two) {
+            if (MODE == MODE_CORE && two) {
                 for (int c0 = 0; c0 < K; c0 += T) {
                     const int c = c0 + tid;
                     const bool in = c < K;
@@ -838,6 +847,100 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                             if (s3) atomicAdd(&sa[3], s3);
                             if (f0) atomicAdd(&sa[4], f0);
                             if (f1) atomicAdd(&sa[5], f1);
+                        }
+                    }
+                    if (wpg == 1) __syncthreads();   // kn[0] is read again next round
+                }
+            } else if (two) {
+                const int h = ncp >> 1;
+                for (int c0 = 0; c0 < K; c0 += T) {
+                    const int c = c0 + tid;
+                    const bool in = c < K;
+                    uint64_t fa = 0ull, fb = 0ull;
+                    uint32_t sz = 0u;
+                    if (in) {
+                        for (int q = 0; q < h; ++q) {
+                            fa += cnt2[2 * (c * h + q)];
+                            fb += cnt2[2 * (c * h + q) + 1];
+                            cnt2[2 * (c * h + q)] = 0ull;
+                            cnt2[2 * (c * h + q) + 1] = 0ull;
+                        }
+                        sz = szc[c];
+                    }
+                    const uint32_t nA = sz & 0xFFFFu, nB = sz >> 16;
+                    const uint32_t a01 = (uint32_t)(fa & 0x1FFFFFull), a10 = (uint32_t)((fa >> 21) & 0x1FFFFFull);
+                    const uint32_t a11 = (uint32_t)(fa >> 42), a00 = nA - a01 - a10 - a11;
+                    const uint32_t b01 = (uint32_t)(fb & 0x1FFFFFull), b10 = (uint32_t)((fb >> 21) & 0x1FFFFFull);
+                    const uint32_t b11 = (uint32_t)(fb >> 42), b00 = nB - b01 - b10 - b11;
+                    // S of A, of B and pooled after the first marker and after the second
+                    uint32_t fA = 0u, fB = 0u, fP = 0u, tA = 0u, tB = 0u, tP = 0u;
+                    if (in) {
+                        fA = choose2(a00 + a01) + choose2(a10 + a11);
+                        fB = choose2(b00 + b01) + choose2(b10 + b11);
+                        fP = choose2(a00 + a01 + b00 + b01) + choose2(a10 + a11 + b10 + b11);
+                        tA = choose2(a00) + choose2(a01) + choose2(a10) + choose2(a11);
+                        tB = choose2(b00) + choose2(b01) + choose2(b10) + choose2(b11);
+                        tP = choose2(a00 + b00) + choose2(a01 + b01) + choose2(a10 + b10) + choose2(a11 + b11);
+                    }
+                    const bool k00 = in && a00 + b00 >= 2u, k01 = in && a01 + b01 >= 2u;
+                    const bool k10 = in && a10 + b10 >= 2u, k11 = in && a11 + b11 >= 2u;
+                    uint32_t s3 = (k00 ? a00 + b00 : 0u) + (k01 ? a01 + b01 : 0u) +
+                                  (k10 ? a10 + b10 : 0u) + (k11 ? a11 + b11 : 0u);
+                    const uint64_t m00 = __ballot(k00), m01 = __ballot(k01);
+                    const uint64_t m10 = __ballot(k10), m11 = __ballot(k11);
+                    const int n00 = __popcll(m00), n01 = __popcll(m01);
+                    const int n10 = __popcll(m10), n11 = __popcll(m11);
+                    const int nk = n00 + n01 + n10 + n11;
+                    int basei = 0;
+                    if (wpg == 1) {
+                        basei = kn[0];
+                    } else {
+                        if (lane == 0 && nk > 0) basei = atomicAdd(kn, nk);
+                        basei = __shfl(basei, 0, 64);
+                    }
+                    const int i00 = basei + (int)lanes_below(m00);
+                    const int i01 = basei + n00 + (int)lanes_below(m01);
+                    const int i10 = basei + n00 + n01 + (int)lanes_below(m10);
+                    const int i11 = basei + n00 + n01 + n10 + (int)lanes_below(m11);
+                    const bool fits = basei + nk <= kmax;   // wave-uniform
+                    if (!fits && lane == 0) *ovf = 1;
+                    if (in) {
+                        map[4 * c + 0] = k00 ? i00 : DEAD;
+                        map[4 * c + 1] = k01 ? i01 : DEAD;
+                        map[4 * c + 2] = k10 ? i10 : DEAD;
+                        map[4 * c + 3] = k11 ? i11 : DEAD;
+                    }
+                    if (fits) {
+                        if (k00) szn[i00] = a00 | (b00 << 16);
+                        if (k01) szn[i01] = a01 | (b01 << 16);
+                        if (k10) szn[i10] = a10 | (b10 << 16);
+                        if (k11) szn[i11] = a11 | (b11 << 16);
+                    }
+                    tA = wave_sum(tA);
+                    tB = wave_sum(tB);
+                    tP = wave_sum(tP);
+                    fA = wave_sum(fA);
+                    fB = wave_sum(fB);
+                    fP = wave_sum(fP);
+                    if (can_pair) s3 = wave_sum(s3);
+                    if (lane == 0) {
+                        if (wpg == 1) {
+                            kn[0] = basei + nk;
+                            sa[0] += tA;
+                            sa[1] += tB;
+                            sa[2] += tP;
+                            sa[3] += s3;
+                            sa[4] += fA;
+                            sa[5] += fB;
+                            sa[6] += fP;
+                        } else {
+                            if (tA) atomicAdd(&sa[0], tA);
+                            if (tB) atomicAdd(&sa[1], tB);
+                            if (tP) atomicAdd(&sa[2], tP);
+                            if (s3) atomicAdd(&sa[3], s3);
+                            if (fA) atomicAdd(&sa[4], fA);
+                            if (fB) atomicAdd(&sa[5], fB);
+                            if (fP) atomicAdd(&sa[6], fP);
                         }
                     }
                     if (wpg == 1) __syncthreads();   // kn[0] is read again next round
@@ -936,7 +1039,7 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                 if (cls[r] != DEAD) cls[r] = map[cls[r]];
             K = kn[0];
             const uint32_t S0 = sa[0], S1 = sa[1], S2 = sa[2], members = sa[3];
-            const uint32_t F0 = sa[4], F1 = sa[5];   // two markers: S after the first
+            const uint32_t F0 = sa[4], F1 = sa[5], F2 = sa[6];   // two markers: S after the first
             if (tid == 0) {
                 uint32_t *other = sacc + 8 * (par ^ 1);
                 for (int x = 0; x < 8; ++x) other[x] = 0u;
@@ -1013,6 +1116,38 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                 }
                 sa0 = S0;
                 sa1 = S1;
+            } else if (two) {
+                // pooled: the first marker's stop test and terms, then the
+                // second's if the walk goes on
+                steps0 += 1;
+                if (F2 <= thr0) {
+                    act0 = false;
+                } else {
+                    if (wave == 0) {
+                        const double g = readlane_f64(gl, i);
+                        const double eA = (double)F0 / P0;
+                        const double eB = (double)F1 / P1;
+                        ihh0 += 0.5 * (ep0 + eA) * g;
+                        ihh1 += 0.5 * (ep1 + eB) * g;
+                        ep0 = eA;
+                        ep1 = eB;
+                    }
+                    steps0 += 1;
+                    if (S2 <= thr0) {
+                        act0 = false;
+                    } else if (wave == 0) {
+                        const double g = readlane_f64(gl, i + 1);
+                        const double eA = (double)S0 / P0;
+                        const double eB = (double)S1 / P1;
+                        ihh0 += 0.5 * (ep0 + eA) * g;
+                        ihh1 += 0.5 * (ep1 + eB) * g;
+                        ep0 = eA;
+                        ep1 = eB;
+                    }
+                }
+                sa0 = S0;
+                sa1 = S1;
+                sa2 = S2;
             } else {
                 steps0 += 1;
                 if (S2 <= thr0) {
