@@ -169,12 +169,15 @@ __host__ __device__ inline BLay batch_layout(int lmax, int kcls, int pcap, int k
     l.copies = copies;
     const uint32_t K = (uint32_t)l.kmax;
     uint32_t o = 0;
-    // counters: 32-bit ones per class, or (iHS steps over two markers)
-    // 64-bit fields of the allele pairs 01, 10 and 11
-    l.cnt1 = o;  o += 8u * K * (uint32_t)copies;
+    // counters: 32-bit ones per class and copy; steps over two markers use
+    // the same space as 64-bit words of 21-bit fields for the allele pairs
+    // 01, 10 and 11 (one word a class and copy for iHS, two for XPEHH's two
+    // populations), over half or a quarter of the copies
+    const uint32_t cw = 4u * K * (uint32_t)copies > 16u * K ? 4u * K * (uint32_t)copies : 16u * K;
+    l.cnt1 = o;  o += cw;
     l.szv0 = o;  o += 4u * K;
     l.szv1 = o;  o += 4u * K;
-    l.map = o;   o += 16u * K;   // children of each class: 2 per marker, 4 per two
+    l.map = o;   o += 8u * K;    // children of each class (16-bit ids: 2 per marker, 4 per two)
     l.sacc = o;  o += 64u;
     l.knext = o; o += 8u;
     l.init = o;  o += 8u;
@@ -239,7 +242,7 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
     uint32_t *init = (uint32_t *)(base + Ly.init);
     int32_t *ovf = (int32_t *)(base + Ly.ovf);   // the class table overflowed
 
-    for (int i = tid; i < 2 * kmax * ncp; i += T) cnt1[i] = 0u;
+    for (int i = tid; i < (ncp > 4 ? kmax * ncp : 4 * kmax); i += T) cnt1[i] = 0u;
     if (tid < 16) sacc[tid] = 0u;
     if (tid < 2) {
         knext[tid] = 0;
@@ -722,16 +725,17 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
             // count per member of its alleles at both, one class pass making
             // the up to four children (S after the first marker from the
             // children's pairs by first allele), so half the workgroup
-            // barriers and LDS round trips per marker.  (XPEHH counts each
-            // population in its own word, so it needs the counter copies'
-            // space: with a single copy it takes one marker per step.)
-            const bool two = (MODE == MODE_CORE || ncp >= 2) && i + 1 < nb && i + 1 < 64;
+            // barriers and LDS round trips per marker.
+            const bool two = i + 1 < nb && i + 1 < 64;
             const int par = (step & 1) ^ pflip;
             uint32_t *szc = par ? szv1 : szv0;
             uint32_t *szn = par ? szv0 : szv1;
             uint32_t *sa = sacc + 8 * par;
             int32_t *kn = knext + par;
             uint64_t *cnt2 = (uint64_t *)cnt1;
+            int16_t *cmap = (int16_t *)map;   // children of each class
+            const int h2 = ncp > 1 ? ncp >> 1 : 1;   // 64-bit counter copies (iHS)
+            const int h4 = ncp > 3 ? ncp >> 2 : 1;   // pairs of them (XPEHH)
 
             // (1) alleles per class; a member's class id becomes its child's
             // index in the class pass's map: 2 * class + allele, or
@@ -744,11 +748,10 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                         const int32_t b2 = (int32_t)((readlane64(rowv[r], i + 1) >> lane) & 1ull);
                         const int32_t ab = 2 * b1 + b2;
                         if (MODE == MODE_CORE) {
-                            if (ab) atomicAdd(&cnt2[cls[r] * ncp + (lane & (ncp - 1))], 1ull << (21 * (ab - 1)));
+                            if (ab) atomicAdd(&cnt2[cls[r] * h2 + (lane & (h2 - 1))], 1ull << (21 * (ab - 1)));
                         } else {
-                            // half the copies, two words each: population A's, B's
-                            const int h = ncp >> 1;
-                            if (ab) atomicAdd(&cnt2[2 * (cls[r] * h + (lane & (h - 1))) + (int)(incu(r) >> 16)],
+                            // two words a copy: population A's, B's
+                            if (ab) atomicAdd(&cnt2[2 * (cls[r] * h4 + (lane & (h4 - 1))) + (int)(incu(r) >> 16)],
                                               1ull << (21 * (ab - 1)));
                         }
                         cls[r] = 4 * cls[r] + ab;
@@ -775,9 +778,9 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                     uint64_t f = 0ull;
                     uint32_t sz = 0u;
                     if (in) {
-                        for (int q = 0; q < ncp; ++q) {
-                            f += cnt2[c * ncp + q];
-                            cnt2[c * ncp + q] = 0ull;
+                        for (int q = 0; q < h2; ++q) {
+                            f += cnt2[c * h2 + q];
+                            cnt2[c * h2 + q] = 0ull;
                         }
                         sz = szc[c];
                     }
@@ -814,10 +817,10 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                     const bool fits = basei + nk <= kmax;   // wave-uniform
                     if (!fits && lane == 0) *ovf = 1;
                     if (in) {
-                        map[4 * c + 0] = k00 ? i00 : DEAD;
-                        map[4 * c + 1] = k01 ? i01 : DEAD;
-                        map[4 * c + 2] = k10 ? i10 : DEAD;
-                        map[4 * c + 3] = k11 ? i11 : DEAD;
+                        cmap[4 * c + 0] = (int16_t)(k00 ? i00 : DEAD);
+                        cmap[4 * c + 1] = (int16_t)(k01 ? i01 : DEAD);
+                        cmap[4 * c + 2] = (int16_t)(k10 ? i10 : DEAD);
+                        cmap[4 * c + 3] = (int16_t)(k11 ? i11 : DEAD);
                     }
                     if (fits) {
                         const uint32_t cb = core << 31;
@@ -852,7 +855,7 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                     if (wpg == 1) __syncthreads();   // kn[0] is read again next round
                 }
             } else if (two) {
-                const int h = ncp >> 1;
+                const int h = h4;
                 for (int c0 = 0; c0 < K; c0 += T) {
                     const int c = c0 + tid;
                     const bool in = c < K;
@@ -905,10 +908,10 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                     const bool fits = basei + nk <= kmax;   // wave-uniform
                     if (!fits && lane == 0) *ovf = 1;
                     if (in) {
-                        map[4 * c + 0] = k00 ? i00 : DEAD;
-                        map[4 * c + 1] = k01 ? i01 : DEAD;
-                        map[4 * c + 2] = k10 ? i10 : DEAD;
-                        map[4 * c + 3] = k11 ? i11 : DEAD;
+                        cmap[4 * c + 0] = (int16_t)(k00 ? i00 : DEAD);
+                        cmap[4 * c + 1] = (int16_t)(k01 ? i01 : DEAD);
+                        cmap[4 * c + 2] = (int16_t)(k10 ? i10 : DEAD);
+                        cmap[4 * c + 3] = (int16_t)(k11 ? i11 : DEAD);
                     }
                     if (fits) {
                         if (k00) szn[i00] = a00 | (b00 << 16);
@@ -1004,8 +1007,8 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
                     const bool fits = basei + nz + no <= kmax;   // wave-uniform
                     if (!fits && lane == 0) *ovf = 1;
                     if (in) {
-                        map[2 * c] = keepz ? idz : DEAD;
-                        map[2 * c + 1] = keepo ? ido : DEAD;
+                        cmap[2 * c] = (int16_t)(keepz ? idz : DEAD);
+                        cmap[2 * c + 1] = (int16_t)(keepo ? ido : DEAD);
                     }
                     if (fits && keepz) szn[idz] = wz;
                     if (fits && keepo) szn[ido] = wo;
@@ -1036,7 +1039,7 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
             // (3) new class ids
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (cls[r] != DEAD) cls[r] = map[cls[r]];
+                if (cls[r] != DEAD) cls[r] = cmap[cls[r]];
             K = kn[0];
             const uint32_t S0 = sa[0], S1 = sa[1], S2 = sa[2], members = sa[3];
             const uint32_t F0 = sa[4], F1 = sa[5], F2 = sa[6];   // two markers: S after the first
