@@ -206,8 +206,10 @@ int check_batch_config(const ss_batch_config &c) {
 
 // Launch configuration of the persistent walk for the largest list lmax and
 // the widest row wmax of its regions; false if it cannot run.
-bool make_wide_cfg(const ss_batch_config &bc, int lmax, int wmax, ss::WideCfg &c) {
+// dev: the launch holds iHS walks (room for their reference passes).
+bool make_wide_cfg(const ss_batch_config &bc, int lmax, int wmax, ss::WideCfg &c, bool dev = true) {
     c.kernel = bc.kernel;
+    c.dev = dev ? 1 : 0;
     c.threads = bc.threads;
     c.pair_cap = bc.pair_cap;
     c.chunk = bc.chunk;
@@ -228,10 +230,11 @@ bool make_wide_cfg(const ss_batch_config &bc, int lmax, int wmax, ss::WideCfg &c
         // workgroups keep one copy and their occupancy
         c.copies = bc.counter_copies ? bc.counter_copies : (c.threads >= 256 ? 8 : 1);
         c.lds = ss::ids_lds_bytes(c.threads, lmax, wmax, c.class_cap, c.pair_cap, c.key_cap,
-                                  c.copies);
+                                  c.copies, dev);
         if (c.lds == 0 || c.lds > (size_t)max_lds_per_block()) {
             c.copies = 1;
-            c.lds = ss::ids_lds_bytes(c.threads, lmax, wmax, c.class_cap, c.pair_cap, c.key_cap, 1);
+            c.lds = ss::ids_lds_bytes(c.threads, lmax, wmax, c.class_cap, c.pair_cap, c.key_cap, 1,
+                                      dev);
         }
     } else {
         // a pair list of P pairs holds at most ~P / 4 haplotypes in classes of
@@ -321,7 +324,8 @@ Route route_for(int32_t nA, int32_t nB, int mode, bool in_batch) {
     if (g_walk_kind == ss::WALK_REG_MASKS) return mask_ok ? RT_MASK : RT_IDS;
     if (g_walk_kind == ss::WALK_AUTO && mask_ok && (!in_batch || g_bcfg.small_kernel)) return RT_MASK;
     ss::WideCfg c;
-    if (make_wide_cfg(g_bcfg, list_len(nA, nB, mode), row_words(nA, nB, mode), c)) return RT_WIDE;
+    if (make_wide_cfg(g_bcfg, list_len(nA, nB, mode), row_words(nA, nB, mode), c, mode == ss::MODE_CORE))
+        return RT_WIDE;
     return RT_IDS;
 }
 
@@ -534,6 +538,7 @@ int launch_ids_group(const ss::Region *regs, int nreg, int64_t total, int64_t st
     a.copies = c.copies;
     a.pcap = c.pair_cap;
     a.kcap = c.key_cap;
+    a.dev = c.dev;
     const bool capped = ss::ids_table_capped(c.lmax, c.class_cap);
     a.redo = capped ? redo : nullptr;
     a.redo_count = capped ? (int32_t *)(ctr + 2 * ss::kQueueWords) : nullptr;
@@ -542,11 +547,11 @@ int launch_ids_group(const ss::Region *regs, int nreg, int64_t total, int64_t st
     ss::WideCfg full = c;
     full.class_cap = 0;
     full.lds = ss::ids_lds_bytes(full.threads, full.lmax, full.wmax, 0, full.pair_cap, full.key_cap,
-                                 full.copies);
+                                 full.copies, full.dev != 0);
     if (full.lds == 0 || full.lds > (size_t)max_lds_per_block()) {
         full.copies = 1;
         full.lds = ss::ids_lds_bytes(full.threads, full.lmax, full.wmax, 0, full.pair_cap,
-                                     full.key_cap, 1);
+                                     full.key_cap, 1, full.dev != 0);
     }
     if (full.lds == 0 || full.lds > (size_t)max_lds_per_block())
         return fail(SS_EDEV, "full class table does not fit this device");
@@ -573,7 +578,8 @@ int walk_scan(Scan &sc, hipStream_t s) {
         const int64_t items = ss::region_items(sc.mode, sc.args.M, g_bcfg.kernel);
         ss::WideCfg c;
         const int lmax = list_len(r.nA, r.nB, sc.mode), wmax = row_words(r.nA, r.nB, sc.mode);
-        if (!make_wide_cfg(g_bcfg, lmax, wmax, c))
+        const bool ihs = sc.mode == ss::MODE_CORE;
+        if (!make_wide_cfg(g_bcfg, lmax, wmax, c, ihs))
             return fail(SS_EDEV, "persistent walk does not fit this device");
         if (c.kernel == 0) {   // as the region's launch group in a batch would run
             const bool pairs = tail_possible(sc.mode, r.nA, r.nB, sc.maf, r.cutoff, c.pair_cap);
@@ -585,7 +591,7 @@ int walk_scan(Scan &sc, hipStream_t s) {
                 SS_HIP(ss::launch_walk(sc.args, sc.mode, false, sc.args.M, s));
                 return t.end();
             }
-            if (!make_wide_cfg(launch_config(g_bcfg, c.threads, pairs), lmax, wmax, c))
+            if (!make_wide_cfg(launch_config(g_bcfg, c.threads, pairs), lmax, wmax, c, ihs))
                 return fail(SS_EDEV, "persistent walk does not fit this device");
         }
         SS_HIP(ss::launch_fill_regions(&r, 1, sc.w.region, s));
@@ -613,6 +619,7 @@ struct Group {
     int64_t total_items = 0;
     int lmax = 0, wmax = 0, threads = 0;
     bool pairs = true;          // some walk can reach the pairwise tail
+    bool ihs = false;           // some region is an iHS scan (reference passes)
 };
 
 constexpr int kMaxGroups = 32;
@@ -741,6 +748,7 @@ void number_items(Batch &B, const ss_batch_config &bc) {
         g.total_items += n_items;
         g.lmax = std::max(g.lmax, k.len);
         g.wmax = std::max(g.wmax, row_words(sc.args.nA, sc.args.nB, sc.mode));
+        g.ihs = g.ihs || sc.mode == ss::MODE_CORE;
         B.total_items += n_items;
         B.regions.push_back(r);
         B.region_scan.push_back(B.wide[k.idx]);
@@ -816,7 +824,7 @@ int launch_batch_wide(Batch &B, const ss_batch_config &bc, int64_t sample_stride
             continue;
         }
         ss::WideCfg c;
-        if (!make_wide_cfg(launch_config(bc, g.threads, g.pairs), g.lmax, g.wmax, c))
+        if (!make_wide_cfg(launch_config(bc, g.threads, g.pairs), g.lmax, g.wmax, c, g.ihs))
             return fail(SS_EDEV, "persistent walk configuration does not fit this device");
         int64_t total = g.total_items;
         if (stride > 1) {   // blocks of 256 items, one in every `stride`
@@ -1309,7 +1317,7 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
             for (const Group &g : B.groups) {
                 ss::WideCfg wc;
                 if ((int)B.groups.size() > kMaxGroups ||
-                    !make_wide_cfg(launch_config(c, g.threads, g.pairs), g.lmax, g.wmax, wc)) {
+                    !make_wide_cfg(launch_config(c, g.threads, g.pairs), g.lmax, g.wmax, wc, g.ihs)) {
                     ms = 1e30;
                     return SS_OK;
                 }
@@ -1421,7 +1429,7 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
                     ss::WideCfg wc;
                     if (t.plain ? !plain_fits(B, g)
                                 : !make_wide_cfg(launch_config(cur, g.threads, g.pairs), g.lmax,
-                                                 g.wmax, wc)) {
+                                                 g.wmax, wc, g.ihs)) {
                         ms = 1e30;
                         return SS_OK;
                     }

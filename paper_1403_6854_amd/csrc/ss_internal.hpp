@@ -140,6 +140,7 @@ struct WideCfg {
     int copies;      // kernel 0: copies of each class counter (1 or 8)
     int wmax;        // largest row width in words (iHS: W, XPEHH: WA + WB)
     size_t lds;      // dynamic LDS bytes
+    int dev;         // kernel 0: room for the iHS walks' reference passes
 };
 
 // LDS bytes of the wide walk for a configuration (0 if it cannot run).
@@ -155,8 +156,10 @@ int ids_slots(int threads, int wmax);
 // with at most `slots` words per wave (16 per wave when that would need more
 // than 1024 threads); 0 if the row does not fit.
 int ids_threads_for(int wmax, int slots);
+// dev: the launch holds iHS walks, which take reference passes (their
+// arrays share the pairwise tail's space and take more when it is smaller).
 size_t ids_lds_bytes(int threads, int lmax, int wmax, int class_cap, int pair_cap, int key_cap,
-                     int copies);
+                     int copies, bool dev);
 // True when a class capacity leaves some walks of lmax haplotypes to a
 // second launch with full tables.
 bool ids_table_capped(int lmax, int class_cap);
@@ -227,6 +230,7 @@ struct IdsArgs {
     int kcls;                    // class-table capacity, 0 = full
     int copies;                  // copies of each class counter (1 or 8)
     int pcap, kcap;              // pair and member capacity of the pairwise tail
+    int dev;                     // room for the iHS walks' reference passes
     const int64_t *list;         // null, or the items to walk ...
     const int32_t *list_count;   // ... and their number (on the device)
     int64_t *redo;               // walks that outgrow a capped table go here ...

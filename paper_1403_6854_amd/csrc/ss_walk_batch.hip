@@ -162,7 +162,7 @@ __host__ __device__ inline uint32_t al16(uint32_t x) { return (x + 15u) & ~15u; 
 // kcls > 0 caps the class table (walks that outgrow it are listed for a
 // launch with full tables); kcls = 0: room for every class a walk can have.
 __host__ __device__ inline BLay batch_layout(int lmax, int kcls, int pcap, int kcap,
-                                             int copies) {
+                                             int copies, bool dev) {
     BLay l;
     l.kmax = lmax / 2 + 2;
     if (kcls > 0 && kcls < l.kmax) l.kmax = kcls;
@@ -197,7 +197,7 @@ __host__ __device__ inline BLay batch_layout(int lmax, int kcls, int pcap, int k
     uint32_t t = o;
     l.mem = t;    t = al16(t + 2u * (uint32_t)kcap);
     l.pairs0 = t; t = al16(t + 4u * (uint32_t)pcap);
-    uint32_t r = o;
+    uint32_t r = o;   // (no arrays without iHS walks: the offsets are not used)
     l.dref = r;   r = al16(r + 4u * kDevClasses);
     l.dkey = r;   r = al16(r + 8u * kDevClasses);
     l.dcnt = r;   r = al16(r + 4u * kDevClasses);
@@ -208,13 +208,13 @@ __host__ __device__ inline BLay batch_layout(int lmax, int kcls, int pcap, int k
     l.egid = r;   r = al16(r + 4u * kDevCap);
     l.dhist = r;  r = al16(r + 4u * 3u * 64u);
     l.dctl = r;   r = al16(r + 16u);
-    l.total = t > r ? t : r;
+    l.total = dev && r > t ? r : t;
     return l;
 }
 
 template <int MODE, int R>
 __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t j, int d, char *base,
-                         const BLay &Ly, int pcap, int kcap, int64_t item, int64_t *redo,
+                         const BLay &Ly, int pcap, int kcap, bool dev, int64_t item, int64_t *redo,
                          int32_t *redo_count) {
     // fields are read through the pointer where they are used (scalar loads),
     // so that a copy of the descriptor does not hold registers for the walk
@@ -357,7 +357,7 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
     // (iHS walks: the pooled walks of XPEHH end within a few markers of their
     // first splits, and the pass's code would cost their per-marker loop
     // registers)
-    const bool can_dev = MODE == MODE_CORE && G.hbitsA != nullptr;
+    const bool can_dev = MODE == MODE_CORE && dev && G.hbitsA != nullptr;
 
     // End of a 64-marker pass: hist[t][L] counts the class-mate pairs of type
     // t (iHS: core 0, core 1; XPEHH: pooled, A-A, B-B) whose alleles first
@@ -1349,7 +1349,7 @@ __global__ void __launch_bounds__(1024) ids_batch_kernel(IdsArgs a) {
     extern __shared__ uint64_t lds_ids[];
     __shared__ int64_t rng[2];   // the chunk being walked
     char *base = (char *)lds_ids;
-    const BLay Ly = batch_layout(a.lmax, a.kcls, a.pcap, a.kcap, a.copies);
+    const BLay Ly = batch_layout(a.lmax, a.kcls, a.pcap, a.kcap, a.copies, a.dev != 0);
     const int64_t total = a.list ? (int64_t)*a.list_count : a.total;
     // the region of the last item (items of one region are consecutive)
     int g_idx = 0;
@@ -1392,9 +1392,10 @@ __global__ void __launch_bounds__(1024) ids_batch_kernel(IdsArgs a) {
             if (j >= G->M) continue;
             if (G->walk_flag && !G->walk_flag[j]) continue;
             if (G->mode == MODE_CORE)
-                ids_walk<MODE_CORE, R>(G, j, d, base, Ly, a.pcap, a.kcap, it, a.redo, a.redo_count);
+                ids_walk<MODE_CORE, R>(G, j, d, base, Ly, a.pcap, a.kcap, a.dev != 0, it, a.redo,
+                                       a.redo_count);
             else
-                ids_walk<MODE_POOLED, R>(G, j, d, base, Ly, a.pcap, a.kcap, it, a.redo,
+                ids_walk<MODE_POOLED, R>(G, j, d, base, Ly, a.pcap, a.kcap, false, it, a.redo,
                                          a.redo_count);
             __syncthreads();
         }
@@ -1442,12 +1443,12 @@ int ids_threads_for(int wmax, int slots) {
 }
 
 size_t ids_lds_bytes(int threads, int lmax, int wmax, int class_cap, int pair_cap, int key_cap,
-                     int copies) {
+                     int copies, bool dev) {
     if (threads < 64 || threads > 1024 || threads % 64) return 0;
     if (lmax < 2 || lmax > 32767 || ids_slots(threads, wmax) == 0) return 0;
     if (class_cap < 0 || pair_cap < 0 || key_cap < 0 || key_cap > 32767) return 0;
     if (copies != 1 && copies != 8) return 0;
-    return batch_layout(lmax, class_cap, pair_cap, key_cap, copies).total;
+    return batch_layout(lmax, class_cap, pair_cap, key_cap, copies, dev).total;
 }
 
 bool ids_table_capped(int lmax, int class_cap) {
