@@ -402,7 +402,7 @@ def main():
         print(json.dumps(ss.micro(ss.pack(torch.from_numpy(d.alleles).cuda()))))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
+        print("bench.py measures one GPU only: the library runs on a single MI355X "
               "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
