@@ -317,7 +317,7 @@ typedef struct ss_batch_config {
                                [default]): fewer words per wave spread a walk over more
                                waves; rows wider than 16 waves of them take 16 per wave */
     int32_t class_cap;      /* kernel 0: classes the LDS table holds (0 = as many as a
-                               walk can have, n/2 + 2; else 64..16386, default 1024):
+                               walk can have, n/2 + 2; else 64..16386, default 256):
                                walks that outgrow it are redone by a second launch with
                                full tables                                             */
     int32_t counter_copies; /* kernel 0: copies of each class counter, over which the

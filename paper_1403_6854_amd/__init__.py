@@ -564,7 +564,7 @@ class BatchConfig:
     kernel: int = 0
     small_pair_cap: int = 1024
     slots: int = 16
-    class_cap: int = 1024
+    class_cap: int = 256
     counter_copies: int = 0
 
 

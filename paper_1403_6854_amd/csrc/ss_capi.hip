@@ -179,7 +179,7 @@ hipEvent_t take_event() {
 int g_walk_kind = ss::WALK_AUTO;
 int g_mask_lpc = 0;   // lanes per class of the bitmask walk; 0 = default
 int g_mask_skip = 32;       // bitmask walk: most class slots for which markers that cut none are skipped
-ss_batch_config g_bcfg = {64, 4096, 1, 0, 0, 1, 0, 1024, 16, 1024, 0};
+ss_batch_config g_bcfg = {64, 4096, 1, 0, 0, 1, 0, 1024, 16, 256, 0};
 bool g_graph_on = false;
 bool g_capturing = false;   // timing events are not recorded into graphs
 
@@ -1377,7 +1377,7 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
                 if (ms < cur_ms) { cur = c; cur_ms = ms; }
             }
             if (cur.kernel == 0) {
-                for (int cc : {0, 512, 1024, 2048}) {
+                for (int cc : {0, 256, 512, 1024, 2048}) {
                     ss_batch_config c = cur;
                     c.class_cap = cc;
                     double ms;
@@ -1456,7 +1456,7 @@ int ss_autotune_batch(const ss_scan_request *reqs, int32_t n_reqs, const ss_para
                     return SS_OK;
                 };
                 for (int cp : {1, 8}) { GroupTune t = bt; t.counter_copies = cp; SS_TRY(try_t(t)); }
-                for (int cc : {0, 512, 1024, 2048}) { GroupTune t = bt; t.class_cap = cc; SS_TRY(try_t(t)); }
+                for (int cc : {0, 256, 512, 1024, 2048}) { GroupTune t = bt; t.class_cap = cc; SS_TRY(try_t(t)); }
                 for (int ch : {1, 2, 4, 8}) { GroupTune t = bt; t.chunk = ch; SS_TRY(try_t(t)); }
                 for (int bpc : {0, 2, 3, 4}) { GroupTune t = bt; t.blocks_per_cu = bpc; SS_TRY(try_t(t)); }
                 {   // or the plain per-locus kernel for this group's regions

@@ -175,7 +175,7 @@ def test_autotune_then_parity(ss, regions):
         for t in tuned:
             assert t["threads"] % 64 == 0 and 64 <= t["threads"] <= 1024 and t["pairs"] in (0, 1)
             assert t["counter_copies"] in (0, 1, 8) and t["chunk"] >= 1
-            assert t["class_cap"] in (0, 512, 1024, 2048) and 0 <= t["blocks_per_cu"] <= 4
+            assert t["class_cap"] in (0, 256, 512, 1024, 2048) and 0 <= t["blocks_per_cu"] <= 4
             assert t["plain"] in (0, 1)
         ss.scan_batch(reqs, ws=ws)
         got = [_np(r.out) for r in reqs]
