@@ -454,7 +454,7 @@ __device__ __forceinline__ void ids_walk(const Region *__restrict__ Gp, int64_t 
             uint32_t *dcnt = (uint32_t *)(base + Ly.dcnt);   // [class] leavers, A | B << 16
             uint32_t *doff = (uint32_t *)(base + Ly.doff);   // [class] first entry of its leavers
             uint64_t *ekey = (uint64_t *)(base + Ly.ekey);   // [leaver] key
-            uint32_t *einfo = (uint32_t *)(base + Ly.einfo); // [leaver] class | marker << 16 | B << 23
+            uint32_t *einfo = (uint32_t *)(base + Ly.einfo); // [leaver] class | marker << 8 | B << 14 | member << 15
             int32_t *elead = (int32_t *)(base + Ly.elead);   // [leaver] first leaver with its key
             int32_t *egid = (int32_t *)(base + Ly.egid);     // [leaver] group size, then new class
             uint32_t *dhist = (uint32_t *)(base + Ly.dhist); // [3][64] pairs splitting per marker
