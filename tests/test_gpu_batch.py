@@ -431,3 +431,28 @@ def test_gaps_at_every_offset_in_two_marker_steps(ss):
         finally:
             ss.set_batch_config(ss.BatchConfig())
         _check_all(got, regions, "gaps %s" % cfg)
+
+
+def test_xpehh_gaps_at_every_offset_in_two_marker_steps(ss):
+    """Pooled XPEHH walks over more than 1,024 haplotypes take two markers per
+    step as well (population counts in two words); gaps after sites of both
+    parities end walks on either marker of a step."""
+    a = hapgen.copying_model(700, 600, 800_000, 25, 0.01, 78)
+    rng = np.random.default_rng(79)
+    b = hapgen.copy_haplotypes(rng, hapgen.derive_founders(rng, a.founders, 0.8), 600, 0.01, 0.001)
+    pos, gpos = a.pos_bp.copy(), a.gpos_cm.copy()
+    for at in (75, 152, 230, 309, 389, 470):
+        pos[at:] += 250_000
+        gpos[at:] += 0.25
+    ref = oracle.xpehh(a.alleles, b, pos, gpos)
+    assert (ref["status"] == 3).sum() > 50
+    regions = [("xpehh", _hm(ss, a.alleles, pos, gpos), _hm(ss, b, pos, gpos), ref)]
+    for cfg in (dict(small_kernel=0), dict(small_kernel=0, counter_copies=1),
+                dict(small_kernel=0, counter_copies=8, class_cap=64)):
+        say("ss_scan_batch xpehh gaps config %s" % cfg)
+        ss.set_batch_config(ss.BatchConfig(**cfg))
+        try:
+            _, got = _run_batch(ss, regions)
+        finally:
+            ss.set_batch_config(ss.BatchConfig())
+        _check_all(got, regions, "xpehh gaps %s" % cfg)
